@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the single-GPU MD hot path on the LJ bulk workload.
+
+Workload: LJ liquid, N = 2,000,000 (fcc 80^3 with 48,000 seeded vacancies,
+density 0.8442, T = 1.2), r_cut = 2.5, r_buff = 0.4, dt = 0.005, NVE velocity
+Verlet, Morton reordering every 500 steps.  One step = the whole hot path
+(fused force + integration + displacement check, and the neighbour-list
+rebuilds and sorts that fall inside the window).  The reported value is the
+mixed-precision rate (FP32 pair arithmetic, FP64 positions / integration /
+reductions); the all-FP64 rate is measured on the same workload beside it.
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-timesteps/sec, LJ 2M particles, mixed vs FP64 at stated force tolerance"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_lj2M_traffic.json")
+KERNEL_SOURCES = ["paper_1412_3387_amd/csrc/forces.hip", "paper_1412_3387_amd/csrc/device.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_precision(B, inputs, torch, s, prec, steps, warmup, tune):
+    p = B.ModelParams(precision=prec, pair=B.PAIR_LJ, r_cut=2.5, r_buff=0.4, dt=0.005,
+                      sort_period=500)
+    ctx = B.Context([p], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+    ctx.build_nlist(True)
+    tuning = ctx.autotune(tune)
+    if warmup > 0:
+        ctx.step(0, warmup)
+    ctx.check()
+    torch.cuda.synchronize()
+    stream = ctx.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    b0 = ctx.build_count()
+    ctx.profile(1)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ctx.step(warmup, steps, log_every=steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ctx.profile(2)
+    ctx.profile(0)
+    ctx.check()
+    gpu_ms = e0.elapsed_time(e1)
+    log = ctx.thermo_log()
+    E0 = log[0, 0, 1] + log[0, 0, 2]
+    E1 = log[-1, 0, 1] + log[-1, 0, 2]
+    lay = ctx.layout()
+    nn = ctx._ws_view(lay.nn, s.n)
+    nbar = float(nn.double().mean().item())
+    builds = ctx.build_count() - b0
+    out = dict(ms=max(gpu_ms, 1e-9), wall=wall, prof=prof, nbar=nbar, builds=builds,
+               drift=abs(E1 - E0) / abs(E0), T_end=float(log[-1, 0, 4]),
+               tuning=dict(tpp_nlist=tuning.tpp_nlist, block_nlist=tuning.block_nlist,
+                           tpp_force=tuning.tpp_force, block_force=tuning.block_force))
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(s, seconds):
+    """The FP64 oracle on the host cores: brute-force forces of a bounded
+    sample of particles against the whole box (its per-particle-step cost)."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    rng = np.random.default_rng(0)
+    lj = [1.0, 1.0, 2.5]
+    m = 64
+    t = 0.0
+    while True:
+        which = np.sort(rng.choice(s.n, m, replace=False))
+        t0 = time.perf_counter()
+        oracle.pair_forces("lj", s.pos, s.L, lj, which=which)
+        t = time.perf_counter() - t0
+        if t > 0.25 * seconds or m >= s.n:
+            break
+        m = min(s.n, int(m * max(2.0, min(16.0, 0.5 * seconds / max(t, 1e-3)))))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": m / t, "unit": "particle-timesteps/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 brute-force forces of {m} random particles against all {s.n} "
+                       f"(O(N) each, minimum image), {t:.1f} s; the integration is negligible "
+                       f"beside it")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (the hot path of one subdomain); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1412_3387_amd import binding as B
+    from paper_1412_3387_amd import inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    B.lib()
+    s = inputs.lj_bulk(args.n)
+    print(f"[bench] N={s.n} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    mixed = run_precision(B, inputs, torch, s, B.MIXED, args.steps, args.warmup, not args.no_tune)
+    print(f"[bench] mixed done {mixed['ms']:.1f} ms", file=sys.stderr, flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_precision(B, inputs, torch, s, B.FP64, args.steps, args.warmup, not args.no_tune)
+        print(f"[bench] fp64 done {fp64['ms']:.1f} ms", file=sys.stderr, flush=True)
+
+    K = args.steps
+    value = s.n * K / (mixed["ms"] / 1e3)
+    pr = mixed["prof"]
+    force_avg_ms = pr.force_ms / max(pr.force_launches, 1)
+    # algorithmic bytes of one fused force launch per particle: neighbour row
+    # (4 n) + its length (4) + own position (32) + velocity in and out (64) +
+    # new position (32) + position at the last build (32)
+    bytes_per_particle = 4.0 * mixed["nbar"] + 4 + 32 + 64 + 32 + 32
+    achieved = s.n * bytes_per_particle / (force_avg_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("n") == s.n:
+            traffic = tr.get("bytes_per_launch")
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-timesteps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair math + f64 state (mixed)",
+        "data": "synthetic",
+        "config": {"workload": "lj_bulk_2M", "N": s.n, "density": 0.8442, "T0": 1.2, "r_cut": 2.5,
+                   "r_buff": 0.4, "dt": 0.005, "sort_period": 500, "precision": "mixed",
+                   "parallelism": "single GPU"},
+        "steps_per_s": K / (mixed["ms"] / 1e3),
+        "energy_drift_rel": mixed["drift"],
+        "T_end": mixed["T_end"],
+        "rebuilds": mixed["builds"],
+        "tuning": mixed["tuning"],
+        "phase_ms_per_step": {"force": pr.force_ms / K, "rebuild": pr.rebuild_ms / K},
+        "roofline": {"bound": "hbm", "kernel": "k_force (fused force + velocity Verlet)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_us": force_avg_ms * 1e3,
+                     "alg_bytes_per_particle": bytes_per_particle, "mean_row": mixed["nbar"]},
+    }
+    if fp64 is not None:
+        line["fp64"] = {"value": s.n * K / (fp64["ms"] / 1e3), "ms_per_step": fp64["ms"] / K,
+                        "energy_drift_rel": fp64["drift"], "rebuilds": fp64["builds"],
+                        "tuning": fp64["tuning"],
+                        "force_avg_us": fp64["prof"].force_ms / max(fp64["prof"].force_launches, 1) * 1e3}
+        line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

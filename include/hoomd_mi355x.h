@@ -1,0 +1,271 @@
+/*
+ * hoomd_mi355x.h -- C ABI of the single-GPU molecular-dynamics hot path for
+ * AMD MI355X (gfx950): cell list, Verlet neighbour list, LJ / WCA / DPD pair
+ * forces, FENE+WCA bonds, velocity-Verlet NVE, and ghost-layer selection with
+ * pack / unpack for one subdomain.
+ *
+ * The operations follow the statement of the problem in Glaser et al.,
+ * "Strong scaling of general-purpose molecular dynamics simulations on GPUs"
+ * (HOOMD-blue 1.0 with domain decomposition):
+ *   - short-range pair forces with a cut-off r_cut and a Verlet buffer
+ *     r_buff whose sum is the neighbour radius and the ghost width
+ *     (Sec. 4.2, Fig. 1);
+ *   - the neighbour list is rebuilt when a particle has moved more than
+ *     r_buff / 2 since the last build (Sec. 4.2);
+ *   - neighbour list and forces with w cooperating lanes per particle and a
+ *     compacting prefix sum (Sec. 5.1, Fig. 4), tuned at run time (Sec. 5.2);
+ *   - a bond is an unordered pair of particle IDs (Sec. 4.3.4);
+ *   - ghosts are selected by a per-direction bitfield, ordered by
+ *     destination, gathered into a send buffer, and appended after the local
+ *     particles (Sec. 4.3.2, Fig. 2); DPD ghosts carry velocities and IDs
+ *     (Sec. 9);
+ *   - the integrator is NVE velocity Verlet (Sec. 3).
+ *
+ * Memory ownership.  The caller allocates and owns every device buffer: the
+ * particle arrays and one workspace block sized by hoomd_workspace_bytes().
+ * The library borrows the pointers for the life of the context, never
+ * allocates or frees device memory, and never aborts.  All work is queued
+ * asynchronously on the stream given to hoomd_init(); only the calls marked
+ * "synchronises" wait for the device.  A context is not thread-safe; use one
+ * context per stream.
+ *
+ * Particle layout (all device pointers, n_cap rows, 64-bit aligned):
+ *   pos    double[n_cap][4]  x, y, z, w.  w is carried along and ignored.
+ *   vel    double[n_cap][4]  vx, vy, vz, w.  Unit mass.
+ *   force  float[n_cap][4] (HOOMD_MIXED) or double[n_cap][4] (HOOMD_FP64):
+ *          fx, fy, fz, and the particle's pair + bond energy.
+ *   tag    int32[n_cap]      identity of each particle (0..n-1 per system).
+ * Rows [0, n_local) are the particles the library integrates; rows
+ * [n_local, n_local + n_ghost) hold ghosts appended by unpack_ghosts().
+ * A spatial sort permutes rows of pos, vel, force and tag together; tags
+ * keep track of identity.
+ *
+ * Positions of a periodic axis lie in [lo, lo + L); after each drift a
+ * coordinate is folded once: x >= hi -> x - L, else x < lo -> x + L, and a
+ * value that rounded up to hi is folded again.
+ */
+#ifndef HOOMD_MI355X_H
+#define HOOMD_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hoomd_ctx hoomd_ctx;
+
+/* Return codes.  Codes >= HOOMD_E_NLIST_OVERFLOW are detected on the device,
+ * latched in a status word and reported by hoomd_sync_status(). */
+typedef enum {
+    HOOMD_OK = 0,
+    HOOMD_E_ARG = 1,             /* invalid argument; nothing was queued    */
+    HOOMD_E_DEVICE = 2,          /* a HIP runtime call failed               */
+    HOOMD_E_WORKSPACE = 3,       /* workspace smaller than required         */
+    HOOMD_E_STATE = 4,           /* call not valid in the context's state   */
+    HOOMD_E_NLIST_OVERFLOW = 5,  /* a neighbour row exceeded nlist_cap      */
+    HOOMD_E_CELL_OVERFLOW = 6,   /* a cell held more than cell_cap members  */
+    HOOMD_E_GHOST_OVERFLOW = 7,  /* send list or buffer capacity exceeded   */
+    HOOMD_E_BOND_STRETCH = 8,    /* a FENE bond reached r >= R0             */
+    HOOMD_E_NAN = 9,             /* a non-finite force or position          */
+    HOOMD_E_DANGEROUS_BUILD = 10 /* rebuild found a particle beyond r_buff/2
+                                    when the check period is > 1            */
+} hoomd_status;
+
+/* Arithmetic of the pair and bond terms.  Positions, velocities, the
+ * integrator and every energy / virial reduction are FP64 in both modes. */
+enum { HOOMD_FP64 = 0, HOOMD_MIXED = 1 };
+
+/* Pair potential of a system (the paper's Sec. 3 names LJ and DPD; WCA is the
+ * bead-bead repulsion of bead-spring polymers).
+ *   LJ : V = 4 eps [(s/r)^12 - (s/r)^6] for r < r_cut, force truncated,
+ *        energy shifted by -V(r_cut).
+ *   WCA: LJ cut at 2^(1/6) sigma and shifted up by eps (r_cut is ignored).
+ *   DPD: F = [A w - gamma w^2 (rhat.v_ij) + sqrt(2 gamma kT) w theta/sqrt(dt)]
+ *        rhat with w = 1 - r/r_cut; theta from Philox4x32-10 with counter
+ *        (min tag, max tag, 0, 0) and key (seed, timestep), mapped to a
+ *        uniform variate of unit variance; pair energy (A r_cut / 2) w^2. */
+enum { HOOMD_PAIR_LJ = 0, HOOMD_PAIR_WCA = 1, HOOMD_PAIR_DPD = 2 };
+
+typedef struct {
+    int32_t precision;     /* HOOMD_FP64 or HOOMD_MIXED                      */
+    int32_t pair;          /* HOOMD_PAIR_*                                  */
+    double r_cut;          /* pair cut-off (LJ, DPD)                        */
+    double r_buff;         /* Verlet buffer; list radius r_cut + r_buff      */
+    double dt;             /* time step                                      */
+    double eps, sigma;     /* LJ / WCA parameters                            */
+    double dpd_A, dpd_gamma, dpd_kT;
+    uint32_t dpd_seed;
+    int32_t bond_cap;      /* max bonds per particle (0 = no bonds)          */
+    double fene_K, fene_R0;/* FENE + WCA(eps, sigma) bond term              */
+    int32_t nlist_cap;     /* neighbour row capacity (entries per particle)  */
+    int32_t cell_cap;      /* cell capacity (0 = derived from the density)   */
+    int32_t sort_period;   /* Morton sort every this many steps (0 = never)  */
+    int32_t check_period;  /* displacement check every k steps (>= 1)        */
+    int32_t tpp_nlist;     /* lanes per particle, neighbour list (0 = tuned) */
+    int32_t tpp_force;     /* lanes per particle, forces (0 = tuned)         */
+    int32_t block_nlist;   /* threads per block (0 = tuned)                  */
+    int32_t block_force;
+} hoomd_params;
+
+/* Geometry of one system.  For a periodic box lo = 0 and L is the box.  For
+ * a subdomain frame with ghosts the open axes have periodic = 0 and [lo, lo
+ * + L) must contain every local and ghost position. */
+typedef struct {
+    double lo[3];
+    double L[3];
+    int32_t periodic[3];
+    int32_t pad_;
+    int64_t n_local;       /* particles integrated and given forces          */
+    int64_t n_cap;         /* rows available (locals + room for ghosts)      */
+    int64_t n_bonds;       /* entries in the bond table                      */
+} hoomd_box;
+
+/* Device arrays of one context (see the layout above).  bonds: int32[n_bonds]
+ * [2] pairs of tags (unordered), or NULL.  When n_sys > 1 the arrays of all
+ * systems are concatenated, system s starting at row sum_{t<s} n_cap_t and at
+ * bond sum_{t<s} n_bonds_t. */
+typedef struct {
+    double *pos;
+    double *vel;
+    void *force;
+    int32_t *tag;
+    const int32_t *bonds;
+} hoomd_arrays;
+
+/* Bytes of device workspace needed for these systems and parameters.  Returns
+ * 0 on invalid arguments. */
+size_t hoomd_workspace_bytes(const hoomd_params *params, int32_t n_sys, const hoomd_box *boxes);
+
+/* Create a context over caller-owned device arrays.  params and boxes hold
+ * n_sys entries each (one per independent system; all systems share the
+ * precision).  `stream` is a hipStream_t (NULL = the null stream).
+ * Copies the bond table into per-particle partner rows, clears the status
+ * word, and queues nothing else.  Errors: HOOMD_E_ARG, HOOMD_E_WORKSPACE,
+ * HOOMD_E_DEVICE. */
+int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys,
+               const hoomd_box *boxes, const hoomd_arrays *arrays, void *workspace,
+               size_t workspace_bytes, void *stream);
+
+void hoomd_destroy(hoomd_ctx *ctx);
+
+/* Build the cell list and the Verlet neighbour list of every system from the
+ * current positions (Sec. 5.1, Fig. 4): particle j != i is listed in row i
+ * when |x_j - x_i|^2 < (r_cut + r_buff)^2 in FP64, minimum image along
+ * periodic axes, excluding bonded partners.  force_rebuild = 0 builds only
+ * if some particle moved more than r_buff/2 since the last build.  Rows are
+ * ordered by stencil cell (z, y, x offsets from -1 to 1) then by ascending
+ * index inside the cell.  Overflow of a row or a cell latches a status. */
+int build_nlist(hoomd_ctx *ctx, int32_t force_rebuild);
+
+/* Flags of compute_forces() and step(). */
+enum { HOOMD_ENERGY = 1u, HOOMD_VIRIAL = 2u };
+
+/* Forces on the local particles at the current state, keyed (for DPD) on
+ * `timestep`.  Builds the neighbour list first if needed.  Writes `force`
+ * (energy in the w component when HOOMD_ENERGY is set) and, with flags, the
+ * per-system thermo sums read by hoomd_thermo(). */
+int compute_forces(hoomd_ctx *ctx, uint64_t timestep, uint32_t flags);
+
+/* Advance every system n_steps velocity-Verlet steps, the state before the
+ * call being that of timestep first_timestep: per step v += dt/2 F; x += dt
+ * v (folded); rebuild when needed; F <- F(x, v, t+1); v += dt/2 F.  With
+ * log_every > 0 the thermo sums are recorded every log_every steps (and at
+ * the last step) in a device ring read by hoomd_thermo_log().  Morton sorts
+ * happen every sort_period steps.  On return pos, vel, force and tag hold
+ * the final state. */
+int step(hoomd_ctx *ctx, uint64_t first_timestep, int32_t n_steps, int32_t log_every);
+
+/* Ghost selection and packing for system `sys` (Sec. 4.3.2, Fig. 2).
+ * subdomain = {lo[3], hi[3], width}: a local particle is sent in direction
+ * d in {-1,0,1}^3 \ {0} (index (dz+1)*9 + (dy+1)*3 + (dx+1), centre removed,
+ * 0..25) when on every axis with d_a = +1 it has x_a >= hi_a - width and on
+ * every axis with d_a = -1 it has x_a < lo_a + width.
+ * mode HOOMD_GHOST_SELECT recomputes the send list (ordered by direction,
+ * then ascending local index) and stores it in the context;
+ * mode HOOMD_GHOST_UPDATE re-gathers the fields of the stored list.
+ * fields (HOOMD_FIELD_*) choose what is packed; the send buffer holds, for
+ * the whole list and in this order, double[k][3] positions, double[k][3]
+ * velocities, int32[k] tags (only the chosen ones), k = total entries.
+ * counts26 / offsets26: device int32[26] outputs (entries per direction and
+ * exclusive offsets).  send_cap is the capacity in entries; a longer list
+ * latches HOOMD_E_GHOST_OVERFLOW and packs nothing past the capacity. */
+typedef struct { double lo[3]; double hi[3]; double width; } hoomd_subdomain;
+enum { HOOMD_GHOST_SELECT = 0, HOOMD_GHOST_UPDATE = 1 };
+enum { HOOMD_FIELD_POS = 1u, HOOMD_FIELD_VEL = 2u, HOOMD_FIELD_TAG = 4u };
+int pack_ghosts(hoomd_ctx *ctx, int32_t sys, const hoomd_subdomain *subdomain, int32_t mode,
+                uint32_t fields, void *send, int64_t send_cap, int32_t *counts26,
+                int32_t *offsets26);
+
+/* Append (HOOMD_GHOST_SELECT) or overwrite in place (HOOMD_GHOST_UPDATE)
+ * the n_recv ghosts of a receive buffer laid out as pack_ghosts() writes it,
+ * after the locals of system `sys`.  Each received position is moved to its
+ * periodic image nearest the centre of the frame [lo, lo + L) of the
+ * system (box_L = the full periodic box).  Exceeding n_cap latches
+ * HOOMD_E_GHOST_OVERFLOW. */
+int unpack_ghosts(hoomd_ctx *ctx, int32_t sys, const void *recv, int64_t n_recv,
+                  uint32_t fields, int32_t mode, const double *box_L);
+
+/* Per-system thermo {KE, PE, W, T} of the last evaluation that asked for
+ * energies (compute_forces with flags, or a logged step), FP64, summed in a
+ * fixed order.  out holds 4 * n_sys doubles.  Synchronises. */
+int hoomd_thermo(hoomd_ctx *ctx, double *out);
+
+/* Copy up to max_rows logged rows {timestep, KE, PE, W, T} per system
+ * (row-major [row][sys][5]) of the last step() call.  Synchronises.  Returns
+ * the number of rows via *rows. */
+int hoomd_thermo_log(hoomd_ctx *ctx, double *out, int32_t max_rows, int32_t *rows);
+
+/* Read and clear the device status word.  Returns the first latched
+ * condition (HOOMD_OK if none); *required (may be NULL) receives the
+ * capacity that would have avoided an overflow (row entries, cell members or
+ * ghost entries).  Synchronises. */
+int hoomd_sync_status(hoomd_ctx *ctx, int64_t *required);
+
+/* Number of neighbour-list builds since hoomd_init.  Synchronises. */
+int hoomd_build_count(hoomd_ctx *ctx, int64_t *builds);
+
+/* Device pointers into the workspace for inspection: the neighbour list
+ * (int32, row of particle i at entries (i/64)*64*cap + k*64 + i%64, k <
+ * nn[i]), the counts nn (int32[n]), the cell members (int32, cell c at c *
+ * cell_cap + k, k < cell_size[c]), cell sizes, and the bins per axis of
+ * system `sys`.  Row i of system s is row offset_s + i of the arrays. */
+typedef struct {
+    const int32_t *nlist;
+    const int32_t *nn;
+    const int32_t *cell_idx;
+    const int32_t *cell_size;
+    int32_t nlist_cap;
+    int32_t cell_cap;
+    int32_t bins[3];
+    int64_t row_offset;
+    int64_t cell_offset;
+} hoomd_layout;
+int hoomd_get_layout(hoomd_ctx *ctx, int32_t sys, hoomd_layout *out);
+
+/* Lanes per particle and block sizes in use; with do_tune != 0, first time
+ * each candidate on the current state (median of 5 launches each) and keep
+ * the fastest (Sec. 5.2).  Synchronises when tuning. */
+typedef struct { int32_t tpp_nlist, block_nlist, tpp_force, block_force; } hoomd_tuning;
+int hoomd_autotune(hoomd_ctx *ctx, int32_t do_tune, hoomd_tuning *out);
+
+/* Device time per phase of step(), measured with HIP events recorded on the
+ * context's stream around every fused force launch and every queued rebuild
+ * sequence (cell list + neighbour list, including launches that find no
+ * rebuild needed).  mode 1 = start (clears the totals), 0 = stop, 2 = read
+ * (synchronises; fills *out with the totals since the last start). */
+typedef struct {
+    double force_ms;
+    int64_t force_launches;
+    double rebuild_ms;
+    int64_t rebuild_launches;
+} hoomd_profile_t;
+int hoomd_profile(hoomd_ctx *ctx, int32_t mode, hoomd_profile_t *out);
+
+const char *hoomd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOOMD_MI355X_H */

@@ -1,0 +1,396 @@
+// forces.hip -- pair + bond forces fused with the velocity-Verlet update.
+//
+// Sec. 5.1: W lanes cooperate on one particle, striding over its neighbour
+// row, and a lane reduction totals the force.  One launch per time step does
+// the whole step of a particle: the closing half kick of the previous step,
+// the thermo sums, the opening half kick, the drift, the fold into the box
+// and the displacement check that decides the next neighbour-list rebuild
+// (Sec. 4.2: rebuild once a particle has moved more than r_buff / 2).  New
+// positions go to the other half of a position double buffer, so every
+// neighbour read in the launch sees the old ones; DPD double-buffers the
+// velocities too, because the pair force reads neighbour velocities.
+//
+// Precision: every separation, the cut-off test and the integrator are
+// FP64.  With MIXED the pair and bond arithmetic after the cut-off test and
+// the force accumulation are FP32; energies and virials are summed in FP64.
+#include <type_traits>
+
+#include "device.h"
+#include "launch.h"
+
+namespace md {
+
+template <typename T> __device__ __forceinline__ T recip(T x);
+template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+
+template <typename T> __device__ __forceinline__ T tsqrt(T x);
+template <> __device__ __forceinline__ float tsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <> __device__ __forceinline__ double tsqrt<double>(double x) { return __builtin_sqrt(x); }
+
+template <typename T> __device__ __forceinline__ T tlog(T x);
+template <> __device__ __forceinline__ float tlog<float>(float x) { return __logf(x); }
+template <> __device__ __forceinline__ double tlog<double>(double x) { return log(x); }
+
+// LJ-family pair term for one neighbour inside the cut-off.  Returns the
+// force divided by r (F_i = ff * (x_i - x_j)); adds energy and virial.
+template <typename T, bool LOG>
+__device__ __forceinline__ T lj_pair(double r2, T eps, T sig2, double shift, double &e, double &vir)
+{
+    const T r2inv = recip<T>((T)r2);
+    const T s2 = sig2 * r2inv;
+    const T s6 = s2 * s2 * s2;
+    const T ff = (T)24 * eps * s6 * ((T)2 * s6 - (T)1) * r2inv;
+    if constexpr (LOG) {
+        e += (double)((T)4 * eps * s6 * (s6 - (T)1)) - shift;
+        vir += (double)(ff * (T)r2);
+    }
+    return ff;
+}
+
+template <int W, bool MIXED, int POT, bool LOG>
+__global__ __launch_bounds__(256) void k_force(const SysDev *__restrict__ sys,
+                                               const int32_t *__restrict__ tprefix, int n_sys,
+                                               int tiles, const int32_t *__restrict__ nlist,
+                                               const int32_t *__restrict__ nn, int cap,
+                                               const int32_t *__restrict__ partners,
+                                               const int32_t *__restrict__ rtag,
+                                               const double4 *__restrict__ xbuild,
+                                               double *__restrict__ partials, Status *st,
+                                               ForceLaunch a)
+{
+    using T = typename std::conditional<MIXED, float, double>::type;
+    constexpr int P = kWave / W;
+    const int lane = lane_id();
+    const int pl = lane % P;
+    const int sl = lane / P;
+    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int tile = gw / W;
+    if (tile >= tiles) return;
+    if (a.flag_clear && gw == 0 && lane == 0) *a.flag_clear = 0;
+    const int s = find_sys(tprefix, n_sys, tile);
+    const SysDev &S = sys[s];
+    const int r = (tile - S.tile0) * kTile + (gw % W) * P + pl;
+    const bool active = r < S.n_local;
+    const int64_t i = S.row0 + (active ? r : 0);
+
+    const double4 xi = a.pos[i];
+    double4 vi;
+    if constexpr (POT == PAIR_DPD) vi = a.vel[i];
+    int32_t ti = 0;
+    if constexpr (POT == PAIR_DPD) ti = a.tag[i];
+    int n = active ? nn[i] : 0;
+    n = n < cap ? n : cap;
+    const int32_t *row = nlist + S.nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
+
+    T fx = 0, fy = 0, fz = 0;
+    double e = 0.0, vir = 0.0;
+    const double rc2 = S.rc2;
+    const T eps = (T)S.eps, sig2 = (T)S.sig2;
+    const double shift = S.shift;
+
+    for (int k = sl; k < n; k += W) {
+        const int32_t j = row[(int64_t)k * kTile];
+        const double2 xyj = *reinterpret_cast<const double2 *>(&a.pos[j]);
+        const double zj = a.pos[j].z;
+        const double dx = min_image(xi.x - xyj.x, S.L[0], S.invL[0]);
+        const double dy = min_image(xi.y - xyj.y, S.L[1], S.invL[1]);
+        const double dz = min_image(xi.z - zj, S.L[2], S.invL[2]);
+        const double r2 = norm2_exact(dx, dy, dz);
+        if (r2 < rc2) {
+            T ff;
+            if constexpr (POT == PAIR_LJ || POT == PAIR_WCA) {
+                ff = lj_pair<T, LOG>(r2, eps, sig2, shift, e, vir);
+            } else {
+                if (r2 == 0.0) continue;
+                const double4 vj = a.vel[j];
+                const T tr2 = (T)r2;
+                const T rr = tsqrt<T>(tr2);
+                const T rinv = recip<T>(rr);
+                const T w = (T)1 - rr * (T)S.dpd_inv_rc;
+                const T dvx = (T)(vi.x - vj.x), dvy = (T)(vi.y - vj.y), dvz = (T)(vi.z - vj.z);
+                const T rv = ((T)dx * dvx + (T)dy * dvy + (T)dz * dvz) * rinv;
+                const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)a.tag[j], S.dpd_seed, a.timestep);
+                const T u = (T)bits * (T)(1.0 / 16777216.0);
+                const T theta = (T)1.7320508075688772 * ((T)2 * u - (T)1);
+                const T mag = (T)S.dpd_A * w - (T)S.dpd_gamma * w * w * rv +
+                              (T)S.dpd_sigma * w * theta * (T)S.dpd_inv_sqrt_dt;
+                ff = mag * rinv;
+                if constexpr (LOG) {
+                    e += 0.5 * S.dpd_A * S.dpd_rc * (double)(w * w);
+                    vir += (double)(ff * tr2);
+                }
+            }
+            fx += ff * (T)dx;
+            fy += ff * (T)dy;
+            fz += ff * (T)dz;
+        }
+    }
+
+    fx = segment_sum<W>(fx);
+    fy = segment_sum<W>(fy);
+    fz = segment_sum<W>(fz);
+    if constexpr (LOG) {
+        e = segment_sum<W>(e);
+        vir = segment_sum<W>(vir);
+    }
+
+    double ke = 0.0;
+    const bool owner = active && sl == 0;
+    if (owner) {
+        double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
+        double ue = 0.5 * e, uw = 0.5 * vir;
+        // bonds: FENE + WCA with partner rows indexed by tag
+        if (S.bond_cap > 0) {
+            const int32_t tg = a.tag[i];
+            const int64_t prow = (S.row0 + tg) * S.bond_cap;
+            for (int b = 0; b < S.bond_cap; ++b) {
+                const int32_t tp = partners[prow + b];
+                if (tp < 0) continue;
+                const int64_t j = rtag[S.row0 + tp];
+                const double4 xj = a.pos[j];
+                const double dx = min_image(xi.x - xj.x, S.L[0], S.invL[0]);
+                const double dy = min_image(xi.y - xj.y, S.L[1], S.invL[1]);
+                const double dz = min_image(xi.z - xj.z, S.L[2], S.invL[2]);
+                const double r2 = norm2_exact(dx, dy, dz);
+                if (!(r2 < S.fene_R02)) {
+                    latch(st, 8 /*BOND_STRETCH*/, 0);
+                    continue;
+                }
+                const T g = (T)1 - (T)r2 * (T)(1.0 / S.fene_R02);
+                T ff = -(T)S.fene_K * recip<T>(g);
+                double eb = 0.0, vb = 0.0;
+                if constexpr (LOG) eb = -0.5 * S.fene_K * S.fene_R02 * (double)tlog<T>(g);
+                if (r2 < S.wca_rc2) {
+                    double e2 = 0.0, v2 = 0.0;
+                    ff += lj_pair<T, LOG>(r2, eps, sig2, -S.eps, e2, v2);
+                    eb += e2;
+                }
+                if constexpr (LOG) vb = (double)(ff * (T)r2);
+                Fx += (double)(ff * (T)dx);
+                Fy += (double)(ff * (T)dy);
+                Fz += (double)(ff * (T)dz);
+                ue += 0.5 * eb;
+                uw += 0.5 * vb;
+            }
+        }
+        if (!__builtin_isfinite(Fx + Fy + Fz)) latch(st, 9 /*NAN*/, 0);
+
+        double4 v = (POT == PAIR_DPD) ? vi : a.vel[i];
+        const double hdt = S.hdt;
+        if (a.mode == MODE_MID || a.mode == MODE_LAST) {
+            v.x += hdt * Fx;
+            v.y += hdt * Fy;
+            v.z += hdt * Fz;
+        }
+        if constexpr (LOG) ke = 0.5 * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+        if (a.mode == MODE_FIRST || a.mode == MODE_MID) {
+            v.x += hdt * Fx;
+            v.y += hdt * Fy;
+            v.z += hdt * Fz;
+            double4 x = xi;
+            x.x += S.dt * v.x;
+            x.y += S.dt * v.y;
+            x.z += S.dt * v.z;
+            if (S.per[0]) x.x = fold(x.x, S.lo[0], S.L[0]);
+            if (S.per[1]) x.y = fold(x.y, S.lo[1], S.L[1]);
+            if (S.per[2]) x.z = fold(x.z, S.lo[2], S.L[2]);
+            a.pos_out[i] = x;
+            a.vel_out[i] = v;
+            const double4 xb = xbuild[i];
+            const double bx = min_image(x.x - xb.x, S.L[0], S.invL[0]);
+            const double by = min_image(x.y - xb.y, S.L[1], S.invL[1]);
+            const double bz = min_image(x.z - xb.z, S.L[2], S.invL[2]);
+            if ((bx * bx + by * by) + bz * bz > S.disp2) *a.flag_set = 1;
+        } else {
+            if (a.mode == MODE_LAST) a.vel_out[i] = v;
+            if (MIXED) {
+                float4 f = make_float4((float)Fx, (float)Fy, (float)Fz, a.energy ? (float)ue : 0.0f);
+                reinterpret_cast<float4 *>(a.force)[i] = f;
+            } else {
+                double4 f = make_double4(Fx, Fy, Fz, a.energy ? ue : 0.0);
+                reinterpret_cast<double4 *>(a.force)[i] = f;
+            }
+        }
+        e = ue;
+        vir = uw;
+    }
+    if constexpr (LOG) {
+        double k3 = owner ? ke : 0.0;
+        double e3 = owner ? e : 0.0;
+        double w3 = owner ? vir : 0.0;
+        k3 = wave_sum(k3);
+        e3 = wave_sum(e3);
+        w3 = wave_sum(w3);
+        if (lane == 0) {
+            partials[3 * (int64_t)gw + 0] = k3;
+            partials[3 * (int64_t)gw + 1] = e3;
+            partials[3 * (int64_t)gw + 2] = w3;
+        }
+    }
+}
+
+// Per-system totals of the wave partials, in a fixed order.
+__global__ void k_thermo_reduce(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
+                                int W, const double *__restrict__ partials,
+                                double *__restrict__ thermo, double *__restrict__ log_rows,
+                                int n_sys, int log_row, double timestep)
+{
+    __shared__ double red[3][256];
+    const int s = blockIdx.x;
+    const SysDev &S = sys[s];
+    const int64_t w0 = (int64_t)tprefix[s] * W;
+    const int64_t w1 = (int64_t)tprefix[s + 1] * W;
+    double k = 0, e = 0, v = 0;
+    for (int64_t q = w0 + threadIdx.x; q < w1; q += blockDim.x) {
+        k += partials[3 * q + 0];
+        e += partials[3 * q + 1];
+        v += partials[3 * q + 2];
+    }
+    red[0][threadIdx.x] = k;
+    red[1][threadIdx.x] = e;
+    red[2][threadIdx.x] = v;
+    __syncthreads();
+    for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + m];
+            red[1][threadIdx.x] += red[1][threadIdx.x + m];
+            red[2][threadIdx.x] += red[2][threadIdx.x + m];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double KE = red[0][0], PE = red[1][0], VW = red[2][0];
+        const double dof = 3.0 * S.n_local - 3.0;
+        const double T = dof > 0 ? 2.0 * KE / dof : 0.0;
+        thermo[4 * s + 0] = KE;
+        thermo[4 * s + 1] = PE;
+        thermo[4 * s + 2] = VW;
+        thermo[4 * s + 3] = T;
+        if (log_row >= 0) {
+            double *o = log_rows + ((int64_t)log_row * n_sys + s) * 5;
+            o[0] = timestep;
+            o[1] = KE;
+            o[2] = PE;
+            o[3] = VW;
+            o[4] = T;
+        }
+    }
+}
+
+__global__ void k_set_flag(int32_t *flag, int32_t v) { *flag = v; }
+
+// Sets *flag when some local particle moved more than r_buff / 2 (minimum
+// image) since the positions recorded at the last build.
+__global__ void k_disp_check(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
+                             int n_sys, int tiles, const double4 *__restrict__ pos,
+                             const double4 *__restrict__ xbuild, int32_t *flag)
+{
+    const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (g >= tiles) return;
+    const int s = find_sys(tprefix, n_sys, g);
+    const SysDev &S = sys[s];
+    const int r = (g - S.tile0) * kTile + lane_id();
+    if (r >= S.n_local) return;
+    const int64_t i = S.row0 + r;
+    const double4 x = pos[i], xb = xbuild[i];
+    const double bx = min_image(x.x - xb.x, S.L[0], S.invL[0]);
+    const double by = min_image(x.y - xb.y, S.L[1], S.invL[1]);
+    const double bz = min_image(x.z - xb.z, S.L[2], S.invL[2]);
+    if ((bx * bx + by * by) + bz * bz > S.disp2) *flag = 1;
+}
+
+// rtag[row0 + tag[i]] = i over all rows of every system.
+__global__ void k_rtag(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys,
+                       int tiles, const int32_t *__restrict__ tag, int32_t *__restrict__ rtag)
+{
+    const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (g >= tiles) return;
+    const int s = find_sys(tprefix, n_sys, g);
+    const SysDev &S = sys[s];
+    const int r = (g - S.tile0_all) * kTile + lane_id();
+    if (r >= S.n_total) return;
+    const int64_t i = S.row0 + r;
+    rtag[S.row0 + tag[i]] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+
+template <int W, bool MIXED, int POT, bool LOG>
+static void force_inst(const LaunchCtx &L, const ForceLaunch &F, int block)
+{
+    const int64_t threads_total = (int64_t)L.tiles_local * W * kWave;
+    const int blocks = (int)((threads_total + block - 1) / block);
+    if (blocks == 0) return;
+    hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(blocks), dim3(block), 0, L.stream, L.sys,
+                       L.tprefix_local, L.n_sys, L.tiles_local, L.nlist, L.nn, L.nlist_cap,
+                       L.partners, L.rtag, L.xbuild, L.partials, L.status, F);
+}
+
+template <int W, bool MIXED, int POT>
+static void force_log(const LaunchCtx &L, const ForceLaunch &F, int block)
+{
+    if (F.log) force_inst<W, MIXED, POT, true>(L, F, block);
+    else force_inst<W, MIXED, POT, false>(L, F, block);
+}
+
+template <int W, bool MIXED>
+static void force_pot(const LaunchCtx &L, const ForceLaunch &F, int block)
+{
+    switch (F.pair) {
+    case PAIR_LJ: force_log<W, MIXED, PAIR_LJ>(L, F, block); break;
+    case PAIR_WCA: force_log<W, MIXED, PAIR_WCA>(L, F, block); break;
+    default: force_log<W, MIXED, PAIR_DPD>(L, F, block); break;
+    }
+}
+
+template <int W>
+static void force_prec(const LaunchCtx &L, const ForceLaunch &F, int block)
+{
+    if (F.mixed) force_pot<W, true>(L, F, block);
+    else force_pot<W, false>(L, F, block);
+}
+
+void launch_force(const LaunchCtx &L, const ForceLaunch &F, int w, int block)
+{
+    switch (w) {
+    case 1: force_prec<1>(L, F, block); break;
+    case 2: force_prec<2>(L, F, block); break;
+    case 4: force_prec<4>(L, F, block); break;
+    case 8: force_prec<8>(L, F, block); break;
+    case 16: force_prec<16>(L, F, block); break;
+    default: force_prec<32>(L, F, block); break;
+    }
+}
+
+void launch_thermo_reduce(const LaunchCtx &L, int w, int log_row, double timestep)
+{
+    hipLaunchKernelGGL(k_thermo_reduce, dim3(L.n_sys), dim3(256), 0, L.stream, L.sys,
+                       L.tprefix_local, w, L.partials, L.thermo, L.thermo_log, L.n_sys, log_row,
+                       timestep);
+}
+
+void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value)
+{
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, L.stream, flag, value);
+}
+
+void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag)
+{
+    const int threads = 256;
+    const int blocks = (L.tiles_local * kWave + threads - 1) / threads;
+    if (blocks == 0) return;
+    hipLaunchKernelGGL(k_disp_check, dim3(blocks), dim3(threads), 0, L.stream, L.sys,
+                       L.tprefix_local, L.n_sys, L.tiles_local, pos, L.xbuild, flag);
+}
+
+void launch_rtag(const LaunchCtx &L, const int32_t *tag)
+{
+    const int threads = 256;
+    const int blocks = (L.tiles_all * kWave + threads - 1) / threads;
+    if (blocks == 0) return;
+    hipLaunchKernelGGL(k_rtag, dim3(blocks), dim3(threads), 0, L.stream, L.sys, L.tprefix_all,
+                       L.n_sys, L.tiles_all, tag, L.rtag);
+}
+
+}  // namespace md

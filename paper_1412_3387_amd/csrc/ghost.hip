@@ -1,0 +1,222 @@
+// ghost.hip -- ghost-layer exchange of one subdomain (Sec. 4.3.2, Fig. 2).
+//
+// The paper marks a per-particle bitfield of destinations, expands (index,
+// destination) pairs with a load-balancing search, merge-sorts them by
+// destination and finds segment bounds by binary search.  With at most 26
+// destinations the same ordered list falls out of a counting sort: one pass
+// builds the 26-bit mask of every local particle and counts, per block and
+// direction, how many go each way (one ballot per direction and wave); a scan
+// of the direction-major count table gives every (direction, block) its
+// first slot; a second pass places each entry at that slot plus its rank
+// among the same-direction entries of lower rows (ballot prefix counts) and
+// gathers the requested fields into the send record at once.  The result is
+// ordered by direction, then by ascending row, with no atomics.
+#include "ghost.h"
+#include "sort.h"
+
+namespace md {
+
+static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t ghost_workspace_bytes(int64_t rows, int n_sys)
+{
+    const int64_t blocks = (rows + kGhostBlock - 1) / kGhostBlock;
+    return a256(sizeof(uint32_t) * rows) + a256(sizeof(int32_t) * 26 * (size_t)blocks) +
+           a256(sizeof(int32_t) * kGhostPerRow * (size_t)rows) + a256(sizeof(int32_t) * n_sys) + 256;
+}
+
+GhostBuffers make_ghost_buffers(char *base, int64_t rows, int n_sys)
+{
+    (void)n_sys;
+    GhostBuffers B{};
+    const int64_t blocks = (rows + kGhostBlock - 1) / kGhostBlock;
+    size_t off = 0;
+    B.mask = reinterpret_cast<uint32_t *>(base + off); off += a256(sizeof(uint32_t) * rows);
+    B.blk_counts = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * 26 * (size_t)blocks);
+    B.list = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * kGhostPerRow * (size_t)rows);
+    B.totals = reinterpret_cast<int32_t *>(base + off);
+    B.rows = rows;
+    return B;
+}
+
+__device__ __forceinline__ uint32_t ghost_mask(const double4 x, const GhostArgs &g)
+{
+    const double xs[3] = {x.x, x.y, x.z};
+    uint32_t up = 0, dn = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        up |= (xs[a] >= g.hi[a] - g.width ? 1u : 0u) << a;
+        dn |= (xs[a] < g.lo[a] + g.width ? 1u : 0u) << a;
+    }
+    uint32_t m = 0;
+    int bit = 0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0) continue;
+                const int d[3] = {dx, dy, dz};
+                bool ok = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (d[a] == 1) ok = ok && ((up >> a) & 1u);
+                    if (d[a] == -1) ok = ok && ((dn >> a) & 1u);
+                }
+                m |= (ok ? 1u : 0u) << bit;
+                ++bit;
+            }
+    return m;
+}
+
+__device__ __forceinline__ void pack_record(const GhostArgs &g, int64_t k, int64_t row)
+{
+    double *rec = reinterpret_cast<double *>(static_cast<char *>(g.send) + k * ghost_record_bytes(g.fields));
+    int q = 0;
+    if (g.fields & 1u) {
+        const double4 x = g.pos[row];
+        rec[q++] = x.x;
+        rec[q++] = x.y;
+        rec[q++] = x.z;
+    }
+    if (g.fields & 2u) {
+        const double4 v = g.vel[row];
+        rec[q++] = v.x;
+        rec[q++] = v.y;
+        rec[q++] = v.z;
+    }
+    if (g.fields & 4u) {
+        int32_t *t = reinterpret_cast<int32_t *>(rec + q);
+        t[0] = g.tag[row];
+        t[1] = 0;
+    }
+}
+
+// Per-wave, per-direction counts into LDS: wc[wave][d].
+__device__ __forceinline__ void wave_dir_counts(uint32_t m, int32_t (*wc)[26])
+{
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    for (int d = 0; d < 26; ++d) {
+        const uint64_t b = __ballot((m >> d) & 1u);
+        if (lane == d) wc[w][d] = __popcll(b);
+    }
+}
+
+__global__ __launch_bounds__(kGhostBlock) void k_ghost_mask(GhostArgs g, int32_t *__restrict__ blk_counts,
+                                                           int nblocks)
+{
+    __shared__ int32_t wc[kGhostBlock / 64][26];
+    const int r = blockIdx.x * kGhostBlock + threadIdx.x;
+    uint32_t m = 0;
+    if (r < g.n_local) {
+        m = ghost_mask(g.pos[g.row0 + r], g);
+        g.mask[r] = m;
+    }
+    wave_dir_counts(m, wc);
+    __syncthreads();
+    if (threadIdx.x < 26) {
+        int32_t t = 0;
+        for (int w = 0; w < kGhostBlock / 64; ++w) t += wc[w][threadIdx.x];
+        blk_counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = t;
+    }
+}
+
+__global__ void k_ghost_totals(const int32_t *__restrict__ scanned, const int32_t *__restrict__ total,
+                               int nblocks, int32_t *__restrict__ counts, int32_t *__restrict__ offsets,
+                               int64_t send_cap, int64_t list_cap, Status *st)
+{
+    const int d = threadIdx.x;
+    if (d < 26) {
+        const int32_t a = scanned[(int64_t)d * nblocks];
+        const int32_t b = d < 25 ? scanned[(int64_t)(d + 1) * nblocks] : *total;
+        offsets[d] = a;
+        counts[d] = b - a;
+    }
+    if (d == 0 && ((int64_t)*total > send_cap || (int64_t)*total > list_cap))
+        latch(st, 7 /*GHOST_OVERFLOW*/, *total);
+}
+
+__global__ __launch_bounds__(kGhostBlock) void k_ghost_scatter(GhostArgs g, const int32_t *__restrict__ scanned,
+                                                              int nblocks)
+{
+    __shared__ int32_t wc[kGhostBlock / 64][26];
+    const int r = blockIdx.x * kGhostBlock + threadIdx.x;
+    const uint32_t m = r < g.n_local ? g.mask[r] : 0u;
+    wave_dir_counts(m, wc);
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    for (int d = 0; d < 26; ++d) {
+        const bool sel = (m >> d) & 1u;
+        const uint64_t b = __ballot(sel);
+        if (!sel) continue;
+        int64_t p = scanned[(int64_t)d * nblocks + blockIdx.x] + __popcll(b & lt);
+        for (int v = 0; v < w; ++v) p += wc[v][d];
+        if (p < g.list_cap) g.list[p] = r;
+        if (p < g.send_cap) pack_record(g, p, g.row0 + r);
+    }
+}
+
+__global__ void k_ghost_regather(GhostArgs g)
+{
+    int64_t n = *g.total;
+    n = n < g.list_cap ? n : g.list_cap;
+    n = n < g.send_cap ? n : g.send_cap;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        pack_record(g, k, g.row0 + g.list[k]);
+}
+
+__global__ void k_ghost_unpack(UnpackArgs u)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= u.n) return;
+    const double *rec = reinterpret_cast<const double *>(static_cast<const char *>(u.recv) +
+                                                         k * ghost_record_bytes(u.fields));
+    const int64_t row = u.first + k;
+    int q = 0;
+    if (u.fields & 1u) {
+        double x[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double v = rec[q++];
+            x[a] = v - u.box_L[a] * rint((v - u.center[a]) / u.box_L[a]);
+        }
+        u.pos[row] = make_double4(x[0], x[1], x[2], 0.0);
+    }
+    if (u.fields & 2u) {
+        u.vel[row] = make_double4(rec[q], rec[q + 1], rec[q + 2], 0.0);
+        q += 3;
+    }
+    if (u.fields & 4u) u.tag[row] = reinterpret_cast<const int32_t *>(rec + q)[0];
+}
+
+int queue_ghost_select(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g)
+{
+    const int nblocks = (g.n_local + kGhostBlock - 1) / kGhostBlock;
+    const int nb = nblocks > 0 ? nblocks : 1;
+    hipLaunchKernelGGL(k_ghost_mask, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb);
+    launch_scan_single(stream, B.blk_counts, B.blk_counts, 26 * (int64_t)nb, g.total);
+    hipLaunchKernelGGL(k_ghost_totals, dim3(1), dim3(64), 0, stream, B.blk_counts, g.total, nb, g.counts,
+                       g.offsets, g.send_cap, g.list_cap, g.status);
+    hipLaunchKernelGGL(k_ghost_scatter, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+int queue_ghost_update(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g)
+{
+    (void)B;
+    hipLaunchKernelGGL(k_ghost_regather, dim3(256), dim3(256), 0, stream, g);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+int queue_ghost_unpack(hipStream_t stream, const UnpackArgs &u)
+{
+    if (u.n <= 0) return 0;
+    const int blocks = (int)((u.n + 255) / 256);
+    hipLaunchKernelGGL(k_ghost_unpack, dim3(blocks), dim3(256), 0, stream, u);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+}  // namespace md

@@ -1,0 +1,73 @@
+// launch.h -- what the host runtime hands to the kernel launchers: device
+// pointers carved from the workspace plus the launch geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace md {
+
+enum StepMode : int32_t {
+    MODE_FORCE = 0,  // F(t) only
+    MODE_FIRST = 1,  // F(t) from v(t); v(t+1/2); x(t+1)
+    MODE_MID = 2,    // F(t) from v(t-1/2); v(t); v(t+1/2); x(t+1)
+    MODE_LAST = 3    // F(t) from v(t-1/2); v(t); writes F
+};
+
+struct LaunchCtx {
+    hipStream_t stream;
+    int n_sys;
+    const SysDev *sys;
+    const int32_t *tprefix_local;  // n_sys+1 prefix of local tiles
+    const int32_t *tprefix_all;    // n_sys+1 prefix of tiles over all rows
+    int tiles_local;
+    int tiles_all;
+    int64_t n_cells;
+    int cell_cap;
+    int32_t *cell_count;
+    int32_t *cell_size;
+    int32_t *cell_idx;
+    int32_t *nlist;
+    int32_t *nn;
+    int nlist_cap;
+    double4 *xbuild;
+    const int32_t *partners;       // per tag: bond_cap partner tags (-1 = none)
+    int32_t *rtag;                 // row of each tag (per system offset row0)
+    bool has_bonds;
+    int32_t *flag;                 // rebuild flag read by the rebuild kernels
+    int32_t *build_count;
+    Status *status;
+    double *partials;              // 3 doubles per wave
+    double *thermo;                // 4 doubles per system
+    double *thermo_log;            // rows of 5 doubles per system
+};
+
+struct ForceLaunch {
+    const double4 *pos;
+    double4 *pos_out;
+    const double4 *vel;
+    double4 *vel_out;
+    const int32_t *tag;
+    void *force;
+    int32_t *flag_set;
+    int32_t *flag_clear;
+    uint32_t timestep;
+    int32_t mode;
+    int32_t log;      // accumulate energy / virial, write thermo partials
+    int32_t energy;   // write the energy into force.w
+    int32_t mixed;
+    int32_t pair;     // one Pair for every system of the launch, or -1 = mixed batch
+};
+
+void launch_bin(const LaunchCtx &L, const double4 *pos);
+void launch_cell_sort(const LaunchCtx &L);
+void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int w, int block);
+void launch_force(const LaunchCtx &L, const ForceLaunch &F, int w, int block);
+void launch_thermo_reduce(const LaunchCtx &L, int w, int log_row, double timestep);
+void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value);
+void launch_rtag(const LaunchCtx &L, const int32_t *tag);
+void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag);
+
+}  // namespace md

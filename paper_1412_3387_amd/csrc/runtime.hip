@@ -1,0 +1,813 @@
+// runtime.hip -- host side of the C ABI: validation, workspace carving, the
+// per-system descriptors, and the scheduling of one velocity-Verlet step as
+// a fixed sequence of launches with device-side rebuild decisions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/hoomd_mi355x.h"
+#include "device.h"
+#include "launch.h"
+#include "sort.h"
+#include "ghost.h"
+
+using namespace md;
+
+#define HIP_OK(call)                                  \
+    do {                                              \
+        if ((call) != hipSuccess) return HOOMD_E_DEVICE; \
+    } while (0)
+
+namespace {
+
+constexpr int kLogRows = 4096;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Layout {
+    // byte offsets into the workspace
+    size_t sysdev, tpl, tpa, status, flags, thermo, thermo_log, partials;
+    size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx;
+    size_t rtag, partners, sort_ws, ghost_ws, total;
+    // sizes
+    int64_t rows, tiles_local, tiles_all, n_cells, nlist_entries;
+    int cell_cap, nlist_cap, bond_cap;
+    std::vector<SysDev> sys;
+    std::vector<int32_t> tpl_host, tpa_host;
+};
+
+double pair_cut(const hoomd_params &p)
+{
+    if (p.pair == HOOMD_PAIR_WCA) return std::pow(2.0, 1.0 / 6.0) * p.sigma;
+    return p.r_cut;
+}
+
+int cell_bins(double L, double rl)
+{
+    int64_t b = (int64_t)std::floor(L / rl);
+    while (b > 1 && L / (double)b < rl) --b;
+    return (int)std::max<int64_t>(b, 1);
+}
+
+bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
+{
+    if (!p || !boxes || n_sys < 1) return false;
+    for (int s = 0; s < n_sys; ++s) {
+        const hoomd_params &q = p[s];
+        const hoomd_box &b = boxes[s];
+        if (q.precision != p[0].precision) return false;
+        if (q.precision != HOOMD_FP64 && q.precision != HOOMD_MIXED) return false;
+        if (q.pair < HOOMD_PAIR_LJ || q.pair > HOOMD_PAIR_DPD) return false;
+        if (!(q.r_buff >= 0) || !(q.dt > 0)) return false;
+        if (q.pair != HOOMD_PAIR_WCA && !(q.r_cut > 0)) return false;
+        if (q.pair != HOOMD_PAIR_DPD && !(q.sigma > 0)) return false;
+        if (q.nlist_cap < 1 || q.nlist_cap > (1 << 16)) return false;
+        if (q.cell_cap < 0 || q.cell_cap > 128) return false;
+        if (q.bond_cap < 0 || q.bond_cap > kMaxBondCap) return false;
+        if (q.check_period < 0) return false;
+        if (b.n_local < 0 || b.n_cap < b.n_local || b.n_cap > (int64_t)1 << 30) return false;
+        if (b.n_bonds < 0 || (b.n_bonds > 0 && q.bond_cap == 0)) return false;
+        const double rl = pair_cut(q) + q.r_buff;
+        for (int a = 0; a < 3; ++a) {
+            if (!(b.L[a] > 0) || !std::isfinite(b.L[a]) || !std::isfinite(b.lo[a])) return false;
+            if (b.periodic[a] && !(2.0 * rl < b.L[a])) return false;  // unique minimum image
+        }
+    }
+    return true;
+}
+
+Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
+{
+    Layout Lo{};
+    Lo.nlist_cap = 0;
+    Lo.cell_cap = 0;
+    Lo.bond_cap = 0;
+    int64_t row = 0, tile = 0, tile_all = 0, cell = 0, nl = 0;
+    Lo.tpl_host.push_back(0);
+    Lo.tpa_host.push_back(0);
+    for (int s = 0; s < n_sys; ++s) {
+        Lo.nlist_cap = std::max(Lo.nlist_cap, p[s].nlist_cap);
+        Lo.bond_cap = std::max(Lo.bond_cap, p[s].bond_cap);
+    }
+    for (int s = 0; s < n_sys; ++s) {
+        const hoomd_params &q = p[s];
+        const hoomd_box &b = boxes[s];
+        SysDev S{};
+        const double rc = pair_cut(q);
+        const double rl = rc + q.r_buff;
+        double vol = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            S.lo[a] = b.lo[a];
+            S.L[a] = b.L[a];
+            S.per[a] = b.periodic[a] ? 1 : 0;
+            S.invL[a] = b.periodic[a] ? 1.0 / b.L[a] : 0.0;
+            S.bins[a] = cell_bins(b.L[a], rl);
+            S.scale[a] = (double)S.bins[a] / b.L[a];
+            if (!S.per[a] || S.bins[a] >= 3) {
+                S.nst[a] = 3;
+                S.st[a][0] = -1; S.st[a][1] = 0; S.st[a][2] = 1;
+            } else if (S.bins[a] == 2) {
+                S.nst[a] = 2;
+                S.st[a][0] = 0; S.st[a][1] = 1;
+            } else {
+                S.nst[a] = 1;
+                S.st[a][0] = 0;
+            }
+            vol *= b.L[a];
+        }
+        S.row0 = row;
+        S.n_local = (int32_t)b.n_local;
+        S.n_total = (int32_t)b.n_local;
+        S.n_cap = (int32_t)b.n_cap;
+        S.nl0 = nl;
+        S.cell0 = cell;
+        S.tile0 = (int32_t)tile;
+        S.tile0_all = (int32_t)tile_all;
+        S.pair = q.pair;
+        S.bond_cap = q.bond_cap;
+        S.rc2 = rc * rc;
+        S.rl2 = rl * rl;
+        S.disp2 = 0.25 * q.r_buff * q.r_buff;
+        S.eps = q.eps;
+        S.sig2 = q.sigma * q.sigma;
+        if (q.pair == HOOMD_PAIR_LJ) {
+            const double sr2 = S.sig2 / S.rc2;
+            const double s6 = sr2 * sr2 * sr2;
+            S.shift = 4.0 * q.eps * (s6 * s6 - s6);
+        } else if (q.pair == HOOMD_PAIR_WCA) {
+            S.shift = -q.eps;
+        }
+        S.dpd_A = q.dpd_A;
+        S.dpd_gamma = q.dpd_gamma;
+        S.dpd_sigma = std::sqrt(2.0 * q.dpd_gamma * q.dpd_kT);
+        S.dpd_rc = q.r_cut;
+        S.dpd_inv_rc = q.r_cut > 0 ? 1.0 / q.r_cut : 0.0;
+        S.dpd_inv_sqrt_dt = 1.0 / std::sqrt(q.dt);
+        S.dpd_seed = q.dpd_seed;
+        S.fene_K = q.fene_K;
+        S.fene_R02 = q.fene_R0 * q.fene_R0;
+        S.wca_rc2 = std::pow(2.0, 1.0 / 3.0) * S.sig2;
+        S.dt = q.dt;
+        S.hdt = 0.5 * q.dt;
+        const int64_t ncell = (int64_t)S.bins[0] * S.bins[1] * S.bins[2];
+        // capacity of a cell: twice the mean occupancy plus a margin
+        if (q.cell_cap > 0) {
+            Lo.cell_cap = std::max(Lo.cell_cap, q.cell_cap);
+        } else {
+            const double mean = (double)std::max<int64_t>(b.n_cap, 1) / (double)ncell;
+            int cc = (int)std::ceil((2.0 * mean + 16.0) / 8.0) * 8;
+            Lo.cell_cap = std::max(Lo.cell_cap, std::min(cc, 128));
+        }
+        Lo.sys.push_back(S);
+        row += b.n_cap;
+        tile += ceil_div(b.n_local, kTile);
+        tile_all += ceil_div(b.n_cap, kTile);
+        cell += ncell;
+        nl += ceil_div(b.n_local, kTile) * kTile * (int64_t)Lo.nlist_cap;
+        Lo.tpl_host.push_back((int32_t)tile);
+        Lo.tpa_host.push_back((int32_t)tile_all);
+        (void)vol;
+    }
+    Lo.rows = row;
+    Lo.tiles_local = tile;
+    Lo.tiles_all = tile_all;
+    Lo.n_cells = cell;
+    Lo.nlist_entries = nl;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t rows = (size_t)std::max<int64_t>(row, 1);
+    Lo.sysdev = take(sizeof(SysDev) * n_sys);
+    Lo.tpl = take(sizeof(int32_t) * (n_sys + 1));
+    Lo.tpa = take(sizeof(int32_t) * (n_sys + 1));
+    Lo.status = take(sizeof(Status));
+    Lo.flags = take(sizeof(int32_t) * 8);
+    Lo.thermo = take(sizeof(double) * 4 * n_sys);
+    Lo.thermo_log = take(sizeof(double) * 5 * (size_t)n_sys * kLogRows);
+    Lo.partials = take(sizeof(double) * 3 * (size_t)std::max<int64_t>(tile, 1) * 64);
+    Lo.pos_alt = take(sizeof(double4) * rows);
+    Lo.vel_alt = take(sizeof(double4) * rows);
+    Lo.xbuild = take(sizeof(double4) * rows);
+    Lo.nlist = take(sizeof(int32_t) * (size_t)std::max<int64_t>(nl, 1));
+    Lo.nn = take(sizeof(int32_t) * rows);
+    Lo.cell_count = take(sizeof(int32_t) * (size_t)cell);
+    Lo.cell_size = take(sizeof(int32_t) * (size_t)cell);
+    Lo.cell_idx = take(sizeof(int32_t) * (size_t)cell * Lo.cell_cap);
+    Lo.rtag = take(sizeof(int32_t) * rows);
+    Lo.partners = take(sizeof(int32_t) * rows * std::max(Lo.bond_cap, 1));
+    Lo.sort_ws = take(sort_workspace_bytes((int64_t)rows));
+    Lo.ghost_ws = take(ghost_workspace_bytes((int64_t)rows, n_sys));
+    Lo.total = off;
+    return Lo;
+}
+
+}  // namespace
+
+struct hoomd_ctx {
+    hipStream_t stream;
+    int n_sys;
+    std::vector<hoomd_params> prm;
+    std::vector<hoomd_box> box;
+    hoomd_arrays arr;
+    char *ws;
+    Layout lay;
+    LaunchCtx L;
+    SortBuffers sortb;
+    GhostBuffers ghostb;
+    int mixed;
+    int pair_uniform;  // common Pair of all systems, or -1
+    bool built;        // a neighbour list exists for the current rows
+    int tpp_nlist, block_nlist, tpp_force, block_force;
+    int last_log_rows;
+    uint64_t steps_done;
+    // phase timing (hoomd_profile)
+    bool profiling;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used;
+    std::vector<std::pair<size_t, size_t>> ev_force, ev_rebuild;
+    ~hoomd_ctx()
+    {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+template <typename T> T *ws_ptr(hoomd_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+void default_tuning(hoomd_ctx *c)
+{
+    // neighbours per particle and particles per CU decide the lane count;
+    // the autotuner refines these on the live state
+    const double per_cu = (double)c->lay.tiles_local * 64.0 / 256.0;
+    c->tpp_nlist = per_cu > 4096 ? 4 : 8;
+    c->tpp_force = per_cu > 4096 ? 2 : (per_cu > 512 ? 4 : 8);
+    c->block_nlist = 256;
+    c->block_force = 256;
+    if (c->prm[0].tpp_nlist > 0) c->tpp_nlist = c->prm[0].tpp_nlist;
+    if (c->prm[0].tpp_force > 0) c->tpp_force = c->prm[0].tpp_force;
+    if (c->prm[0].block_nlist > 0) c->block_nlist = c->prm[0].block_nlist;
+    if (c->prm[0].block_force > 0) c->block_force = c->prm[0].block_force;
+}
+
+bool pow2_le(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
+
+// Record the next pooled event on the stream when profiling; returns its
+// index (unused otherwise).
+size_t mark(hoomd_ctx *c)
+{
+    if (!c->profiling) return 0;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            c->profiling = false;
+            return 0;
+        }
+        c->ev_pool.push_back(e);
+    }
+    const size_t k = c->ev_used++;
+    if (hipEventRecord(c->ev_pool[k], c->stream) != hipSuccess) c->profiling = false;
+    return k;
+}
+
+int32_t *flag_ptr(hoomd_ctx *c, int k) { return ws_ptr<int32_t>(c, c->lay.flags) + k; }
+
+// Queue the rebuild sequence: bin -> per-cell sort -> neighbour rows.  Every
+// kernel returns at once when *flag is clear.
+void queue_rebuild(hoomd_ctx *c, const double4 *pos, const int32_t *tag, int32_t *flag)
+{
+    c->L.flag = flag;
+    launch_bin(c->L, pos);
+    launch_cell_sort(c->L);
+    launch_nlist(c->L, pos, tag, c->tpp_nlist, c->block_nlist);
+}
+
+ForceLaunch base_force(hoomd_ctx *c)
+{
+    ForceLaunch F{};
+    F.tag = c->arr.tag;
+    F.force = c->arr.force;
+    F.mixed = c->mixed;
+    F.pair = c->pair_uniform;
+    return F;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hoomd_workspace_bytes(const hoomd_params *params, int32_t n_sys, const hoomd_box *boxes)
+{
+    if (!valid(params, n_sys, boxes)) return 0;
+    return make_layout(params, n_sys, boxes).total;
+}
+
+int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const hoomd_box *boxes,
+               const hoomd_arrays *arrays, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!out || !arrays || !workspace) return HOOMD_E_ARG;
+    *out = nullptr;
+    if (!valid(params, n_sys, boxes)) return HOOMD_E_ARG;
+    if (!arrays->pos || !arrays->vel || !arrays->force || !arrays->tag) return HOOMD_E_ARG;
+    Layout lay = make_layout(params, n_sys, boxes);
+    if (workspace_bytes < lay.total) return HOOMD_E_WORKSPACE;
+    int64_t nb_total = 0;
+    for (int s = 0; s < n_sys; ++s) nb_total += boxes[s].n_bonds;
+    if (nb_total > 0 && !arrays->bonds) return HOOMD_E_ARG;
+
+    hoomd_ctx *c = new hoomd_ctx();
+    c->stream = (hipStream_t)stream;
+    c->n_sys = n_sys;
+    c->prm.assign(params, params + n_sys);
+    c->box.assign(boxes, boxes + n_sys);
+    c->arr = *arrays;
+    c->ws = (char *)workspace;
+    c->lay = lay;
+    c->mixed = params[0].precision == HOOMD_MIXED;
+    c->pair_uniform = params[0].pair;
+    for (int s = 1; s < n_sys; ++s)
+        if (params[s].pair != params[0].pair) c->pair_uniform = -1;
+    if (c->pair_uniform < 0) {
+        delete c;
+        return HOOMD_E_ARG;  // mixed potentials in one context are not supported
+    }
+    c->built = false;
+    c->last_log_rows = 0;
+    c->steps_done = 0;
+
+    LaunchCtx &L = c->L;
+    L.stream = c->stream;
+    L.n_sys = n_sys;
+    L.sys = ws_ptr<SysDev>(c, lay.sysdev);
+    L.tprefix_local = ws_ptr<int32_t>(c, lay.tpl);
+    L.tprefix_all = ws_ptr<int32_t>(c, lay.tpa);
+    L.tiles_local = (int)lay.tiles_local;
+    L.tiles_all = (int)lay.tiles_all;
+    L.n_cells = lay.n_cells;
+    L.cell_cap = lay.cell_cap;
+    L.cell_count = ws_ptr<int32_t>(c, lay.cell_count);
+    L.cell_size = ws_ptr<int32_t>(c, lay.cell_size);
+    L.cell_idx = ws_ptr<int32_t>(c, lay.cell_idx);
+    L.nlist = ws_ptr<int32_t>(c, lay.nlist);
+    L.nn = ws_ptr<int32_t>(c, lay.nn);
+    L.nlist_cap = lay.nlist_cap;
+    L.xbuild = ws_ptr<double4>(c, lay.xbuild);
+    L.partners = ws_ptr<int32_t>(c, lay.partners);
+    L.rtag = ws_ptr<int32_t>(c, lay.rtag);
+    L.has_bonds = nb_total > 0;
+    L.flag = flag_ptr(c, 0);
+    L.build_count = flag_ptr(c, 4);
+    L.status = ws_ptr<Status>(c, lay.status);
+    L.partials = ws_ptr<double>(c, lay.partials);
+    L.thermo = ws_ptr<double>(c, lay.thermo);
+    L.thermo_log = ws_ptr<double>(c, lay.thermo_log);
+    c->sortb = make_sort_buffers(c->ws + lay.sort_ws, lay.rows);
+    c->ghostb = make_ghost_buffers(c->ws + lay.ghost_ws, lay.rows, n_sys);
+    default_tuning(c);
+    if (!pow2_le(c->tpp_nlist, 64) || !pow2_le(c->tpp_force, 32) || c->block_nlist % 64 ||
+        c->block_force % 64 || c->block_nlist < 64 || c->block_force < 64 ||
+        c->block_nlist > 1024 || c->block_force > 256) {
+        delete c;
+        return HOOMD_E_ARG;
+    }
+
+    // descriptors, prefixes, cleared counters (synchronous: init is not hot)
+    hipError_t e = hipSuccess;
+    e = hipMemcpy(c->ws + lay.sysdev, lay.sys.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpl, lay.tpl_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpa, lay.tpa_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->ws + lay.status, 0, sizeof(Status));
+    if (e == hipSuccess) e = hipMemset(c->ws + lay.flags, 0, sizeof(int32_t) * 8);
+    if (e == hipSuccess) e = hipMemset(c->ws + lay.cell_count, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(lay.n_cells, 1));
+    if (e == hipSuccess) e = hipMemset(c->ws + lay.thermo, 0, sizeof(double) * 4 * n_sys);
+    // bond partner rows by tag (built on the host from the caller's table)
+    if (e == hipSuccess && lay.bond_cap > 0) {
+        std::vector<int32_t> rows((size_t)lay.rows * lay.bond_cap, -1);
+        std::vector<int32_t> pairs;
+        // bonded systems index partner rows by tag: tags must be 0..n-1
+        {
+            std::vector<int32_t> tags((size_t)lay.rows);
+            e = hipMemcpy(tags.data(), arrays->tag, sizeof(int32_t) * lay.rows, hipMemcpyDeviceToHost);
+            for (int s = 0; s < n_sys && e == hipSuccess; ++s) {
+                std::vector<char> seen((size_t)boxes[s].n_local, 0);
+                for (int64_t r = 0; r < boxes[s].n_local; ++r) {
+                    const int32_t t = tags[(size_t)(lay.sys[s].row0 + r)];
+                    if (t < 0 || t >= boxes[s].n_local || seen[(size_t)t]) {
+                        e = hipErrorInvalidValue;
+                        break;
+                    }
+                    seen[(size_t)t] = 1;
+                }
+            }
+        }
+        int64_t b0 = 0;
+        for (int s = 0; s < n_sys && e == hipSuccess; ++s) {
+            const int64_t nb = boxes[s].n_bonds;
+            if (nb > 0) {
+                pairs.resize((size_t)nb * 2);
+                e = hipMemcpy(pairs.data(), arrays->bonds + 2 * b0, sizeof(int32_t) * 2 * nb, hipMemcpyDeviceToHost);
+                for (int64_t k = 0; k < nb && e == hipSuccess; ++k) {
+                    const int32_t ta = pairs[2 * k], tb = pairs[2 * k + 1];
+                    if (ta < 0 || tb < 0 || ta >= boxes[s].n_local || tb >= boxes[s].n_local || ta == tb) {
+                        e = hipErrorInvalidValue;
+                        break;
+                    }
+                    for (int side = 0; side < 2; ++side) {
+                        const int32_t me = side ? tb : ta, other = side ? ta : tb;
+                        int32_t *slot = &rows[(size_t)(lay.sys[s].row0 + me) * lay.bond_cap];
+                        int q = 0;
+                        while (q < params[s].bond_cap && slot[q] >= 0) ++q;
+                        if (q == params[s].bond_cap) {
+                            e = hipErrorInvalidValue;
+                            break;
+                        }
+                        slot[q] = other;
+                    }
+                }
+            }
+            b0 += nb;
+        }
+        if (e == hipSuccess)
+            e = hipMemcpy(c->ws + lay.partners, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice);
+        if (e == hipErrorInvalidValue) {
+            delete c;
+            return HOOMD_E_ARG;
+        }
+    }
+    if (e != hipSuccess) {
+        delete c;
+        return HOOMD_E_DEVICE;
+    }
+    if (lay.bond_cap > 0) launch_rtag(c->L, c->arr.tag);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        delete c;
+        return HOOMD_E_DEVICE;
+    }
+    *out = c;
+    return HOOMD_OK;
+}
+
+void hoomd_destroy(hoomd_ctx *ctx) { delete ctx; }
+
+int build_nlist(hoomd_ctx *c, int32_t force_rebuild)
+{
+    if (!c) return HOOMD_E_ARG;
+    int32_t *flag = flag_ptr(c, 2);
+    const double4 *pos = reinterpret_cast<const double4 *>(c->arr.pos);
+    if (force_rebuild || !c->built) {
+        launch_set_flag(c->L, flag, 1);
+    } else {
+        launch_set_flag(c->L, flag, 0);
+        launch_disp_check(c->L, pos, flag);
+    }
+    queue_rebuild(c, pos, c->arr.tag, flag);
+    c->built = true;
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
+}
+
+int compute_forces(hoomd_ctx *c, uint64_t timestep, uint32_t flags)
+{
+    if (!c) return HOOMD_E_ARG;
+    int rc = build_nlist(c, 0);
+    if (rc) return rc;
+    ForceLaunch F = base_force(c);
+    F.pos = reinterpret_cast<const double4 *>(c->arr.pos);
+    F.vel = reinterpret_cast<const double4 *>(c->arr.vel);
+    F.vel_out = reinterpret_cast<double4 *>(c->arr.vel);
+    F.timestep = (uint32_t)timestep;
+    F.mode = MODE_FORCE;
+    F.log = flags != 0;
+    F.energy = (flags & HOOMD_ENERGY) ? 1 : 0;
+    launch_force(c->L, F, c->tpp_force, c->block_force);
+    if (F.log) launch_thermo_reduce(c->L, c->tpp_force, -1, (double)timestep);
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
+}
+
+int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
+{
+    if (!c || n_steps < 0) return HOOMD_E_ARG;
+    if (n_steps == 0) return HOOMD_OK;
+    for (int s = 0; s < c->n_sys; ++s)
+        if (c->lay.sys[s].n_total != c->lay.sys[s].n_local || !c->box[s].periodic[0] ||
+            !c->box[s].periodic[1] || !c->box[s].periodic[2])
+            return HOOMD_E_STATE;  // stepping a subdomain needs particle migration
+    int rc = build_nlist(c, 0);
+    if (rc) return rc;
+
+    const bool dpd = c->pair_uniform == PAIR_DPD;
+    double4 *P[2] = {reinterpret_cast<double4 *>(c->arr.pos), ws_ptr<double4>(c, c->lay.pos_alt)};
+    double4 *V[2] = {reinterpret_cast<double4 *>(c->arr.vel), ws_ptr<double4>(c, c->lay.vel_alt)};
+    int32_t *tag = c->arr.tag;
+    int pc = 0, vc = 0;
+    int log_row = 0;
+    const int sort_period = c->prm[0].sort_period;
+    for (int32_t s = 0; s <= n_steps; ++s) {
+        const uint64_t t = t0 + (uint64_t)s;
+        ForceLaunch F = base_force(c);
+        F.pos = P[pc];
+        F.pos_out = P[pc ^ 1];
+        F.vel = V[vc];
+        F.vel_out = dpd ? V[vc ^ 1] : V[vc];
+        F.tag = tag;
+        F.timestep = (uint32_t)t;
+        F.mode = s == 0 ? MODE_FIRST : (s == n_steps ? MODE_LAST : MODE_MID);
+        F.flag_set = F.mode == MODE_LAST ? nullptr : flag_ptr(c, s & 1);
+        F.flag_clear = F.mode == MODE_LAST ? nullptr : flag_ptr(c, (s + 1) & 1);
+        F.log = log_every > 0 && (s % log_every == 0 || s == n_steps);
+        F.energy = F.mode == MODE_LAST ? 1 : 0;
+        if (F.mode == MODE_LAST) F.log = F.log || log_every > 0;
+        const size_t e0 = mark(c);
+        launch_force(c->L, F, c->tpp_force, c->block_force);
+        if (c->profiling) c->ev_force.emplace_back(e0, mark(c));
+        if (F.log) {
+            launch_thermo_reduce(c->L, c->tpp_force, log_row < kLogRows ? log_row : -1, (double)t);
+            ++log_row;
+        }
+        if (dpd) vc ^= 1;
+        if (F.mode == MODE_LAST) break;
+        pc ^= 1;
+        int32_t *flag = flag_ptr(c, s & 1);
+        if (sort_period > 0 && ((t + 1) % (uint64_t)sort_period) == 0) {
+            rc = queue_morton_sort(c->L, c->sortb, P[pc], V[vc], tag, P[pc ^ 1], V[vc ^ 1]);
+            if (rc) return HOOMD_E_DEVICE;
+            if (c->lay.bond_cap > 0) launch_rtag(c->L, tag);
+            launch_set_flag(c->L, flag, 1);
+        }
+        const size_t r0 = mark(c);
+        queue_rebuild(c, P[pc], tag, flag);
+        if (c->profiling) c->ev_rebuild.emplace_back(r0, mark(c));
+    }
+    // leave the final state in the caller's arrays
+    if (pc == 1)
+        HIP_OK(hipMemcpyAsync(c->arr.pos, P[1], sizeof(double4) * c->lay.rows, hipMemcpyDeviceToDevice, c->stream));
+    if (vc == 1)
+        HIP_OK(hipMemcpyAsync(c->arr.vel, V[1], sizeof(double4) * c->lay.rows, hipMemcpyDeviceToDevice, c->stream));
+    c->last_log_rows = std::min(log_row, kLogRows);
+    c->steps_done += (uint64_t)n_steps;
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
+}
+
+int pack_ghosts(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, int32_t mode, uint32_t fields,
+                void *send, int64_t send_cap, int32_t *counts26, int32_t *offsets26)
+{
+    if (!c || !sd || sys < 0 || sys >= c->n_sys || !counts26 || !offsets26) return HOOMD_E_ARG;
+    if (mode != HOOMD_GHOST_SELECT && mode != HOOMD_GHOST_UPDATE) return HOOMD_E_ARG;
+    if ((fields & ~7u) || send_cap < 0 || (send_cap > 0 && !send)) return HOOMD_E_ARG;
+    if (!(sd->width >= 0)) return HOOMD_E_ARG;
+    GhostArgs g{};
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = sd->lo[a];
+        g.hi[a] = sd->hi[a];
+    }
+    g.width = sd->width;
+    g.row0 = c->lay.sys[sys].row0;
+    g.n_local = c->lay.sys[sys].n_local;
+    g.fields = fields;
+    g.send = send;
+    g.send_cap = send_cap;
+    g.counts = counts26;
+    g.offsets = offsets26;
+    g.pos = reinterpret_cast<const double4 *>(c->arr.pos);
+    g.vel = reinterpret_cast<const double4 *>(c->arr.vel);
+    g.tag = c->arr.tag;
+    g.status = c->L.status;
+    g.mask = c->ghostb.mask + c->lay.sys[sys].row0;
+    g.list = c->ghostb.list + (int64_t)kGhostPerRow * c->lay.sys[sys].row0;
+    g.list_cap = (int64_t)kGhostPerRow * c->box[sys].n_cap;
+    g.total = c->ghostb.totals + sys;
+    int rc = mode == HOOMD_GHOST_SELECT ? queue_ghost_select(c->stream, c->ghostb, g)
+                                        : queue_ghost_update(c->stream, c->ghostb, g);
+    return rc ? HOOMD_E_DEVICE : HOOMD_OK;
+}
+
+int unpack_ghosts(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, uint32_t fields,
+                  int32_t mode, const double *box_L)
+{
+    if (!c || sys < 0 || sys >= c->n_sys || n_recv < 0 || (n_recv > 0 && !recv) || !box_L)
+        return HOOMD_E_ARG;
+    if (mode != HOOMD_GHOST_SELECT && mode != HOOMD_GHOST_UPDATE) return HOOMD_E_ARG;
+    if ((fields & ~7u) || !(fields & HOOMD_FIELD_POS)) return HOOMD_E_ARG;
+    SysDev &S = c->lay.sys[sys];
+    if (S.bond_cap > 0) return HOOMD_E_STATE;  // bonded ghosts are not supported
+    if (mode == HOOMD_GHOST_UPDATE && n_recv != S.n_total - S.n_local) return HOOMD_E_STATE;
+    if (S.n_local + n_recv > c->box[sys].n_cap) {
+        return HOOMD_E_GHOST_OVERFLOW;
+    }
+    UnpackArgs u{};
+    for (int a = 0; a < 3; ++a) {
+        u.box_L[a] = box_L[a];
+        u.center[a] = S.lo[a] + 0.5 * S.L[a];
+    }
+    u.first = S.row0 + S.n_local;
+    u.n = n_recv;
+    u.fields = fields;
+    u.recv = recv;
+    u.pos = reinterpret_cast<double4 *>(c->arr.pos);
+    u.vel = reinterpret_cast<double4 *>(c->arr.vel);
+    u.tag = c->arr.tag;
+    if (queue_ghost_unpack(c->stream, u)) return HOOMD_E_DEVICE;
+    if (mode == HOOMD_GHOST_SELECT) {
+        S.n_total = (int32_t)(S.n_local + n_recv);
+        HIP_OK(hipMemcpyAsync(ws_ptr<SysDev>(c, c->lay.sysdev) + sys, &S, sizeof(SysDev),
+                              hipMemcpyHostToDevice, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));  // the copy reads host memory that later calls modify
+        c->built = false;
+    }
+    return HOOMD_OK;
+}
+
+int hoomd_thermo(hoomd_ctx *c, double *out)
+{
+    if (!c || !out) return HOOMD_E_ARG;
+    HIP_OK(hipMemcpyAsync(out, c->ws + c->lay.thermo, sizeof(double) * 4 * c->n_sys, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return HOOMD_OK;
+}
+
+int hoomd_thermo_log(hoomd_ctx *c, double *out, int32_t max_rows, int32_t *rows)
+{
+    if (!c || !out || !rows || max_rows < 0) return HOOMD_E_ARG;
+    const int n = std::min(max_rows, c->last_log_rows);
+    if (n > 0)
+        HIP_OK(hipMemcpyAsync(out, c->ws + c->lay.thermo_log, sizeof(double) * 5 * c->n_sys * n,
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    *rows = n;
+    return HOOMD_OK;
+}
+
+int hoomd_sync_status(hoomd_ctx *c, int64_t *required)
+{
+    if (!c) return HOOMD_E_ARG;
+    Status st{};
+    HIP_OK(hipMemcpyAsync(&st, c->ws + c->lay.status, sizeof(Status), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipMemsetAsync(c->ws + c->lay.status, 0, sizeof(Status), c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (required) *required = st.required;
+    return st.code;
+}
+
+int hoomd_build_count(hoomd_ctx *c, int64_t *builds)
+{
+    if (!c || !builds) return HOOMD_E_ARG;
+    int32_t v = 0;
+    HIP_OK(hipMemcpyAsync(&v, flag_ptr(c, 4), sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    *builds = v;
+    return HOOMD_OK;
+}
+
+int hoomd_get_layout(hoomd_ctx *c, int32_t sys, hoomd_layout *out)
+{
+    if (!c || !out || sys < 0 || sys >= c->n_sys) return HOOMD_E_ARG;
+    const SysDev &S = c->lay.sys[sys];
+    out->nlist = c->L.nlist + S.nl0;
+    out->nn = c->L.nn + S.row0;
+    out->cell_idx = c->L.cell_idx + S.cell0 * c->lay.cell_cap;
+    out->cell_size = c->L.cell_size + S.cell0;
+    out->nlist_cap = c->lay.nlist_cap;
+    out->cell_cap = c->lay.cell_cap;
+    for (int a = 0; a < 3; ++a) out->bins[a] = S.bins[a];
+    out->row_offset = S.row0;
+    out->cell_offset = S.cell0;
+    return HOOMD_OK;
+}
+
+}  // extern "C"
+
+// Median of five timed launches of `launch` on the context's stream (ms); a
+// failing timer call gives +inf so the candidate is never chosen.
+template <typename Fn>
+static float median5(hoomd_ctx *c, Fn launch, hipEvent_t e0, hipEvent_t e1)
+{
+    float t[5];
+    launch();  // warm-up
+    for (int k = 0; k < 5; ++k) {
+        bool ok = hipEventRecord(e0, c->stream) == hipSuccess;
+        launch();
+        ok = ok && hipEventRecord(e1, c->stream) == hipSuccess;
+        ok = ok && hipEventSynchronize(e1) == hipSuccess;
+        ok = ok && hipEventElapsedTime(&t[k], e0, e1) == hipSuccess;
+        if (!ok) t[k] = 1e30f;
+    }
+    std::sort(t, t + 5);
+    return t[2];
+}
+
+extern "C" {
+
+int hoomd_autotune(hoomd_ctx *c, int32_t do_tune, hoomd_tuning *out)
+{
+    if (!c) return HOOMD_E_ARG;
+    if (do_tune) {
+        const double4 *pos = reinterpret_cast<const double4 *>(c->arr.pos);
+        int32_t *flag = flag_ptr(c, 2);
+        launch_set_flag(c->L, flag, 1);
+        c->L.flag = flag;
+        launch_bin(c->L, pos);
+        launch_cell_sort(c->L);
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        // neighbour list: lanes per particle x block size
+        float best = 1e30f;
+        int bw = c->tpp_nlist, bb = c->block_nlist;
+        for (int w = 1; w <= 64; w <<= 1)
+            for (int b = 64; b <= 512; b <<= 1) {
+                const float t = median5(c, [&] { launch_nlist(c->L, pos, c->arr.tag, w, b); }, e0, e1);
+                if (t < best) { best = t; bw = w; bb = b; }
+            }
+        c->tpp_nlist = bw;
+        c->block_nlist = bb;
+        launch_nlist(c->L, pos, c->arr.tag, bw, bb);
+        c->built = true;
+        // forces
+        best = 1e30f;
+        bw = c->tpp_force;
+        bb = c->block_force;
+        ForceLaunch F = base_force(c);
+        F.pos = pos;
+        F.vel = reinterpret_cast<const double4 *>(c->arr.vel);
+        F.vel_out = reinterpret_cast<double4 *>(c->arr.vel);
+        F.mode = MODE_FORCE;
+        for (int w = 1; w <= 32; w <<= 1)
+            for (int b = 64; b <= 256; b <<= 1) {
+                const float t = median5(c, [&] { launch_force(c->L, F, w, b); }, e0, e1);
+                if (t < best) { best = t; bw = w; bb = b; }
+            }
+        c->tpp_force = bw;
+        c->block_force = bb;
+        HIP_OK(hipEventDestroy(e0));
+        HIP_OK(hipEventDestroy(e1));
+        HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    if (out) {
+        out->tpp_nlist = c->tpp_nlist;
+        out->block_nlist = c->block_nlist;
+        out->tpp_force = c->tpp_force;
+        out->block_force = c->block_force;
+    }
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
+}
+
+int hoomd_profile(hoomd_ctx *c, int32_t mode, hoomd_profile_t *out)
+{
+    if (!c || mode < 0 || mode > 2) return HOOMD_E_ARG;
+    if (mode == 1) {
+        c->profiling = true;
+        c->ev_used = 0;
+        c->ev_force.clear();
+        c->ev_rebuild.clear();
+        return HOOMD_OK;
+    }
+    if (mode == 0) {
+        c->profiling = false;
+        return HOOMD_OK;
+    }
+    if (!out) return HOOMD_E_ARG;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    auto total = [&](const std::vector<std::pair<size_t, size_t>> &v, double &ms) {
+        ms = 0.0;
+        for (const auto &pr : v) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, c->ev_pool[pr.first], c->ev_pool[pr.second]) != hipSuccess) return false;
+            ms += t;
+        }
+        return true;
+    };
+    if (!total(c->ev_force, out->force_ms) || !total(c->ev_rebuild, out->rebuild_ms)) return HOOMD_E_DEVICE;
+    out->force_launches = (int64_t)c->ev_force.size();
+    out->rebuild_launches = (int64_t)c->ev_rebuild.size();
+    return HOOMD_OK;
+}
+
+const char *hoomd_strerror(int code)
+{
+    switch (code) {
+    case HOOMD_OK: return "ok";
+    case HOOMD_E_ARG: return "invalid argument";
+    case HOOMD_E_DEVICE: return "HIP runtime error";
+    case HOOMD_E_WORKSPACE: return "workspace too small";
+    case HOOMD_E_STATE: return "call not valid in the current state";
+    case HOOMD_E_NLIST_OVERFLOW: return "neighbour row capacity exceeded";
+    case HOOMD_E_CELL_OVERFLOW: return "cell capacity exceeded";
+    case HOOMD_E_GHOST_OVERFLOW: return "ghost capacity exceeded";
+    case HOOMD_E_BOND_STRETCH: return "bond stretched beyond R0";
+    case HOOMD_E_NAN: return "non-finite force";
+    case HOOMD_E_DANGEROUS_BUILD: return "dangerous neighbour-list build";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

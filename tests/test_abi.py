@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+the header declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hoomd_mi355x.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set()
+    for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([A-Za-z_]\w*)\s*\(", txt, flags=re.M):
+        name = m.group(1)
+        if name not in ("if", "while", "sizeof", "defined"):
+            names.add(name)
+    return names
+
+
+@pytest.fixture(scope="module")
+def hlib():
+    from paper_1412_3387_amd import binding, build
+    if build.needs_build():
+        build.build()
+    return binding.lib()
+
+
+def test_header_declares_the_five_entry_points():
+    names = declared_functions()
+    for n in ("hoomd_init", "build_nlist", "compute_forces", "step", "pack_ghosts"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(hlib):
+    from paper_1412_3387_amd import binding
+    names = declared_functions()
+    assert names == set(binding.EXPORTS)
+    for n in names:
+        assert hasattr(hlib, n), n
+
+
+def test_strerror_and_workspace_sizing(hlib):
+    from paper_1412_3387_amd import binding as B
+    assert hlib.hoomd_strerror(0) == b"ok"
+    assert hlib.hoomd_strerror(5) == b"neighbour row capacity exceeded"
+    p = B.ModelParams(precision=B.MIXED).to_c(0.8442)
+    box = B.Box()
+    for a in range(3):
+        box.L[a] = 16.796
+        box.periodic[a] = 1
+    box.n_local = box.n_cap = 4000
+    n1 = hlib.hoomd_workspace_bytes(C.byref(p), 1, C.byref(box))
+    assert n1 > 4000 * 4 * p.nlist_cap
+    box.n_local = box.n_cap = 8000
+    assert hlib.hoomd_workspace_bytes(C.byref(p), 1, C.byref(box)) > n1
+    # a box too small for a unique minimum image is rejected
+    for a in range(3):
+        box.L[a] = 5.0
+    assert hlib.hoomd_workspace_bytes(C.byref(p), 1, C.byref(box)) == 0
+
+
+def test_init_rejects_bad_arguments_without_device_work(hlib):
+    from paper_1412_3387_amd import binding as B
+    p = B.ModelParams(precision=B.MIXED).to_c(0.8442)
+    box = B.Box()
+    for a in range(3):
+        box.L[a] = 16.796
+        box.periodic[a] = 1
+    box.n_local = box.n_cap = 4000
+    arr = B.Arrays(None, None, None, None, None)
+    h = C.c_void_p()
+    assert hlib.hoomd_init(C.byref(h), C.byref(p), 1, C.byref(box), C.byref(arr), 1, 1 << 30, None) == 1
+    p.precision = 7
+    arr = B.Arrays(1, 1, 1, 1, None)
+    assert hlib.hoomd_init(C.byref(h), C.byref(p), 1, C.byref(box), C.byref(arr), 1, 1 << 30, None) == 1
+    p.precision = B.MIXED
+    assert hlib.hoomd_init(C.byref(h), C.byref(p), 1, C.byref(box), C.byref(arr), 1, 16, None) == 3
+    assert hlib.build_nlist(None, 1) == 1 and hlib.step(None, 0, 1, 0) == 1
+    assert hlib.compute_forces(None, 0, 0) == 1

@@ -1,0 +1,126 @@
+"""GPU parity: LJ, DPD and FENE+WCA forces, energies and virials against the
+oracle, in FP64 (1e-12 of the RMS force) and mixed precision (1e-5)."""
+import numpy as np
+import pytest
+
+from paper_1412_3387_amd import inputs
+from tests.gpu_helpers import LJ, frel
+
+pytestmark = pytest.mark.gpu
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1412_3387_amd import binding
+    binding.lib()
+    return binding
+
+
+def _forces(B, sys_, p, timestep=0, flags=1):
+    ctx = B.Context([p], [dict(pos=sys_.pos, vel=sys_.vel, L=sys_.L, bonds=sys_.bonds, tag=sys_.tag)])
+    ctx.compute_forces(timestep, flags)
+    ctx.check()
+    x, v, f, tag = ctx.host_state()
+    th = ctx.thermo()[0]
+    return f, th, ctx
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("w", [1, 2, 4, 8, 16, 32])
+def test_lj_forces_small(orc, B, prec, w):
+    s = inputs.lj_small()
+    p = B.ModelParams(precision=prec, tpp_force=w, block_force=128)
+    f, th, _ = _forces(B, s, p)
+    F, u, wv, nc = orc.pair_forces("lj", s.pos, s.L, LJ)
+    assert frel(f[:, :3], F) <= TOL[prec]
+    etol = 1e-12 if prec == 0 else 1e-6
+    assert np.max(np.abs(f[:, 3] - u)) <= etol * np.max(np.abs(u)) + 1e-12
+    ref = orc.thermo(s.vel, u, wv)
+    assert abs(th[0] - ref[0]) <= 1e-12 * abs(ref[0])
+    assert abs(th[1] - ref[1]) <= (1e-12 if prec == 0 else 1e-6) * abs(ref[1])
+    assert abs(th[2] - ref[2]) <= (1e-12 if prec == 0 else 1e-6) * abs(ref[2])
+    assert abs(th[3] - 1.2) < 1e-12
+
+
+def test_lj_forces_newton_third_law(B):
+    s = inputs.lj_fluid(20000, 9, 10)
+    f, th, _ = _forces(B, s, B.ModelParams(precision=0))
+    frms = np.sqrt(np.mean(np.sum(f[:, :3] ** 2, axis=1)))
+    assert np.all(np.abs(f[:, :3].sum(axis=0)) < 20000 * 1e-15 * frms * 10)
+
+
+def test_lj_dimer_across_boundary(orc, B):
+    L = np.array([8.0, 8.0, 8.0])
+    pos = np.array([[0.3, 4.0, 4.0], [7.2, 4.0, 4.0]])
+    s = inputs.System(pos=pos, vel=np.zeros_like(pos), tag=np.arange(2, dtype=np.int32), L=L)
+    f, th, _ = _forces(B, s, B.ModelParams(precision=0))
+    F, u, _, _ = orc.pair_forces("lj", pos, L, LJ)
+    assert np.allclose(f[:, :3], F, rtol=1e-14, atol=0) and f[0, 0] > 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lj_forces_bulk_sampled(orc, B, prec):
+    """2,000,000 particles (the measured workload): sampled particles against
+    brute force over the whole box."""
+    s = inputs.lj_bulk()
+    f, th, _ = _forces(B, s, B.ModelParams(precision=prec), flags=0)
+    rng = np.random.default_rng(1)
+    which = np.sort(rng.choice(s.n, 256, replace=False))
+    F, u, w, nc = orc.pair_forces("lj", s.pos, s.L, LJ, which=which)
+    fr = np.sqrt(np.mean(np.sum(F * F, axis=1)))
+    err = np.max(np.sqrt(np.sum((f[which, :3] - F) ** 2, axis=1))) / fr
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dpd_forces(orc, B, prec):
+    s = inputs.dpd_fluid(6000, 31, 32)
+    p = B.ModelParams(precision=prec, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02,
+                      dpd_A=25.0, dpd_gamma=4.5, dpd_kT=1.0, dpd_seed=33)
+    f, th, _ = _forces(B, s, p, timestep=17)
+    F, u, w, nc = orc.pair_forces("dpd", s.pos, s.L, [25.0, 4.5, 1.0, 1.0, 0.02, 33],
+                                  vel=s.vel, tag=s.tag, timestep=17)
+    assert frel(f[:, :3], F) <= TOL[prec]
+    ref = orc.thermo(s.vel, u, w)
+    assert abs(th[1] - ref[1]) <= 1e-6 * abs(ref[1])
+    # momentum: the random and dissipative pair terms cancel pairwise
+    frms = np.sqrt(np.mean(np.sum(F * F, axis=1)))
+    assert np.all(np.abs(f[:, :3].sum(axis=0)) < (1e-9 if prec == 0 else 1e-3) * frms)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_polymer_forces_kremer_grest(orc, B, prec):
+    """GPU: WCA on non-bonded pairs + FENE+WCA per bond.  Oracle: WCA on all
+    pairs + FENE (the Kremer-Grest definition)."""
+    m = inputs.polymer_melt(60, seed_vel=3)
+    rng = np.random.default_rng(3)
+    m.pos = inputs.wrap(m.pos + rng.uniform(-0.08, 0.08, m.pos.shape), m.L)
+    p = B.ModelParams(precision=prec, pair=B.PAIR_WCA, bond_cap=2, fene_K=30.0, fene_R0=1.5)
+    f, th, _ = _forces(B, m, p)
+    Fp, up, wp, _ = orc.pair_forces("wca", m.pos, m.L, [1.0, 1.0])
+    Fb, ub, wb, ns = orc.bond_forces(m.pos, m.L, m.bonds, with_wca=False)
+    assert ns == 0
+    assert frel(f[:, :3], Fp + Fb) <= TOL[prec]
+    ref = orc.thermo(m.vel, up + ub, wp + wb)
+    assert abs(th[1] - ref[1]) <= (1e-12 if prec == 0 else 1e-6) * abs(ref[1])
+
+
+def test_bond_stretch_is_reported(B):
+    L = np.array([20.0, 20.0, 20.0])
+    pos = np.array([[5.0, 5.0, 5.0], [6.6, 5.0, 5.0]])
+    s = inputs.System(pos=pos, vel=np.zeros_like(pos), tag=np.arange(2, dtype=np.int32), L=L,
+                      bonds=np.array([[0, 1]], dtype=np.int32))
+    p = B.ModelParams(precision=1, pair=B.PAIR_WCA, bond_cap=2)
+    ctx = B.Context([p], [dict(pos=pos, vel=s.vel, L=L, bonds=s.bonds)])
+    ctx.compute_forces(0, 0)
+    assert ctx.sync_status()[0] == 8
+
+
+def test_nan_is_reported(B):
+    s = inputs.lj_fluid(500, 1, 2)
+    pos = s.pos.copy()
+    pos[3] = pos[7]  # coincident pair: infinite force
+    ctx = B.Context([B.ModelParams(precision=0)], [dict(pos=pos, vel=s.vel, L=s.L)])
+    ctx.compute_forces(0, 0)
+    assert ctx.sync_status()[0] == 9

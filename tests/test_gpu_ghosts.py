@@ -1,0 +1,159 @@
+"""GPU parity: ghost selection, packing, the 26-neighbour exchange (as
+device-to-device copies between the 27 subdomains of one box held on one
+GPU) and unpacking, against the oracle's brute-force ghost geometry; then
+local forces of subdomain 0 against forces in the full periodic box."""
+import numpy as np
+import pytest
+
+from paper_1412_3387_amd import inputs
+from tests.gpu_helpers import LJ
+
+pytestmark = pytest.mark.gpu
+W = 2.9
+MARGIN = 0.25
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1412_3387_amd import binding
+    binding.lib()
+    return binding
+
+
+def _dir_to(s_from, s_to, g=3):
+    a = np.array([s_from % g, (s_from // g) % g, s_from // (g * g)])
+    b = np.array([s_to % g, (s_to // g) % g, s_to // (g * g)])
+    d = (b - a + 1) % g - 1
+    k = (d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1)
+    return k if k < 13 else k - 1
+
+
+def _loopback(B, sd, precision=1, update_shift=None):
+    import torch
+    full = sd.full
+    L = full.L
+    systems, params = [], []
+    for s in range(27):
+        loc = sd.local(s)
+        lo = sd.lo(s) - W - MARGIN
+        systems.append(dict(pos=full.pos[loc], vel=full.vel[loc], tag=loc.astype(np.int32),
+                            L=np.full(3, sd.side + 2 * (W + MARGIN)), lo=lo, periodic=(0, 0, 0),
+                            n_cap=len(loc) * 3))
+        params.append(B.ModelParams(precision=precision, nlist_cap=160))
+    ctx = B.Context(params, systems)
+    dev = ctx.device
+    fields = B.FIELD_POS | B.FIELD_TAG
+    cap = 8 * max(ctx.n_local)
+    rec = 32
+    sends, counts, offs = [], [], []
+    for s in range(27):
+        buf = torch.zeros(cap * rec, dtype=torch.uint8, device=dev)
+        cnt = torch.zeros(26, dtype=torch.int32, device=dev)
+        off = torch.zeros(26, dtype=torch.int32, device=dev)
+        ctx.pack_ghosts(s, sd.lo(s), sd.hi(s), W, B.GHOST_SELECT, fields, buf, cap, cnt, off)
+        sends.append(buf)
+        counts.append(cnt)
+        offs.append(off)
+    ctx.check()
+    hc = [c.cpu().numpy() for c in counts]
+    ho = [o.cpu().numpy() for o in offs]
+
+    def gather_recv():
+        pieces = []
+        for s in range(1, 27):
+            d = _dir_to(s, 0)
+            a, n = int(ho[s][d]), int(hc[s][d])
+            pieces.append(sends[s][a * rec:(a + n) * rec])
+        return torch.cat(pieces)
+    recv = gather_recv()
+    n_recv = recv.numel() // rec
+    ctx.unpack_ghosts(0, recv, n_recv, fields, B.GHOST_SELECT, L)
+    ctx.check()
+    out = dict(ctx=ctx, counts=hc, offsets=ho, sends=sends, n_recv=n_recv)
+    if update_shift is not None:
+        # move every local of the other subdomains, re-gather, re-send
+        for s in range(1, 27):
+            o, n = ctx.offsets[s], ctx.n_local[s]
+            ctx.pos[o:o + n, :3] += torch.as_tensor(update_shift, device=dev, dtype=torch.float64)
+            ctx.pack_ghosts(s, sd.lo(s), sd.hi(s), W, B.GHOST_UPDATE, fields, sends[s], cap,
+                            counts[s], offs[s])
+        recv = gather_recv()
+        ctx.unpack_ghosts(0, recv, n_recv, fields, B.GHOST_UPDATE, L)
+        ctx.check()
+    return out
+
+
+@pytest.mark.parametrize("cells", [12, 60])
+def test_ghost_select_pack_exact(orc, B, cells):
+    sd = inputs.lj_subdomain_box(grid=3, cells=cells)
+    r = _loopback(B, sd)
+    for s in (0, 5, 13, 26):
+        loc = sd.local(s)
+        m = orc.ghost_masks(sd.full.pos[loc], sd.lo(s), sd.hi(s), W)
+        cnt, off, idx = orc.ghost_list(m)
+        assert np.array_equal(r["counts"][s], cnt) and np.array_equal(r["offsets"][s], off)
+        buf = r["sends"][s][: len(idx) * 32].cpu().numpy()
+        recs = buf.view(np.float64).reshape(-1, 4)
+        tags = buf.view(np.int32).reshape(-1, 8)[:, 6]
+        assert np.array_equal(tags, loc[idx])
+        assert np.array_equal(recs[:, :3], sd.full.pos[loc[idx]])
+
+
+@pytest.mark.parametrize("cells", [12, 60])
+def test_ghost_receive_set_and_local_forces(orc, B, cells):
+    sd = inputs.lj_subdomain_box(grid=3, cells=cells)
+    r = _loopback(B, sd, precision=0)
+    ctx = r["ctx"]
+    full = sd.full
+    ridx, rimg = orc.ghost_receive(full.pos, sd.owner, 0, full.L, sd.lo(0), sd.hi(0), W)
+    n0 = ctx.n_local[0]
+    assert r["n_recv"] == len(ridx)
+    o = ctx.offsets[0]
+    gpos = ctx.pos[o + n0:o + n0 + r["n_recv"], :3].cpu().numpy()
+    gtag = ctx.tag[o + n0:o + n0 + r["n_recv"]].cpu().numpy()
+    og = np.argsort(gtag)
+    oref = np.argsort(ridx)
+    assert np.array_equal(gtag[og], ridx[oref])
+    assert np.array_equal(gpos[og], rimg[oref])
+    # local forces of subdomain 0 from locals + ghosts equal full-box forces
+    ctx.compute_forces(0, 1)
+    ctx.check()
+    f = ctx.force[o:o + n0, :3].cpu().numpy()
+    loc = sd.local(0)
+    rng = np.random.default_rng(4)
+    pick = np.sort(rng.choice(n0, min(n0, 256), replace=False))
+    F, u, w, nc = orc.pair_forces("lj", full.pos, full.L, LJ, which=loc[pick])
+    fr = np.sqrt(np.mean(np.sum(F * F, axis=1)))
+    assert np.max(np.abs(f[pick] - F)) <= 1e-12 * fr
+
+
+def test_ghost_update_mode(orc, B):
+    sd = inputs.lj_subdomain_box(grid=3, cells=12)
+    shift = np.array([0.013, -0.007, 0.002])
+    r = _loopback(B, sd, update_shift=shift)
+    ctx = r["ctx"]
+    moved = inputs.wrap(sd.full.pos + shift, sd.full.L)
+    # ownership is unchanged by the update: the same particles, new images
+    ridx, rimg = orc.ghost_receive(sd.full.pos, sd.owner, 0, sd.full.L, sd.lo(0), sd.hi(0), W)
+    n0 = ctx.n_local[0]
+    o = ctx.offsets[0]
+    gpos = ctx.pos[o + n0:o + n0 + r["n_recv"], :3].cpu().numpy()
+    gtag = ctx.tag[o + n0:o + n0 + r["n_recv"]].cpu().numpy()
+    og, oref = np.argsort(gtag), np.argsort(ridx)
+    assert np.array_equal(gtag[og], ridx[oref])
+    assert np.allclose(gpos[og], rimg[oref] + shift, atol=1e-12)
+    del moved
+
+
+def test_ghost_overflow_is_reported(B):
+    import torch
+    sd = inputs.lj_subdomain_box(grid=3, cells=12)
+    loc = sd.local(0)
+    p = B.ModelParams(precision=1)
+    ctx = B.Context([p], [dict(pos=sd.full.pos[loc], vel=sd.full.vel[loc], L=sd.full.L)])
+    buf = torch.zeros(10 * 32, dtype=torch.uint8, device=ctx.device)
+    cnt = torch.zeros(26, dtype=torch.int32, device=ctx.device)
+    off = torch.zeros(26, dtype=torch.int32, device=ctx.device)
+    ctx.pack_ghosts(0, sd.lo(0), sd.hi(0), W, B.GHOST_SELECT, B.FIELD_POS | B.FIELD_TAG, buf, 10, cnt, off)
+    code, req = ctx.sync_status()
+    assert code == 7 and req == int(cnt.sum().item())

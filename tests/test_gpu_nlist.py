@@ -1,0 +1,125 @@
+"""GPU parity: cell list and Verlet neighbour list against the oracle
+(bit-exact as index sets), including the degenerate geometries."""
+import numpy as np
+import pytest
+
+from paper_1412_3387_amd import inputs
+from tests.gpu_helpers import neighbor_sets_equal
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1412_3387_amd import binding
+    binding.lib()
+    return binding
+
+
+def _ctx(B, pos, vel, L, **kw):
+    p = B.ModelParams(**kw)
+    return B.Context([p], [dict(pos=pos, vel=vel, L=L)])
+
+
+def test_cell_list_matches_stable_counting_sort(orc, B):
+    s = inputs.lj_small()
+    ctx = _ctx(B, s.pos, s.vel, s.L, precision=B.FP64)
+    ctx.build_nlist(True)
+    ctx.check()
+    bins, size, members = ctx.cells()
+    rb = orc.cell_bins(s.L, 2.9)
+    assert np.array_equal(bins, rb)
+    cell_of, start, idx = orc.cell_list(s.pos, s.L, rb)
+    assert np.array_equal(size, np.diff(start))
+    for c in range(len(size)):
+        assert np.array_equal(members[c], idx[start[c]:start[c + 1]]), c
+
+
+@pytest.mark.parametrize("w", [1, 2, 4, 8, 16, 32, 64])
+def test_neighbor_sets_exact_all_lane_counts(orc, B, w):
+    s = inputs.lj_small()
+    ctx = _ctx(B, s.pos, s.vel, s.L, tpp_nlist=w, block_nlist=256)
+    ctx.build_nlist(True)
+    ctx.check()
+    assert neighbor_sets_equal(orc, ctx, s.pos, s.L, 2.5, 0.4) == []
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 65, 500, 4097])
+def test_neighbor_sets_ragged_sizes(orc, B, n):
+    """Sizes below, at and across tile boundaries; n = 500 gives a 2-cell box."""
+    if n < 500:
+        L = np.array([9.0, 9.0, 9.0])
+        rng = np.random.default_rng(n)
+        pos = rng.uniform(0, 9.0, (n, 3))
+    else:
+        s = inputs.lj_fluid(n, 3, 4)
+        pos, L = s.pos, s.L
+    ctx = _ctx(B, pos, np.zeros_like(pos), L, tpp_nlist=4)
+    ctx.build_nlist(True)
+    ctx.check()
+    assert neighbor_sets_equal(orc, ctx, pos, L, 2.5, 0.4) == []
+    if n == 500:
+        assert list(ctx.layout().bins) == [2, 2, 2]
+
+
+def test_trimer_across_box_edge(orc, B):
+    L = np.array([10.0, 10.0, 10.0])
+    pos = np.array([[0.1, 5.0, 5.0], [9.5, 5.0, 5.0], [9.95, 9.9, 0.05]])
+    ctx = _ctx(B, pos, np.zeros_like(pos), L)
+    ctx.build_nlist(True)
+    nn, rows = ctx.neighbor_rows()
+    assert sorted(rows[0].tolist()) == [1, 2] and sorted(rows[2].tolist()) == [0, 1]
+    assert neighbor_sets_equal(orc, ctx, pos, L, 2.5, 0.4) == []
+
+
+def test_empty_cells_and_a_crowded_cell(orc, B):
+    L = np.array([30.0, 30.0, 30.0])
+    rng = np.random.default_rng(1)
+    pos = np.concatenate([rng.uniform(1.0, 2.5, (40, 3)), rng.uniform(15, 16, (5, 3))])
+    ctx = _ctx(B, pos, np.zeros_like(pos), L, cell_cap=64, nlist_cap=64)
+    ctx.build_nlist(True)
+    ctx.check()
+    assert neighbor_sets_equal(orc, ctx, pos, L, 2.5, 0.4) == []
+
+
+def test_cell_overflow_is_reported(B):
+    L = np.array([30.0, 30.0, 30.0])
+    rng = np.random.default_rng(2)
+    pos = rng.uniform(1.0, 2.5, (40, 3))
+    ctx = _ctx(B, pos, np.zeros_like(pos), L, cell_cap=16, nlist_cap=64)
+    ctx.build_nlist(True)
+    code, req = ctx.sync_status()
+    assert code == 6 and req == 40
+
+
+def test_row_capacity_edge(orc, B):
+    s = inputs.lj_fluid(2000, 5, 6)
+    off, _ = orc.neighbors(s.pos, s.L, 2.5, 0.4)
+    mx = int(np.diff(off).max())
+    ctx = _ctx(B, s.pos, s.vel, s.L, nlist_cap=mx)
+    ctx.build_nlist(True)
+    assert ctx.sync_status() == (0, 0)
+    assert neighbor_sets_equal(orc, ctx, s.pos, s.L, 2.5, 0.4) == []
+    ctx = _ctx(B, s.pos, s.vel, s.L, nlist_cap=mx - 1)
+    ctx.build_nlist(True)
+    assert ctx.sync_status() == (5, mx)
+
+
+def test_exclusions_of_bonded_partners(orc, B):
+    m = inputs.polymer_melt(20, seed_vel=4)
+    p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_WCA, bond_cap=2)
+    ctx = B.Context([p], [dict(pos=m.pos, vel=m.vel, L=m.L, bonds=m.bonds)])
+    ctx.build_nlist(True)
+    ctx.check()
+    assert neighbor_sets_equal(orc, ctx, m.pos, m.L, 2 ** (1 / 6), 0.4, bonds=m.bonds) == []
+
+
+def test_bulk_sampled_rows(orc, B):
+    """2,000,000-particle LJ box: sampled rows against brute force."""
+    s = inputs.lj_bulk()
+    ctx = _ctx(B, s.pos, s.vel, s.L, precision=B.MIXED)
+    ctx.build_nlist(True)
+    ctx.check()
+    rng = np.random.default_rng(0)
+    which = np.sort(rng.choice(s.n, 64, replace=False))
+    assert neighbor_sets_equal(orc, ctx, s.pos, s.L, 2.5, 0.4, which=which) == []
