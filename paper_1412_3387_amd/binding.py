@@ -92,6 +92,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run paper_1412_3387_amd/build.py "
                                "(there is no CPU fallback)")
+        # torch ships its own HIP runtime (soname libamdhip64.so.7); loading it
+        # first makes the library bind to that same runtime, so device
+        # pointers from torch allocations are known to every HIP call here.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.hoomd_workspace_bytes.argtypes = [C.POINTER(Params), C.c_int32, C.POINTER(Box)]
