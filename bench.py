@@ -36,9 +36,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run_precision(B, inputs, torch, s, prec, steps, warmup, tune):
+def run_precision(B, inputs, torch, s, prec, steps, warmup, tune, fixed=None):
+    kw = {}
+    if fixed:
+        kw = {k: int(fixed[k]) for k in ("tpp_nlist", "block_nlist", "tpp_force", "block_force")}
+        tune = False
     p = B.ModelParams(precision=prec, pair=B.PAIR_LJ, r_cut=2.5, r_buff=0.4, dt=0.005,
-                      sort_period=500)
+                      sort_period=500, **kw)
     ctx = B.Context([p], [dict(pos=s.pos, vel=s.vel, L=s.L)])
     ctx.build_nlist(True)
     tuning = ctx.autotune(tune)
@@ -113,6 +117,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tuning-out", default=None,
+                    help="write the lanes/block sizes chosen per precision to this JSON file")
+    ap.add_argument("--tuning-from", default=None,
+                    help="use lanes/block sizes from a file written by --tuning-out (no tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the hot path of one subdomain); "
@@ -128,12 +136,21 @@ def main():
     B.lib()
     s = inputs.lj_bulk(args.n)
     print(f"[bench] N={s.n} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-    mixed = run_precision(B, inputs, torch, s, B.MIXED, args.steps, args.warmup, not args.no_tune)
+    fixed = {}
+    if args.tuning_from:
+        with open(args.tuning_from) as f:
+            fixed = json.load(f)
+    mixed = run_precision(B, inputs, torch, s, B.MIXED, args.steps, args.warmup, not args.no_tune,
+                          fixed.get("mixed"))
     print(f"[bench] mixed done {mixed['ms']:.1f} ms", file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_precision(B, inputs, torch, s, B.FP64, args.steps, args.warmup, not args.no_tune)
+        fp64 = run_precision(B, inputs, torch, s, B.FP64, args.steps, args.warmup, not args.no_tune,
+                             fixed.get("fp64"))
         print(f"[bench] fp64 done {fp64['ms']:.1f} ms", file=sys.stderr, flush=True)
+    if args.tuning_out:
+        with open(args.tuning_out, "w") as f:
+            json.dump({"mixed": mixed["tuning"], "fp64": fp64["tuning"] if fp64 else None}, f)
 
     K = args.steps
     value = s.n * K / (mixed["ms"] / 1e3)

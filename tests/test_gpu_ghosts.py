@@ -33,12 +33,15 @@ def _loopback(B, sd, precision=1, update_shift=None):
     full = sd.full
     L = full.L
     systems, params = [], []
+    frame = sd.side + 2 * (W + MARGIN)
+    rho = full.n / float(np.prod(L))
     for s in range(27):
         loc = sd.local(s)
         lo = sd.lo(s) - W - MARGIN
+        # rows for the locals and every ghost the frame can hold
         systems.append(dict(pos=full.pos[loc], vel=full.vel[loc], tag=loc.astype(np.int32),
-                            L=np.full(3, sd.side + 2 * (W + MARGIN)), lo=lo, periodic=(0, 0, 0),
-                            n_cap=len(loc) * 3))
+                            L=np.full(3, frame), lo=lo, periodic=(0, 0, 0),
+                            n_cap=int(1.2 * rho * frame ** 3) + 64))
         params.append(B.ModelParams(precision=precision, nlist_cap=160))
     ctx = B.Context(params, systems)
     dev = ctx.device
