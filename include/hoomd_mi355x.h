@@ -69,8 +69,11 @@ typedef enum {
     HOOMD_E_GHOST_OVERFLOW = 7,  /* send list or buffer capacity exceeded   */
     HOOMD_E_BOND_STRETCH = 8,    /* a FENE bond reached r >= R0             */
     HOOMD_E_NAN = 9,             /* a non-finite force or position          */
-    HOOMD_E_DANGEROUS_BUILD = 10 /* rebuild found a particle beyond r_buff/2
+    HOOMD_E_DANGEROUS_BUILD = 10,/* rebuild found a particle beyond r_buff/2
                                     when the check period is > 1            */
+    HOOMD_E_HALO_OVERFLOW = 11   /* a 64-row tile needs more halo entries
+                                    than halo_cap (or its cell box is too
+                                    large); Morton-sorted rows avoid it      */
 } hoomd_status;
 
 /* Arithmetic of the pair and bond terms.  Positions, velocities, the
@@ -101,6 +104,9 @@ typedef struct {
     double fene_K, fene_R0;/* FENE + WCA(eps, sigma) bond term              */
     int32_t nlist_cap;     /* neighbour row capacity (entries per particle)  */
     int32_t cell_cap;      /* cell capacity (0 = derived from the density)   */
+    int32_t halo_cap;      /* halo entries per 64-row tile (0 = derived: from
+                              the density when sort_period > 0, else the LDS
+                              limit, since unsorted rows make wide tiles)    */
     int32_t sort_period;   /* Morton sort every this many steps (0 = never)  */
     int32_t check_period;  /* displacement check every k steps (>= 1)        */
     int32_t tpp_nlist;     /* lanes per particle, neighbour list (0 = tuned) */
@@ -226,21 +232,31 @@ int hoomd_sync_status(hoomd_ctx *ctx, int64_t *required);
 /* Number of neighbour-list builds since hoomd_init.  Synchronises. */
 int hoomd_build_count(hoomd_ctx *ctx, int64_t *builds);
 
-/* Device pointers into the workspace for inspection: the neighbour list
- * (int32, row of particle i at entries (i/64)*64*cap + k*64 + i%64, k <
- * nn[i]), the counts nn (int32[n]), the cell members (int32, cell c at c *
- * cell_cap + k, k < cell_size[c]), cell sizes, and the bins per axis of
- * system `sys`.  Row i of system s is row offset_s + i of the arrays. */
+/* Device pointers into the workspace for inspection, for system `sys`:
+ *   nlist  uint16, row of local particle i at entries (i/64)*64*cap +
+ *          k*64 + i%64, k < nn[i]; an entry is an index into the halo of
+ *          the row's 64-row tile;
+ *   nn     int32[n] row lengths;
+ *   halo   int32, halo_cap array rows (global row numbers) per tile, the
+ *          first (halo_n[tile] & 0x7fffffff) valid;
+ *   cell_idx / cell_size: cell c holds cell_idx[c * cell_cap + k], k <
+ *          cell_size[c] (global row numbers, ascending);
+ *   bins per axis.  Row i of system s is row row_offset + i of the arrays,
+ *   tile t of the system is tile tile_offset + t of halo and halo_n. */
 typedef struct {
-    const int32_t *nlist;
+    const uint16_t *nlist;
     const int32_t *nn;
+    const int32_t *halo;
+    const int32_t *halo_n;
     const int32_t *cell_idx;
     const int32_t *cell_size;
     int32_t nlist_cap;
     int32_t cell_cap;
+    int32_t halo_cap;
     int32_t bins[3];
     int64_t row_offset;
     int64_t cell_offset;
+    int64_t tile_offset;
 } hoomd_layout;
 int hoomd_get_layout(hoomd_ctx *ctx, int32_t sys, hoomd_layout *out);
 

@@ -26,7 +26,7 @@ FIELD_POS, FIELD_VEL, FIELD_TAG = 1, 2, 4
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_DEVICE", 3: "E_WORKSPACE", 4: "E_STATE",
           5: "E_NLIST_OVERFLOW", 6: "E_CELL_OVERFLOW", 7: "E_GHOST_OVERFLOW",
-          8: "E_BOND_STRETCH", 9: "E_NAN", 10: "E_DANGEROUS_BUILD"}
+          8: "E_BOND_STRETCH", 9: "E_NAN", 10: "E_DANGEROUS_BUILD", 11: "E_HALO_OVERFLOW"}
 
 
 class HoomdError(RuntimeError):
@@ -41,7 +41,7 @@ class Params(C.Structure):
                 ("sigma", C.c_double), ("dpd_A", C.c_double), ("dpd_gamma", C.c_double),
                 ("dpd_kT", C.c_double), ("dpd_seed", C.c_uint32), ("bond_cap", C.c_int32),
                 ("fene_K", C.c_double), ("fene_R0", C.c_double), ("nlist_cap", C.c_int32),
-                ("cell_cap", C.c_int32), ("sort_period", C.c_int32), ("check_period", C.c_int32),
+                ("cell_cap", C.c_int32), ("halo_cap", C.c_int32), ("sort_period", C.c_int32), ("check_period", C.c_int32),
                 ("tpp_nlist", C.c_int32), ("tpp_force", C.c_int32), ("block_nlist", C.c_int32),
                 ("block_force", C.c_int32)]
 
@@ -62,9 +62,11 @@ class Subdomain(C.Structure):
 
 
 class Layout(C.Structure):
-    _fields_ = [("nlist", C.c_void_p), ("nn", C.c_void_p), ("cell_idx", C.c_void_p),
-                ("cell_size", C.c_void_p), ("nlist_cap", C.c_int32), ("cell_cap", C.c_int32),
-                ("bins", C.c_int32 * 3), ("row_offset", C.c_int64), ("cell_offset", C.c_int64)]
+    _fields_ = [("nlist", C.c_void_p), ("nn", C.c_void_p), ("halo", C.c_void_p),
+                ("halo_n", C.c_void_p), ("cell_idx", C.c_void_p), ("cell_size", C.c_void_p),
+                ("nlist_cap", C.c_int32), ("cell_cap", C.c_int32), ("halo_cap", C.c_int32),
+                ("bins", C.c_int32 * 3), ("row_offset", C.c_int64), ("cell_offset", C.c_int64),
+                ("tile_offset", C.c_int64)]
 
 
 class Tuning(C.Structure):
@@ -143,6 +145,7 @@ class ModelParams:
     fene_R0: float = 1.5
     nlist_cap: int = 0
     cell_cap: int = 0
+    halo_cap: int = 0
     sort_period: int = 0
     check_period: int = 1
     tpp_nlist: int = 0
@@ -330,26 +333,35 @@ class Context:
         _check(lib().hoomd_get_layout(self.h, sys, C.byref(lay)), "hoomd_get_layout")
         return lay
 
-    def _ws_view(self, ptr: int, count: int):
+    def _ws_view(self, ptr: int, count: int, itemsize: int = 4):
         base = self.workspace.data_ptr()
         off = ptr - base
-        assert 0 <= off and off + 4 * count <= self.workspace.numel()
-        return self.workspace[off:off + 4 * count].view(self.torch.int32)
+        assert 0 <= off and off + itemsize * count <= self.workspace.numel()
+        v = self.workspace[off:off + itemsize * count]
+        return v.view(self.torch.int32) if itemsize == 4 else v.view(self.torch.int16)
 
     def neighbor_rows(self, sys: int = 0):
-        """(nn (n,), rows as a list of int arrays of system-local indices)."""
+        """(nn (n,), rows as a list of int arrays of system-local row
+        numbers), decoded through the per-tile halos."""
         lay = self.layout(sys)
         n = self.n_local[sys]
         o = self.offsets[sys]
         cap = lay.nlist_cap
         tiles = (n + 63) // 64
         nn = self._ws_view(lay.nn, n).cpu().numpy().copy()
-        nl = self._ws_view(lay.nlist, tiles * 64 * cap).cpu().numpy().reshape(tiles, cap, 64)
+        nl = self._ws_view(lay.nlist, tiles * 64 * cap, 2).cpu().numpy().view(np.uint16)
+        nl = nl.reshape(tiles, cap, 64).astype(np.int64)
+        halo = self._ws_view(lay.halo, tiles * lay.halo_cap).cpu().numpy().reshape(tiles, lay.halo_cap)
         rows = []
         for r in range(n):
             t, l = divmod(r, 64)
-            rows.append(nl[t, : nn[r], l].astype(np.int64) - o)
+            rows.append(halo[t][nl[t, : nn[r], l]].astype(np.int64) - o)
         return nn, rows
+
+    def halo_sizes(self, sys: int = 0) -> np.ndarray:
+        lay = self.layout(sys)
+        tiles = (self.n_local[sys] + 63) // 64
+        return self._ws_view(lay.halo_n, tiles).cpu().numpy() & 0x7FFFFFFF
 
     def cells(self, sys: int = 0):
         """(bins, sizes (ncell,), members list per cell in system-local rows)."""

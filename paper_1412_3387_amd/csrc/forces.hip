@@ -1,14 +1,18 @@
 // forces.hip -- pair + bond forces fused with the velocity-Verlet update.
 //
 // Sec. 5.1: W lanes cooperate on one particle, striding over its neighbour
-// row, and a lane reduction totals the force.  One launch per time step does
-// the whole step of a particle: the closing half kick of the previous step,
-// the thermo sums, the opening half kick, the drift, the fold into the box
-// and the displacement check that decides the next neighbour-list rebuild
+// row, and a lane reduction totals the force.  One workgroup handles one tile
+// of 64 rows: it first copies the tile's halo (the union of the rows'
+// neighbours) from HBM/L2 into LDS, each halo position moved to its periodic
+// image nearest the tile, so every neighbour read afterwards is an LDS read
+// and needs no minimum-image arithmetic.  The same launch then does the whole
+// step of each particle: the closing half kick of the previous step, the
+// thermo sums, the opening half kick, the drift, the fold into the box, and
+// the displacement check that decides the next neighbour-list rebuild
 // (Sec. 4.2: rebuild once a particle has moved more than r_buff / 2).  New
-// positions go to the other half of a position double buffer, so every
-// neighbour read in the launch sees the old ones; DPD double-buffers the
-// velocities too, because the pair force reads neighbour velocities.
+// positions go to the other half of a position double buffer, so every halo
+// read in the launch sees the old ones; DPD double-buffers the velocities
+// too, because the pair force reads neighbour velocities.
 //
 // Precision: every separation, the cut-off test and the integrator are
 // FP64.  With MIXED the pair and bond arithmetic after the cut-off test and
@@ -48,31 +52,74 @@ __device__ __forceinline__ T lj_pair(double r2, T eps, T sig2, double shift, dou
     return ff;
 }
 
+// Bytes of LDS per halo entry.
+__host__ __device__ constexpr int halo_entry_bytes(int pot) { return pot == PAIR_DPD ? 52 : 24; }
+
 template <int W, bool MIXED, int POT, bool LOG>
-__global__ __launch_bounds__(256) void k_force(const SysDev *__restrict__ sys,
-                                               const int32_t *__restrict__ tprefix, int n_sys,
-                                               int tiles, const int32_t *__restrict__ nlist,
-                                               const int32_t *__restrict__ nn, int cap,
-                                               const int32_t *__restrict__ partners,
-                                               const int32_t *__restrict__ rtag,
-                                               const double4 *__restrict__ xbuild,
-                                               double *__restrict__ partials, Status *st,
-                                               ForceLaunch a)
+__global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
+                                                const int32_t *__restrict__ tprefix, int n_sys,
+                                                const uint16_t *__restrict__ nlist,
+                                                const int32_t *__restrict__ nn, int cap,
+                                                const int32_t *__restrict__ halo,
+                                                const int32_t *__restrict__ halo_n, int halo_cap,
+                                                const int32_t *__restrict__ partners,
+                                                const int32_t *__restrict__ rtag,
+                                                const double4 *__restrict__ xbuild,
+                                                double *__restrict__ partials, Status *st,
+                                                ForceLaunch a)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
+    extern __shared__ double lds[];
+    double *hx = lds;
+    double *hy = hx + halo_cap;
+    double *hz = hy + halo_cap;
+    double *hvx = hz + halo_cap;           // DPD only
+    double *hvy = hvx + halo_cap;
+    double *hvz = hvy + halo_cap;
+    int32_t *htag = reinterpret_cast<int32_t *>(hvz + halo_cap);
+
     constexpr int P = kWave / W;
+    const int tid = threadIdx.x;
     const int lane = lane_id();
+    const int wv = tid >> 6;
     const int pl = lane % P;
     const int sl = lane / P;
-    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int tile = gw / W;
-    if (tile >= tiles) return;
-    if (a.flag_clear && gw == 0 && lane == 0) *a.flag_clear = 0;
+    const int tile = blockIdx.x;
+    const int gw = tile * W + wv;
+    if (a.flag_clear && tile == 0 && tid == 0) *a.flag_clear = 0;
     const int s = find_sys(tprefix, n_sys, tile);
     const SysDev &S = sys[s];
-    const int r = (tile - S.tile0) * kTile + (gw % W) * P + pl;
+    const int r0 = (tile - S.tile0) * kTile;
+    const int r = r0 + wv * P + pl;
     const bool active = r < S.n_local;
-    const int64_t i = S.row0 + (active ? r : 0);
+    const int64_t i = S.row0 + (active ? r : r0);
+
+    // ---- stage the halo -----------------------------------------------------
+    const int32_t hn = halo_n[tile];
+    const int nh = hn & 0x7FFFFFFF;
+    const bool per_pair = hn < 0;  // tile too wide for one image per halo entry
+    const double4 xref = a.pos[S.row0 + r0];
+    const int32_t *hl = halo + (int64_t)tile * halo_cap;
+    for (int h = tid; h < nh; h += W * kWave) {
+        const int32_t j = hl[h];
+        double4 x = a.pos[j];
+        if (!per_pair) {
+            x.x = __fma_rn(-S.L[0], rint((x.x - xref.x) * S.invL[0]), x.x);
+            x.y = __fma_rn(-S.L[1], rint((x.y - xref.y) * S.invL[1]), x.y);
+            x.z = __fma_rn(-S.L[2], rint((x.z - xref.z) * S.invL[2]), x.z);
+        }
+        hx[h] = x.x;
+        hy[h] = x.y;
+        hz[h] = x.z;
+        if constexpr (POT == PAIR_DPD) {
+            const double4 v = a.vel[j];
+            hvx[h] = v.x;
+            hvy[h] = v.y;
+            hvz[h] = v.z;
+            htag[h] = a.tag[j];
+        }
+    }
+    __syncthreads();
 
     const double4 xi = a.pos[i];
     double4 vi;
@@ -81,7 +128,7 @@ __global__ __launch_bounds__(256) void k_force(const SysDev *__restrict__ sys,
     if constexpr (POT == PAIR_DPD) ti = a.tag[i];
     int n = active ? nn[i] : 0;
     n = n < cap ? n : cap;
-    const int32_t *row = nlist + S.nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
+    const uint16_t *row = nlist + S.nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
 
     T fx = 0, fy = 0, fz = 0;
     double e = 0.0, vir = 0.0;
@@ -89,13 +136,17 @@ __global__ __launch_bounds__(256) void k_force(const SysDev *__restrict__ sys,
     const T eps = (T)S.eps, sig2 = (T)S.sig2;
     const double shift = S.shift;
 
+#pragma unroll 4
     for (int k = sl; k < n; k += W) {
-        const int32_t j = row[(int64_t)k * kTile];
-        const double2 xyj = *reinterpret_cast<const double2 *>(&a.pos[j]);
-        const double zj = a.pos[j].z;
-        const double dx = min_image(xi.x - xyj.x, S.L[0], S.invL[0]);
-        const double dy = min_image(xi.y - xyj.y, S.L[1], S.invL[1]);
-        const double dz = min_image(xi.z - zj, S.L[2], S.invL[2]);
+        const int h = row[(int64_t)k * kTile];
+        double dx = xi.x - hx[h];
+        double dy = xi.y - hy[h];
+        double dz = xi.z - hz[h];
+        if (per_pair) {
+            dx = min_image(dx, S.L[0], S.invL[0]);
+            dy = min_image(dy, S.L[1], S.invL[1]);
+            dz = min_image(dz, S.L[2], S.invL[2]);
+        }
         const double r2 = norm2_exact(dx, dy, dz);
         if (r2 < rc2) {
             T ff;
@@ -103,14 +154,13 @@ __global__ __launch_bounds__(256) void k_force(const SysDev *__restrict__ sys,
                 ff = lj_pair<T, LOG>(r2, eps, sig2, shift, e, vir);
             } else {
                 if (r2 == 0.0) continue;
-                const double4 vj = a.vel[j];
                 const T tr2 = (T)r2;
                 const T rr = tsqrt<T>(tr2);
                 const T rinv = recip<T>(rr);
                 const T w = (T)1 - rr * (T)S.dpd_inv_rc;
-                const T dvx = (T)(vi.x - vj.x), dvy = (T)(vi.y - vj.y), dvz = (T)(vi.z - vj.z);
+                const T dvx = (T)(vi.x - hvx[h]), dvy = (T)(vi.y - hvy[h]), dvz = (T)(vi.z - hvz[h]);
                 const T rv = ((T)dx * dvx + (T)dy * dvy + (T)dz * dvz) * rinv;
-                const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)a.tag[j], S.dpd_seed, a.timestep);
+                const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)htag[h], S.dpd_seed, a.timestep);
                 const T u = (T)bits * (T)(1.0 / 16777216.0);
                 const T theta = (T)1.7320508075688772 * ((T)2 * u - (T)1);
                 const T mag = (T)S.dpd_A * w - (T)S.dpd_gamma * w * w * rv +
@@ -231,12 +281,14 @@ __global__ __launch_bounds__(256) void k_force(const SysDev *__restrict__ sys,
 }
 
 // Per-system totals of the wave partials, in a fixed order.
-__global__ void k_thermo_reduce(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
-                                int W, const double *__restrict__ partials,
-                                double *__restrict__ thermo, double *__restrict__ log_rows,
-                                int n_sys, int log_row, double timestep)
+__global__ __launch_bounds__(1024) void k_thermo_reduce(const SysDev *__restrict__ sys,
+                                                        const int32_t *__restrict__ tprefix, int W,
+                                                        const double *__restrict__ partials,
+                                                        double *__restrict__ thermo,
+                                                        double *__restrict__ log_rows, int n_sys,
+                                                        int log_row, double timestep)
 {
-    __shared__ double red[3][256];
+    __shared__ double red[3][1024];
     const int s = blockIdx.x;
     const SysDev &S = sys[s];
     const int64_t w0 = (int64_t)tprefix[s] * W;
@@ -316,58 +368,58 @@ __global__ void k_rtag(const SysDev *__restrict__ sys, const int32_t *__restrict
 
 // ---------------------------------------------------------------------------
 
+size_t force_lds_bytes(int pair, int halo_cap) { return (size_t)halo_entry_bytes(pair) * (size_t)halo_cap; }
+
 template <int W, bool MIXED, int POT, bool LOG>
-static void force_inst(const LaunchCtx &L, const ForceLaunch &F, int block)
+static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
 {
-    const int64_t threads_total = (int64_t)L.tiles_local * W * kWave;
-    const int blocks = (int)((threads_total + block - 1) / block);
-    if (blocks == 0) return;
-    hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(blocks), dim3(block), 0, L.stream, L.sys,
-                       L.tprefix_local, L.n_sys, L.tiles_local, L.nlist, L.nn, L.nlist_cap,
-                       L.partners, L.rtag, L.xbuild, L.partials, L.status, F);
+    if (L.tiles_local == 0) return;
+    const size_t lds = force_lds_bytes(POT, L.halo_cap);
+    hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(L.tiles_local), dim3(W * kWave), lds, L.stream,
+                       L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
+                       L.halo_cap, L.partners, L.rtag, L.xbuild, L.partials, L.status, F);
 }
 
 template <int W, bool MIXED, int POT>
-static void force_log(const LaunchCtx &L, const ForceLaunch &F, int block)
+static void force_log(const LaunchCtx &L, const ForceLaunch &F)
 {
-    if (F.log) force_inst<W, MIXED, POT, true>(L, F, block);
-    else force_inst<W, MIXED, POT, false>(L, F, block);
+    if (F.log) force_inst<W, MIXED, POT, true>(L, F);
+    else force_inst<W, MIXED, POT, false>(L, F);
 }
 
 template <int W, bool MIXED>
-static void force_pot(const LaunchCtx &L, const ForceLaunch &F, int block)
+static void force_pot(const LaunchCtx &L, const ForceLaunch &F)
 {
     switch (F.pair) {
-    case PAIR_LJ: force_log<W, MIXED, PAIR_LJ>(L, F, block); break;
-    case PAIR_WCA: force_log<W, MIXED, PAIR_WCA>(L, F, block); break;
-    default: force_log<W, MIXED, PAIR_DPD>(L, F, block); break;
+    case PAIR_LJ: force_log<W, MIXED, PAIR_LJ>(L, F); break;
+    case PAIR_WCA: force_log<W, MIXED, PAIR_WCA>(L, F); break;
+    default: force_log<W, MIXED, PAIR_DPD>(L, F); break;
     }
 }
 
 template <int W>
-static void force_prec(const LaunchCtx &L, const ForceLaunch &F, int block)
+static void force_prec(const LaunchCtx &L, const ForceLaunch &F)
 {
-    if (F.mixed) force_pot<W, true>(L, F, block);
-    else force_pot<W, false>(L, F, block);
+    if (F.mixed) force_pot<W, true>(L, F);
+    else force_pot<W, false>(L, F);
 }
 
 void launch_force(const LaunchCtx &L, const ForceLaunch &F, int w, int block)
 {
+    (void)block;
     switch (w) {
-    case 1: force_prec<1>(L, F, block); break;
-    case 2: force_prec<2>(L, F, block); break;
-    case 4: force_prec<4>(L, F, block); break;
-    case 8: force_prec<8>(L, F, block); break;
-    case 16: force_prec<16>(L, F, block); break;
-    default: force_prec<32>(L, F, block); break;
+    case 1: force_prec<1>(L, F); break;
+    case 2: force_prec<2>(L, F); break;
+    case 4: force_prec<4>(L, F); break;
+    case 8: force_prec<8>(L, F); break;
+    default: force_prec<16>(L, F); break;
     }
 }
 
 void launch_thermo_reduce(const LaunchCtx &L, int w, int log_row, double timestep)
 {
-    hipLaunchKernelGGL(k_thermo_reduce, dim3(L.n_sys), dim3(256), 0, L.stream, L.sys,
-                       L.tprefix_local, w, L.partials, L.thermo, L.thermo_log, L.n_sys, log_row,
-                       timestep);
+    hipLaunchKernelGGL(k_thermo_reduce, dim3(L.n_sys), dim3(1024), 0, L.stream, L.sys, L.tprefix_local, w,
+                       L.partials, L.thermo, L.thermo_log, L.n_sys, log_row, timestep);
 }
 
 void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value)

@@ -29,9 +29,12 @@ struct LaunchCtx {
     int32_t *cell_count;
     int32_t *cell_size;
     int32_t *cell_idx;
-    int32_t *nlist;
+    uint16_t *nlist;               // halo indices, tile-major rows
     int32_t *nn;
     int nlist_cap;
+    int32_t *halo;                 // halo_cap row numbers per tile
+    int32_t *halo_n;               // halo size per tile (top bit: per-pair images)
+    int halo_cap;
     double4 *xbuild;
     const int32_t *partners;       // per tag: bond_cap partner tags (-1 = none)
     int32_t *rtag;                 // row of each tag (per system offset row0)
@@ -69,5 +72,6 @@ void launch_thermo_reduce(const LaunchCtx &L, int w, int log_row, double timeste
 void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value);
 void launch_rtag(const LaunchCtx &L, const int32_t *tag);
 void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag);
+size_t force_lds_bytes(int pair, int halo_cap);
 
 }  // namespace md

@@ -1,184 +1,466 @@
-// nlist.hip -- cell list and Verlet neighbour list (Sec. 5.1, Fig. 4).
+// nlist.hip -- cell list and tile-halo Verlet neighbour list (Sec. 5.1,
+// Fig. 4, rebuilt for LDS-staged tiles on CDNA).
 //
 // Cell list: fixed-capacity bins.  A binning pass assigns every row to the
-// cell floor((x - lo) * bins / L) with an integer atomic slot; a per-cell
+// cell floor((x - lo) * bins / L); lanes of a wave that hit the same cell
+// claim their slots with one integer atomic per distinct cell.  A per-cell
 // pass then sorts the members of each cell by row index (rank sort inside
 // one wave), so the list is deterministic although the slots were claimed
-// in arbitrary order.  The per-cell pass also resets the atomic counters for
-// the next build, so no memset is needed between builds.
+// in arbitrary order.  It also resets the counters for the next build.
 //
-// Neighbour list: W lanes cooperate on one particle (lane = s * P + pl, P =
-// 64 / W particles per wave).  The W lanes stride over the members of each
-// stencil cell, test |x_j - x_i|^2 < r_list^2 in FP64, and compact the hits
-// into the particle's row with one 64-bit ballot: the write position is the
-// running count plus the number of hits of the same particle on lower lanes.
-// Rows are stored tile-major: entry k of row r of a system lives at
-// nl0 + (r / 64) * cap * 64 + k * 64 + r % 64, so a wave that reads entry k
-// of 64/W consecutive particles touches consecutive words.
+// Neighbour list: one workgroup per tile of 64 consecutive rows (Morton
+// ordered rows make a tile a compact cluster).  The workgroup
+//   1. finds the box of cells that covers the stencils of all its rows,
+//   2. stages the members of those cells (positions and row numbers) in LDS,
+//      a chunk at a time,
+//   3. lets W = 4 lanes per particle stride over the members of the
+//      particle's own 27 stencil cells and test |x_j - x_i|^2 < r_list^2 in
+//      FP64 (minimum image written as the stencil's image shift, which for
+//      every pair inside r_list is bitwise the shift the exact quotient
+//      gives), compacting hits into the row with a 64-bit ballot,
+//   4. marks every staged member that some row uses, numbers the marked
+//      members in staging order -- the tile's halo -- and rewrites the rows
+//      as 16-bit halo indices.
+// The force pass then loads each halo position once per tile into LDS
+// instead of once per neighbour from L2.
+//
+// Row layout (uint16): entry k of row r of a system lives at
+// nl0 + (r / 64) * cap * 64 + k * 64 + r % 64.
 #include "device.h"
 #include "launch.h"
 
 namespace md {
 
-// All kernels below return at once unless the rebuild flag is set, so the
-// whole rebuild sequence can be queued every step without a host round trip.
+constexpr int kBuildThreads = 256;   // 64 rows x 4 lanes
+constexpr int kBuildW = 4;
+constexpr int kChunk = 512;          // members staged at once
+constexpr int kBoxMax = 512;         // cells in a tile's box
+constexpr int kSlotMax = 16384;      // members in a tile's box
+constexpr int kRebuildGrid = 2048;   // blocks of the grid-stride rebuild kernels
 
-__global__ void k_bin(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
-                      int n_sys, int tiles, const double4 *__restrict__ pos,
-                      int32_t *__restrict__ cell_count, int32_t *__restrict__ cell_idx,
-                      int cell_cap, const int32_t *__restrict__ flag, Status *st)
+// ---------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
+                                             const int32_t *__restrict__ tprefix, int n_sys, int tiles,
+                                             const double4 *__restrict__ pos,
+                                             int32_t *__restrict__ cell_count,
+                                             int32_t *__restrict__ cell_idx, int cell_cap,
+                                             const int32_t *__restrict__ flag, Status *st)
 {
     if (*flag == 0) return;
-    const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (g >= tiles) return;
-    const int s = find_sys(tprefix, n_sys, g);
-    const SysDev &S = sys[s];
-    const int r = (g - S.tile0_all) * kTile + lane_id();
-    if (r >= S.n_total) return;
-    const int64_t i = S.row0 + r;
-    const double4 x = pos[i];
-    const int cx = cell_coord(x.x, S.lo[0], S.scale[0], S.bins[0]);
-    const int cy = cell_coord(x.y, S.lo[1], S.scale[1], S.bins[1]);
-    const int cz = cell_coord(x.z, S.lo[2], S.scale[2], S.bins[2]);
-    const int64_t c = S.cell0 + ((int64_t)cz * S.bins[1] + cy) * S.bins[0] + cx;
-    const int slot = atomicAdd(&cell_count[c], 1);
-    if (slot < cell_cap) cell_idx[c * cell_cap + slot] = (int32_t)i;
-    else latch(st, 6 /*CELL_OVERFLOW*/, slot + 1);
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const int waves = (int)(gridDim.x * blockDim.x) >> 6;
+    for (int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); g < tiles; g += waves) {
+        const int s = find_sys(tprefix, n_sys, g);
+        const SysDev &S = sys[s];
+        const int r = (g - S.tile0_all) * kTile + lane;
+        const bool valid = r < S.n_total;
+        int64_t c = -1;
+        int64_t i = 0;
+        if (valid) {
+            i = S.row0 + r;
+            const double4 x = pos[i];
+            const int cx = cell_coord(x.x, S.lo[0], S.scale[0], S.bins[0]);
+            const int cy = cell_coord(x.y, S.lo[1], S.scale[1], S.bins[1]);
+            const int cz = cell_coord(x.z, S.lo[2], S.scale[2], S.bins[2]);
+            c = S.cell0 + ((int64_t)cz * S.bins[1] + cy) * S.bins[0] + cx;
+        }
+        // one atomic per distinct cell of the wave
+        uint64_t todo = __ballot(valid);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int64_t lc = __shfl(c, leader, kWave);
+            const uint64_t same = __ballot(valid && c == lc);
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&cell_count[lc], __popcll(same));
+            base = __shfl(base, leader, kWave);
+            if (valid && c == lc) {
+                const int slot = base + __popcll(same & lt);
+                if (slot < cell_cap) cell_idx[c * cell_cap + slot] = (int32_t)i;
+                else latch(st, 6 /*CELL_OVERFLOW*/, slot + 1);
+            }
+            todo &= ~same;
+        }
+    }
 }
 
 // One wave per cell: members ranked by row index, sizes published, counters
 // cleared.  cell_cap <= 64 * CPL.
 template <int CPL>
-__global__ void k_cell_sort(int64_t n_cells, int32_t *__restrict__ cell_count,
-                            int32_t *__restrict__ cell_size, int32_t *__restrict__ cell_idx,
-                            int cell_cap, const int32_t *__restrict__ flag)
+__global__ __launch_bounds__(256) void k_cell_sort(int64_t n_cells, int32_t *__restrict__ cell_count,
+                                                   int32_t *__restrict__ cell_size,
+                                                   int32_t *__restrict__ cell_idx, int cell_cap,
+                                                   const int32_t *__restrict__ flag)
 {
     if (*flag == 0) return;
-    const int64_t c = (int64_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (c >= n_cells) return;
     const int lane = lane_id();
-    int m = cell_count[c];
-    m = m < cell_cap ? m : cell_cap;
-    int32_t v[CPL];
+    const int64_t waves = (int64_t)(gridDim.x * blockDim.x) >> 6;
+    for (int64_t c = (int64_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); c < n_cells; c += waves) {
+        int m = cell_count[c];
+        m = m < cell_cap ? m : cell_cap;
+        int32_t v[CPL];
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-        const int k = q * kWave + lane;
-        v[q] = k < m ? cell_idx[c * cell_cap + k] : INT32_MAX;
-    }
-    int rank[CPL];
+        for (int q = 0; q < CPL; ++q) {
+            const int k = q * kWave + lane;
+            v[q] = k < m ? cell_idx[c * cell_cap + k] : INT32_MAX;
+        }
+        int rank[CPL];
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) rank[q] = 0;
-    for (int t = 0; t < m; ++t) {
-        const int32_t other = __shfl(v[t / kWave], t % kWave, kWave);
+        for (int q = 0; q < CPL; ++q) rank[q] = 0;
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) rank[q] += other < v[q] ? 1 : 0;
-    }
+        for (int q2 = 0; q2 < CPL; ++q2) {
+            const int tmax = m - q2 * kWave < kWave ? m - q2 * kWave : kWave;
+            for (int t = 0; t < tmax; ++t) {
+                const int32_t other = __shfl(v[q2], t, kWave);
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-        const int k = q * kWave + lane;
-        if (k < m) cell_idx[c * cell_cap + rank[q]] = v[q];
-    }
-    if (lane == 0) {
-        cell_size[c] = m;
-        cell_count[c] = 0;
+                for (int q = 0; q < CPL; ++q) rank[q] += other < v[q] ? 1 : 0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            const int k = q * kWave + lane;
+            if (k < m) cell_idx[c * cell_cap + rank[q]] = v[q];
+        }
+        if (lane == 0) {
+            cell_size[c] = m;
+            cell_count[c] = 0;
+        }
     }
 }
 
-template <int W, bool EXCL>
-__global__ void k_nlist(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
-                        int n_sys, int tiles, const double4 *__restrict__ pos,
-                        const int32_t *__restrict__ tag, const int32_t *__restrict__ partners,
-                        const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx,
-                        int cell_cap, int32_t *__restrict__ nlist, int32_t *__restrict__ nn,
-                        int cap, double4 *__restrict__ xbuild, const int32_t *__restrict__ flag,
-                        int32_t *build_count, Status *st)
+// ---------------------------------------------------------------------------
+// tile-halo neighbour list
+// ---------------------------------------------------------------------------
+
+// Wrap a cell coordinate difference into [-bins/2, bins - bins/2).
+__device__ __forceinline__ int wrap_rel(int d, int bins)
+{
+    const int h = bins / 2;
+    d = ((d + h) % bins + bins) % bins - h;
+    return d;
+}
+
+struct BuildShared {
+    double cx[kChunk], cy[kChunk], cz[kChunk];
+    int32_t cj[kChunk];
+    int32_t bstart[kBoxMax + 1];
+    int32_t bcell[kBoxMax];
+    uint32_t used[kSlotMax / 32];
+    int32_t wpre[kSlotMax / 32 + 1];
+    int32_t scan[kBuildThreads];
+    int32_t ext[6];       // min rel (3), max rel (3)
+    int32_t info[8];      // box lo (3), dims (3), nbox, nslot
+};
+
+template <bool EXCL>
+__global__ __launch_bounds__(kBuildThreads) void k_build_tile(
+    const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
+    const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ partners,
+    const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx, int cell_cap,
+    uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int32_t *__restrict__ halo,
+    int32_t *__restrict__ halo_n, int halo_cap, double4 *__restrict__ xbuild,
+    const int32_t *__restrict__ flag, int32_t *build_count, Status *st)
 {
     if (*flag == 0) return;
+    __shared__ BuildShared sh;
+    constexpr int W = kBuildW;
     constexpr int P = kWave / W;
+    const int tid = threadIdx.x;
     const int lane = lane_id();
+    const int w = tid >> 6;
     const int pl = lane % P;
     const int sl = lane / P;
-    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int tile = gw / W;
-    if (tile >= tiles) return;
-    if (gw == 0 && lane == 0) atomicAdd(build_count, 1);
-    const int s = find_sys(tprefix, n_sys, tile);
-    const SysDev &S = sys[s];
-    const int r = (tile - S.tile0) * kTile + (gw % W) * P + pl;
-    const bool active = r < S.n_local;
-    const int64_t i = S.row0 + (active ? r : 0);
-    const double4 xi = pos[i];
-    const int cx = cell_coord(xi.x, S.lo[0], S.scale[0], S.bins[0]);
-    const int cy = cell_coord(xi.y, S.lo[1], S.scale[1], S.bins[1]);
-    const int cz = cell_coord(xi.z, S.lo[2], S.scale[2], S.bins[2]);
-
-    int32_t part[kMaxBondCap];
-    if constexpr (EXCL) {
-#pragma unroll
-        for (int b = 0; b < kMaxBondCap; ++b) part[b] = -1;
-        if (active) {
-            const int64_t prow = (S.row0 + tag[i]) * S.bond_cap;
-            for (int b = 0; b < S.bond_cap && b < kMaxBondCap; ++b) part[b] = partners[prow + b];
-        }
-    }
-
+    const int t = w * P + pl;  // particle slot in the tile
     const uint64_t seg = segment_bits(pl, P);
     const uint64_t below = lanemask_lt();
-    const int64_t rowbase = S.nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
-    const double rl2 = S.rl2;
-    int ntot = 0;
-    if (active) {
-        for (int a = 0; a < S.nst[2]; ++a) {
-            int z = cz + S.st[2][a];
-            if (S.per[2]) z = z < 0 ? z + S.bins[2] : (z >= S.bins[2] ? z - S.bins[2] : z);
-            else if (z < 0 || z >= S.bins[2]) continue;
-            for (int b = 0; b < S.nst[1]; ++b) {
-                int y = cy + S.st[1][b];
-                if (S.per[1]) y = y < 0 ? y + S.bins[1] : (y >= S.bins[1] ? y - S.bins[1] : y);
-                else if (y < 0 || y >= S.bins[1]) continue;
-                for (int e = 0; e < S.nst[0]; ++e) {
-                    int x = cx + S.st[0][e];
-                    if (S.per[0]) x = x < 0 ? x + S.bins[0] : (x >= S.bins[0] ? x - S.bins[0] : x);
-                    else if (x < 0 || x >= S.bins[0]) continue;
-                    const int64_t c = S.cell0 + ((int64_t)z * S.bins[1] + y) * S.bins[0] + x;
-                    const int m = cell_size[c];
-                    const int32_t *members = cell_idx + c * cell_cap;
-                    for (int k0 = 0; k0 < m; k0 += W) {
-                        const int k = k0 + sl;
-                        bool hit = false;
-                        int32_t j = 0;
-                        if (k < m) {
-                            j = members[k];
-                            if (j != (int32_t)i) {
-                                const double4 xj = pos[j];
-                                const double dx = min_image(xj.x - xi.x, S.L[0], S.invL[0]);
-                                const double dy = min_image(xj.y - xi.y, S.L[1], S.invL[1]);
-                                const double dz = min_image(xj.z - xi.z, S.L[2], S.invL[2]);
-                                hit = norm2_exact(dx, dy, dz) < rl2;
-                                if constexpr (EXCL) {
-                                    if (hit) {
-                                        const int32_t tj = tag[j];
+    if (blockIdx.x == 0 && tid == 0) atomicAdd(build_count, 1);
+
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int s = find_sys(tprefix, n_sys, tile);
+        const SysDev &S = sys[s];
+        const int r0 = (tile - S.tile0) * kTile;
+        const int r = r0 + t;
+        const bool active = r < S.n_local;
+        const int64_t i = S.row0 + (active ? r : r0);
+        const double4 xi = pos[i];
+        int ci[3];
+        ci[0] = cell_coord(xi.x, S.lo[0], S.scale[0], S.bins[0]);
+        ci[1] = cell_coord(xi.y, S.lo[1], S.scale[1], S.bins[1]);
+        ci[2] = cell_coord(xi.z, S.lo[2], S.scale[2], S.bins[2]);
+        // reference cell: the tile's first row
+        const double4 x0 = pos[S.row0 + r0];
+        int c0[3];
+        c0[0] = cell_coord(x0.x, S.lo[0], S.scale[0], S.bins[0]);
+        c0[1] = cell_coord(x0.y, S.lo[1], S.scale[1], S.bins[1]);
+        c0[2] = cell_coord(x0.z, S.lo[2], S.scale[2], S.bins[2]);
+        int rel[3];
 #pragma unroll
-                                        for (int q = 0; q < kMaxBondCap; ++q) hit = hit && (part[q] != tj);
+        for (int a = 0; a < 3; ++a) rel[a] = S.per[a] ? wrap_rel(ci[a] - c0[a], S.bins[a]) : ci[a] - c0[a];
+
+        // ---- 1. box of cells --------------------------------------------
+        if (tid < 3) {
+            sh.ext[tid] = INT32_MAX;
+            sh.ext[3 + tid] = INT32_MIN;
+        }
+        __syncthreads();
+        if (active && sl == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                atomicMin(&sh.ext[a], rel[a]);
+                atomicMax(&sh.ext[3 + a], rel[a]);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int nbox = 1;
+            // one periodic image per halo entry serves every row of the tile
+            // while tile extent + list radius + drift stays below half a box
+            int pp = 0;
+            for (int a = 0; a < 3; ++a)
+                if (S.per[a] && (double)(sh.ext[3 + a] - sh.ext[a] + 3) * (S.L[a] / S.bins[a]) >= 0.5 * S.L[a])
+                    pp = 1;
+            sh.info[7] = pp;
+            for (int a = 0; a < 3; ++a) {
+                int lo = sh.ext[a] - 1, hi = sh.ext[3 + a] + 1;
+                if (S.per[a]) {
+                    if (hi - lo + 1 >= S.bins[a]) {
+                        lo = -c0[a];
+                        hi = S.bins[a] - 1 - c0[a];
+                    }
+                } else {
+                    lo = lo > -c0[a] ? lo : -c0[a];
+                    hi = hi < S.bins[a] - 1 - c0[a] ? hi : S.bins[a] - 1 - c0[a];
+                }
+                sh.info[a] = lo;
+                sh.info[3 + a] = hi - lo + 1;
+                nbox *= hi - lo + 1;
+            }
+            sh.info[6] = nbox;
+        }
+        __syncthreads();
+        const int bl[3] = {sh.info[0], sh.info[1], sh.info[2]};
+        const int D[3] = {sh.info[3], sh.info[4], sh.info[5]};
+        const int nbox = sh.info[6];
+        if (nbox > kBoxMax) {
+            if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nbox);
+            if (active && sl == 0) nn[i] = 0;
+            if (tid == 0) halo_n[tile] = 0;
+            __syncthreads();
+            continue;
+        }
+        // ---- 2. member counts of the box cells and their prefix ------------
+        for (int b = tid; b < nbox; b += kBuildThreads) {
+            const int bx = b % D[0], by = (b / D[0]) % D[1], bz = b / (D[0] * D[1]);
+            int cc[3] = {c0[0] + bl[0] + bx, c0[1] + bl[1] + by, c0[2] + bl[2] + bz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (S.per[a]) cc[a] = ((cc[a] % S.bins[a]) + S.bins[a]) % S.bins[a];
+            const int pc = (cc[2] * S.bins[1] + cc[1]) * S.bins[0] + cc[0];
+            sh.bcell[b] = pc;
+            sh.bstart[b + 1] = cell_size[S.cell0 + pc];
+        }
+        if (tid == 0) sh.bstart[0] = 0;
+        __syncthreads();
+        // inclusive scan of bstart[1..nbox] (nbox <= 512 = 2 per thread)
+        {
+            const int b0 = 2 * tid;
+            int v0 = b0 < nbox ? sh.bstart[b0 + 1] : 0;
+            int v1 = b0 + 1 < nbox ? sh.bstart[b0 + 2] : 0;
+            sh.scan[tid] = v0 + v1;
+            __syncthreads();
+            for (int off = 1; off < kBuildThreads; off <<= 1) {
+                const int add = tid >= off ? sh.scan[tid - off] : 0;
+                __syncthreads();
+                sh.scan[tid] += add;
+                __syncthreads();
+            }
+            const int before = tid > 0 ? sh.scan[tid - 1] : 0;
+            if (b0 < nbox) sh.bstart[b0 + 1] = before + v0;
+            if (b0 + 1 < nbox) sh.bstart[b0 + 2] = before + v0 + v1;
+            __syncthreads();
+        }
+        const int nslot = sh.bstart[nbox];
+        if (nslot > kSlotMax) {
+            if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nslot);
+            if (active && sl == 0) nn[i] = 0;
+            if (tid == 0) halo_n[tile] = 0;
+            __syncthreads();
+            continue;
+        }
+        for (int q = tid; q < (nslot + 31) / 32; q += kBuildThreads) sh.used[q] = 0u;
+
+        // ---- 3. stencil scan, chunk by chunk --------------------------------
+        int32_t part[kMaxBondCap];
+        if constexpr (EXCL) {
+#pragma unroll
+            for (int b = 0; b < kMaxBondCap; ++b) part[b] = -1;
+            if (active) {
+                const int64_t prow = (S.row0 + tag[i]) * S.bond_cap;
+                for (int b = 0; b < S.bond_cap && b < kMaxBondCap; ++b) part[b] = partners[prow + b];
+            }
+        }
+        int bi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bi[a] = rel[a] - bl[a];
+        const int64_t rowbase = S.nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
+        const double rl2 = S.rl2;
+        int ntot = 0;
+        for (int q0 = 0; q0 < nslot; q0 += kChunk) {
+            const int q1 = q0 + kChunk < nslot ? q0 + kChunk : nslot;
+            __syncthreads();
+            for (int q = q0 + tid; q < q1; q += kBuildThreads) {
+                int lo = 0, hi = nbox;  // bstart[lo] <= q < bstart[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (sh.bstart[mid] <= q) lo = mid;
+                    else hi = mid;
+                }
+                const int32_t j = cell_idx[(S.cell0 + sh.bcell[lo]) * cell_cap + (q - sh.bstart[lo])];
+                const double4 xj = pos[j];
+                sh.cx[q - q0] = xj.x;
+                sh.cy[q - q0] = xj.y;
+                sh.cz[q - q0] = xj.z;
+                sh.cj[q - q0] = j;
+            }
+            __syncthreads();
+            if (!active) continue;
+            for (int oz = 0; oz < S.nst[2]; ++oz) {
+                const int dz = S.st[2][oz];
+                int bz = bi[2] + dz;
+                double mz = 0.0;
+                if (S.per[2]) {
+                    if (D[2] == S.bins[2]) bz = (bz % D[2] + D[2]) % D[2];
+                    const int pcz = ci[2] + dz;
+                    mz = pcz < 0 ? 1.0 : (pcz >= S.bins[2] ? -1.0 : 0.0);
+                } else if (bz < 0 || bz >= D[2]) {
+                    continue;
+                }
+                for (int oy = 0; oy < S.nst[1]; ++oy) {
+                    const int dy = S.st[1][oy];
+                    int by = bi[1] + dy;
+                    double my = 0.0;
+                    if (S.per[1]) {
+                        if (D[1] == S.bins[1]) by = (by % D[1] + D[1]) % D[1];
+                        const int pcy = ci[1] + dy;
+                        my = pcy < 0 ? 1.0 : (pcy >= S.bins[1] ? -1.0 : 0.0);
+                    } else if (by < 0 || by >= D[1]) {
+                        continue;
+                    }
+                    for (int ox = 0; ox < S.nst[0]; ++ox) {
+                        const int dx = S.st[0][ox];
+                        int bx = bi[0] + dx;
+                        double mx = 0.0;
+                        if (S.per[0]) {
+                            if (D[0] == S.bins[0]) bx = (bx % D[0] + D[0]) % D[0];
+                            const int pcx = ci[0] + dx;
+                            mx = pcx < 0 ? 1.0 : (pcx >= S.bins[0] ? -1.0 : 0.0);
+                        } else if (bx < 0 || bx >= D[0]) {
+                            continue;
+                        }
+                        const int b = (bz * D[1] + by) * D[0] + bx;
+                        int a0 = sh.bstart[b], a1 = sh.bstart[b + 1];
+                        a0 = a0 > q0 ? a0 : q0;
+                        a1 = a1 < q1 ? a1 : q1;
+                        for (int k0 = a0; k0 < a1; k0 += W) {
+                            const int q = k0 + sl;
+                            bool hit = false;
+                            if (q < a1) {
+                                const int32_t j = sh.cj[q - q0];
+                                if (j != (int32_t)i) {
+                                    double ddx = sh.cx[q - q0] - xi.x;
+                                    double ddy = sh.cy[q - q0] - xi.y;
+                                    double ddz = sh.cz[q - q0] - xi.z;
+                                    // bins < 3: several images share a cell; take the nearest
+                                    ddx = S.bins[0] < 3 && S.per[0] ? min_image(ddx, S.L[0], S.invL[0]) : __fma_rn(-S.L[0], mx, ddx);
+                                    ddy = S.bins[1] < 3 && S.per[1] ? min_image(ddy, S.L[1], S.invL[1]) : __fma_rn(-S.L[1], my, ddy);
+                                    ddz = S.bins[2] < 3 && S.per[2] ? min_image(ddz, S.L[2], S.invL[2]) : __fma_rn(-S.L[2], mz, ddz);
+                                    hit = norm2_exact(ddx, ddy, ddz) < rl2;
+                                    if constexpr (EXCL) {
+                                        if (hit) {
+                                            const int32_t tj = tag[j];
+#pragma unroll
+                                            for (int e = 0; e < kMaxBondCap; ++e) hit = hit && (part[e] != tj);
+                                        }
                                     }
                                 }
                             }
+                            const uint64_t mask = __ballot(hit) & seg;
+                            if (hit) {
+                                const int p = ntot + __popcll(mask & below);
+                                if (p < cap) nlist[rowbase + (int64_t)p * kTile] = (uint16_t)q;
+                                atomicOr(&sh.used[q >> 5], 1u << (q & 31));
+                            }
+                            ntot += __popcll(mask);
                         }
-                        const uint64_t mask = __ballot(hit) & seg;
-                        if (hit) {
-                            const int p = ntot + __popcll(mask & below);
-                            if (p < cap) nlist[rowbase + (int64_t)p * kTile] = j;
-                        }
-                        ntot += __popcll(mask);
                     }
                 }
             }
         }
-        if (sl == 0) {
-            nn[i] = ntot < cap ? ntot : cap;
-            xbuild[i] = xi;
-            if (ntot > cap) latch(st, 5 /*NLIST_OVERFLOW*/, ntot);
+        __syncthreads();
+        // ---- 4. halo numbering and row rewrite ---------------------------------
+        const int nwords = (nslot + 31) / 32;
+        {
+            // exclusive prefix of popcounts over nwords (<= 512) words
+            const int w0 = 2 * tid;
+            const int v0 = w0 < nwords ? __popc(sh.used[w0]) : 0;
+            const int v1 = w0 + 1 < nwords ? __popc(sh.used[w0 + 1]) : 0;
+            sh.scan[tid] = v0 + v1;
+            __syncthreads();
+            for (int off = 1; off < kBuildThreads; off <<= 1) {
+                const int add = tid >= off ? sh.scan[tid - off] : 0;
+                __syncthreads();
+                sh.scan[tid] += add;
+                __syncthreads();
+            }
+            const int before = tid > 0 ? sh.scan[tid - 1] : 0;
+            if (w0 < nwords) sh.wpre[w0] = before;
+            if (w0 + 1 < nwords) sh.wpre[w0 + 1] = before + v0;
+            if (tid == kBuildThreads - 1) sh.wpre[nwords] = sh.scan[tid];
+            __syncthreads();
         }
+        const int nhalo = sh.wpre[nwords];
+        if (nhalo > halo_cap) {
+            if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nhalo);
+            if (active && sl == 0) nn[i] = 0;
+            if (tid == 0) halo_n[tile] = 0;
+            __syncthreads();
+            continue;
+        }
+        // halo list: row number of every used member, in staging order
+        int32_t *hl = halo + (int64_t)tile * halo_cap;
+        for (int q = tid; q < nslot; q += kBuildThreads) {
+            const uint32_t word = sh.used[q >> 5];
+            if (word & (1u << (q & 31))) {
+                int lo = 0, hi = nbox;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (sh.bstart[mid] <= q) lo = mid;
+                    else hi = mid;
+                }
+                const int h = sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u));
+                hl[h] = cell_idx[(S.cell0 + sh.bcell[lo]) * cell_cap + (q - sh.bstart[lo])];
+            }
+        }
+        if (tid == 0) halo_n[tile] = sh.info[7] ? (int32_t)((uint32_t)nhalo | 0x80000000u) : nhalo;
+        __threadfence_block();
+        __syncthreads();
+        if (active) {
+            const int n = ntot < cap ? ntot : cap;
+            for (int k = sl; k < n; k += W) {
+                const int64_t a = rowbase + (int64_t)k * kTile;
+                const int q = nlist[a];
+                const uint32_t word = sh.used[q >> 5];
+                nlist[a] = (uint16_t)(sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u)));
+            }
+            if (sl == 0) {
+                nn[i] = n;
+                xbuild[i] = xi;
+                if (ntot > cap) latch(st, 5 /*NLIST_OVERFLOW*/, ntot);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -186,59 +468,44 @@ __global__ void k_nlist(const SysDev *__restrict__ sys, const int32_t *__restric
 // host-side launchers
 // ---------------------------------------------------------------------------
 
+static int capped(int64_t blocks) { return (int)(blocks < kRebuildGrid ? (blocks > 0 ? blocks : 1) : kRebuildGrid); }
+
 void launch_bin(const LaunchCtx &L, const double4 *pos)
 {
-    const int threads = 256;
-    const int blocks = (L.tiles_all * kWave + threads - 1) / threads;
-    if (blocks == 0) return;
-    hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(threads), 0, L.stream, L.sys, L.tprefix_all,
-                       L.n_sys, L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag,
-                       L.status);
+    if (L.tiles_all == 0) return;
+    const int blocks = capped(((int64_t)L.tiles_all * kWave + 255) / 256);
+    hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.tprefix_all, L.n_sys,
+                       L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.status);
 }
 
 void launch_cell_sort(const LaunchCtx &L)
 {
-    const int threads = 256;
-    const int64_t blocks = (L.n_cells * kWave + threads - 1) / threads;
-    if (blocks == 0) return;
+    if (L.n_cells == 0) return;
+    const int blocks = capped((L.n_cells * kWave + 255) / 256);
     if (L.cell_cap <= 64)
-        hipLaunchKernelGGL(k_cell_sort<1>, dim3((unsigned)blocks), dim3(threads), 0, L.stream,
-                           L.n_cells, L.cell_count, L.cell_size, L.cell_idx, L.cell_cap, L.flag);
+        hipLaunchKernelGGL(k_cell_sort<1>, dim3(blocks), dim3(256), 0, L.stream, L.n_cells, L.cell_count,
+                           L.cell_size, L.cell_idx, L.cell_cap, L.flag);
     else
-        hipLaunchKernelGGL(k_cell_sort<2>, dim3((unsigned)blocks), dim3(threads), 0, L.stream,
-                           L.n_cells, L.cell_count, L.cell_size, L.cell_idx, L.cell_cap, L.flag);
-}
-
-template <int W, bool EXCL>
-static void nlist_w(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int block)
-{
-    const int64_t threads_total = (int64_t)L.tiles_local * W * kWave;
-    const int blocks = (int)((threads_total + block - 1) / block);
-    if (blocks == 0) return;
-    hipLaunchKernelGGL((k_nlist<W, EXCL>), dim3(blocks), dim3(block), 0, L.stream, L.sys,
-                       L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners,
-                       L.cell_size, L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap,
-                       L.xbuild, L.flag, L.build_count, L.status);
-}
-
-template <bool EXCL>
-static void nlist_excl(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int w, int block)
-{
-    switch (w) {
-    case 1: nlist_w<1, EXCL>(L, pos, tag, block); break;
-    case 2: nlist_w<2, EXCL>(L, pos, tag, block); break;
-    case 4: nlist_w<4, EXCL>(L, pos, tag, block); break;
-    case 8: nlist_w<8, EXCL>(L, pos, tag, block); break;
-    case 16: nlist_w<16, EXCL>(L, pos, tag, block); break;
-    case 32: nlist_w<32, EXCL>(L, pos, tag, block); break;
-    default: nlist_w<64, EXCL>(L, pos, tag, block); break;
-    }
+        hipLaunchKernelGGL(k_cell_sort<2>, dim3(blocks), dim3(256), 0, L.stream, L.n_cells, L.cell_count,
+                           L.cell_size, L.cell_idx, L.cell_cap, L.flag);
 }
 
 void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int w, int block)
 {
-    if (L.has_bonds) nlist_excl<true>(L, pos, tag, w, block);
-    else nlist_excl<false>(L, pos, tag, w, block);
+    (void)w;
+    (void)block;
+    if (L.tiles_local == 0) return;
+    const int blocks = capped(L.tiles_local);
+    if (L.has_bonds)
+        hipLaunchKernelGGL(k_build_tile<true>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
+                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
+                           L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
+                           L.halo_cap, L.xbuild, L.flag, L.build_count, L.status);
+    else
+        hipLaunchKernelGGL(k_build_tile<false>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
+                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
+                           L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
+                           L.halo_cap, L.xbuild, L.flag, L.build_count, L.status);
 }
 
 }  // namespace md

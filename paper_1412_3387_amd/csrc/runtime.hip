@@ -33,11 +33,11 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
     // byte offsets into the workspace
     size_t sysdev, tpl, tpa, status, flags, thermo, thermo_log, partials;
-    size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx;
+    size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, halo, halo_n;
     size_t rtag, partners, sort_ws, ghost_ws, total;
     // sizes
     int64_t rows, tiles_local, tiles_all, n_cells, nlist_entries;
-    int cell_cap, nlist_cap, bond_cap;
+    int cell_cap, nlist_cap, bond_cap, halo_cap;
     std::vector<SysDev> sys;
     std::vector<int32_t> tpl_host, tpa_host;
 };
@@ -69,6 +69,8 @@ bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         if (q.pair != HOOMD_PAIR_DPD && !(q.sigma > 0)) return false;
         if (q.nlist_cap < 1 || q.nlist_cap > (1 << 16)) return false;
         if (q.cell_cap < 0 || q.cell_cap > 128) return false;
+        if (q.halo_cap < 0 || q.halo_cap > 65535) return false;
+        if (q.tpp_force < 0 || q.tpp_force > 16 || (q.tpp_force & (q.tpp_force - 1))) return false;
         if (q.bond_cap < 0 || q.bond_cap > kMaxBondCap) return false;
         if (q.check_period < 0) return false;
         if (b.n_local < 0 || b.n_cap < b.n_local || b.n_cap > (int64_t)1 << 30) return false;
@@ -91,9 +93,24 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     int64_t row = 0, tile = 0, tile_all = 0, cell = 0, nl = 0;
     Lo.tpl_host.push_back(0);
     Lo.tpa_host.push_back(0);
+    Lo.halo_cap = 64;
     for (int s = 0; s < n_sys; ++s) {
         Lo.nlist_cap = std::max(Lo.nlist_cap, p[s].nlist_cap);
         Lo.bond_cap = std::max(Lo.bond_cap, p[s].bond_cap);
+        // halo of a compact 64-row tile: density x (tile side + 2 r_list)^3
+        const int lds_max = (int)(65536 / force_lds_bytes(p[s].pair, 1)) / 64 * 64;
+        int hc = p[s].halo_cap;
+        if (hc <= 0) {
+            const double vol = boxes[s].L[0] * boxes[s].L[1] * boxes[s].L[2];
+            const double rho = (double)std::max<int64_t>(boxes[s].n_cap, 1) / vol;
+            const double side = std::cbrt(64.0 / rho);
+            const double rl = pair_cut(p[s]) + p[s].r_buff;
+            const double est = rho * std::pow(side + 2.0 * rl, 3.0);
+            hc = p[s].sort_period > 0 ? (int)std::ceil((1.6 * est + 64.0) / 64.0) * 64 : lds_max;
+            hc = (int)std::min<int64_t>(hc, (boxes[s].n_cap + 63) / 64 * 64);
+        }
+        hc = std::min(std::max(hc, 64), lds_max);
+        Lo.halo_cap = std::max(Lo.halo_cap, hc);
     }
     for (int s = 0; s < n_sys; ++s) {
         const hoomd_params &q = p[s];
@@ -198,7 +215,9 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.pos_alt = take(sizeof(double4) * rows);
     Lo.vel_alt = take(sizeof(double4) * rows);
     Lo.xbuild = take(sizeof(double4) * rows);
-    Lo.nlist = take(sizeof(int32_t) * (size_t)std::max<int64_t>(nl, 1));
+    Lo.nlist = take(sizeof(uint16_t) * (size_t)std::max<int64_t>(nl, 1));
+    Lo.halo = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1) * Lo.halo_cap);
+    Lo.halo_n = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
     Lo.nn = take(sizeof(int32_t) * rows);
     Lo.cell_count = take(sizeof(int32_t) * (size_t)cell);
     Lo.cell_size = take(sizeof(int32_t) * (size_t)cell);
@@ -227,6 +246,7 @@ struct hoomd_ctx {
     int mixed;
     int pair_uniform;  // common Pair of all systems, or -1
     bool built;        // a neighbour list exists for the current rows
+    int64_t ghosts;    // ghost rows appended over all systems (no sorting then)
     int tpp_nlist, block_nlist, tpp_force, block_force;
     int last_log_rows;
     uint64_t steps_done;
@@ -249,15 +269,15 @@ void default_tuning(hoomd_ctx *c)
 {
     // neighbours per particle and particles per CU decide the lane count;
     // the autotuner refines these on the live state
+    // the build always runs 4 lanes per row, one 64-row tile per 256-thread
+    // workgroup; the force pass runs W lanes per row, one tile per 64 W
+    // threads
     const double per_cu = (double)c->lay.tiles_local * 64.0 / 256.0;
-    c->tpp_nlist = per_cu > 4096 ? 4 : 8;
-    c->tpp_force = per_cu > 4096 ? 2 : (per_cu > 512 ? 4 : 8);
+    c->tpp_nlist = 4;
     c->block_nlist = 256;
-    c->block_force = 256;
-    if (c->prm[0].tpp_nlist > 0) c->tpp_nlist = c->prm[0].tpp_nlist;
+    c->tpp_force = per_cu > 2048 ? 4 : 8;
     if (c->prm[0].tpp_force > 0) c->tpp_force = c->prm[0].tpp_force;
-    if (c->prm[0].block_nlist > 0) c->block_nlist = c->prm[0].block_nlist;
-    if (c->prm[0].block_force > 0) c->block_force = c->prm[0].block_force;
+    c->block_force = 64 * c->tpp_force;
 }
 
 bool pow2_le(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
@@ -358,7 +378,10 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.cell_count = ws_ptr<int32_t>(c, lay.cell_count);
     L.cell_size = ws_ptr<int32_t>(c, lay.cell_size);
     L.cell_idx = ws_ptr<int32_t>(c, lay.cell_idx);
-    L.nlist = ws_ptr<int32_t>(c, lay.nlist);
+    L.nlist = ws_ptr<uint16_t>(c, lay.nlist);
+    L.halo = ws_ptr<int32_t>(c, lay.halo);
+    L.halo_n = ws_ptr<int32_t>(c, lay.halo_n);
+    L.halo_cap = lay.halo_cap;
     L.nn = ws_ptr<int32_t>(c, lay.nn);
     L.nlist_cap = lay.nlist_cap;
     L.xbuild = ws_ptr<double4>(c, lay.xbuild);
@@ -374,9 +397,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     c->sortb = make_sort_buffers(c->ws + lay.sort_ws, lay.rows);
     c->ghostb = make_ghost_buffers(c->ws + lay.ghost_ws, lay.rows, n_sys);
     default_tuning(c);
-    if (!pow2_le(c->tpp_nlist, 64) || !pow2_le(c->tpp_force, 32) || c->block_nlist % 64 ||
-        c->block_force % 64 || c->block_nlist < 64 || c->block_force < 64 ||
-        c->block_nlist > 1024 || c->block_force > 256) {
+    if (!pow2_le(c->tpp_force, 16)) {
         delete c;
         return HOOMD_E_ARG;
     }
@@ -463,8 +484,16 @@ int build_nlist(hoomd_ctx *c, int32_t force_rebuild)
 {
     if (!c) return HOOMD_E_ARG;
     int32_t *flag = flag_ptr(c, 2);
-    const double4 *pos = reinterpret_cast<const double4 *>(c->arr.pos);
+    double4 *pos = reinterpret_cast<double4 *>(c->arr.pos);
     if (force_rebuild || !c->built) {
+        // with spatial sorting enabled, every full build starts from Morton
+        // order so that the 64-row tiles are compact clusters
+        if (c->prm[0].sort_period > 0 && c->ghosts == 0) {
+            if (queue_morton_sort(c->L, c->sortb, pos, reinterpret_cast<double4 *>(c->arr.vel), c->arr.tag,
+                                  ws_ptr<double4>(c, c->lay.pos_alt), ws_ptr<double4>(c, c->lay.vel_alt)))
+                return HOOMD_E_DEVICE;
+            if (c->lay.bond_cap > 0) launch_rtag(c->L, c->arr.tag);
+        }
         launch_set_flag(c->L, flag, 1);
     } else {
         launch_set_flag(c->L, flag, 0);
@@ -617,6 +646,7 @@ int unpack_ghosts(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, u
     u.tag = c->arr.tag;
     if (queue_ghost_unpack(c->stream, u)) return HOOMD_E_DEVICE;
     if (mode == HOOMD_GHOST_SELECT) {
+        c->ghosts += (int64_t)(S.n_local + n_recv) - S.n_total;
         S.n_total = (int32_t)(S.n_local + n_recv);
         HIP_OK(hipMemcpyAsync(ws_ptr<SysDev>(c, c->lay.sysdev) + sys, &S, sizeof(SysDev),
                               hipMemcpyHostToDevice, c->stream));
@@ -674,13 +704,17 @@ int hoomd_get_layout(hoomd_ctx *c, int32_t sys, hoomd_layout *out)
     const SysDev &S = c->lay.sys[sys];
     out->nlist = c->L.nlist + S.nl0;
     out->nn = c->L.nn + S.row0;
+    out->halo = c->L.halo + (int64_t)S.tile0 * c->lay.halo_cap;
+    out->halo_n = c->L.halo_n + S.tile0;
     out->cell_idx = c->L.cell_idx + S.cell0 * c->lay.cell_cap;
     out->cell_size = c->L.cell_size + S.cell0;
     out->nlist_cap = c->lay.nlist_cap;
     out->cell_cap = c->lay.cell_cap;
+    out->halo_cap = c->lay.halo_cap;
     for (int a = 0; a < 3; ++a) out->bins[a] = S.bins[a];
     out->row_offset = S.row0;
     out->cell_offset = S.cell0;
+    out->tile_offset = S.tile0;
     return HOOMD_OK;
 }
 
@@ -711,43 +745,27 @@ int hoomd_autotune(hoomd_ctx *c, int32_t do_tune, hoomd_tuning *out)
 {
     if (!c) return HOOMD_E_ARG;
     if (do_tune) {
+        // a current neighbour list, then the force pass over lanes per row
+        // (the workgroup is 64 rows x W lanes)
+        int rc = build_nlist(c, 0);
+        if (rc) return rc;
         const double4 *pos = reinterpret_cast<const double4 *>(c->arr.pos);
-        int32_t *flag = flag_ptr(c, 2);
-        launch_set_flag(c->L, flag, 1);
-        c->L.flag = flag;
-        launch_bin(c->L, pos);
-        launch_cell_sort(c->L);
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
-        // neighbour list: lanes per particle x block size
         float best = 1e30f;
-        int bw = c->tpp_nlist, bb = c->block_nlist;
-        for (int w = 1; w <= 64; w <<= 1)
-            for (int b = 64; b <= 512; b <<= 1) {
-                const float t = median5(c, [&] { launch_nlist(c->L, pos, c->arr.tag, w, b); }, e0, e1);
-                if (t < best) { best = t; bw = w; bb = b; }
-            }
-        c->tpp_nlist = bw;
-        c->block_nlist = bb;
-        launch_nlist(c->L, pos, c->arr.tag, bw, bb);
-        c->built = true;
-        // forces
-        best = 1e30f;
-        bw = c->tpp_force;
-        bb = c->block_force;
+        int bw = c->tpp_force;
         ForceLaunch F = base_force(c);
         F.pos = pos;
         F.vel = reinterpret_cast<const double4 *>(c->arr.vel);
         F.vel_out = reinterpret_cast<double4 *>(c->arr.vel);
         F.mode = MODE_FORCE;
-        for (int w = 1; w <= 32; w <<= 1)
-            for (int b = 64; b <= 256; b <<= 1) {
-                const float t = median5(c, [&] { launch_force(c->L, F, w, b); }, e0, e1);
-                if (t < best) { best = t; bw = w; bb = b; }
-            }
+        for (int w = 1; w <= 16; w <<= 1) {
+            const float t = median5(c, [&] { launch_force(c->L, F, w, 64 * w); }, e0, e1);
+            if (t < best) { best = t; bw = w; }
+        }
         c->tpp_force = bw;
-        c->block_force = bb;
+        c->block_force = 64 * bw;
         HIP_OK(hipEventDestroy(e0));
         HIP_OK(hipEventDestroy(e1));
         HIP_OK(hipStreamSynchronize(c->stream));
@@ -806,6 +824,7 @@ const char *hoomd_strerror(int code)
     case HOOMD_E_BOND_STRETCH: return "bond stretched beyond R0";
     case HOOMD_E_NAN: return "non-finite force";
     case HOOMD_E_DANGEROUS_BUILD: return "dangerous neighbour-list build";
+    case HOOMD_E_HALO_OVERFLOW: return "tile halo capacity exceeded";
     default: return "unknown status";
     }
 }

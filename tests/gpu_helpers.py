@@ -23,14 +23,20 @@ def min_image_diff(a, b, L):
 
 
 def neighbor_sets_equal(orc, ctx, pos, L, r_cut, r_buff, which=None, bonds=None, sys=0):
-    """Compare the GPU rows (as sets) with the oracle's brute-force sets."""
+    """Compare the GPU rows (as sets of tags) with the oracle's brute-force
+    sets over the input positions (input order = tag order).  `which` lists
+    tags to check."""
     nn, rows = ctx.neighbor_rows(sys)
-    idx = np.arange(len(rows)) if which is None else np.asarray(which)
+    o, n = ctx.offsets[sys], ctx.n_local[sys]
+    tag = ctx.tag[o:o + n].cpu().numpy().astype(np.int64)
+    row_of = np.empty(n, dtype=np.int64)
+    row_of[tag] = np.arange(n)
+    idx = np.arange(n) if which is None else np.asarray(which)
     off, ref = orc.neighbors(pos, L, r_cut, r_buff, which=idx, bonds=bonds)
     bad = []
-    for q, i in enumerate(idx):
-        got = np.sort(rows[i])
+    for q, t in enumerate(idx):
+        got = np.sort(tag[rows[row_of[t]]])
         want = ref[off[q]:off[q + 1]]
         if not np.array_equal(got, want):
-            bad.append(int(i))
+            bad.append(int(t))
     return bad

@@ -129,7 +129,8 @@ def test_dpd_short_run_fp64(orc, B):
     s = inputs.dpd_fluid(3000, 31, 32)
     prm = [25.0, 4.5, 1.0, 1.0, 0.02, 33]
     xo, vo, Fo, th, st = orc.run_nve("dpd", s.pos, s.vel, s.L, prm, 0.02, 5, tag=s.tag, t0=100)
-    p = B.ModelParams(precision=0, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=33)
+    p = B.ModelParams(precision=0, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=33,
+                      sort_period=1000)
     c = B.Context([p], [dict(pos=s.pos, vel=s.vel, L=s.L)])
     c.step(100, 5)
     c.check()

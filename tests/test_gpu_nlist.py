@@ -35,13 +35,26 @@ def test_cell_list_matches_stable_counting_sort(orc, B):
         assert np.array_equal(members[c], idx[start[c]:start[c + 1]]), c
 
 
-@pytest.mark.parametrize("w", [1, 2, 4, 8, 16, 32, 64])
-def test_neighbor_sets_exact_all_lane_counts(orc, B, w):
+@pytest.mark.parametrize("sort_period,halo_cap", [(0, 0), (1, 0), (0, 2048), (1, 1024)])
+def test_neighbor_sets_exact(orc, B, sort_period, halo_cap):
+    """Unsorted and Morton-sorted rows, default and explicit halo capacity."""
     s = inputs.lj_small()
-    ctx = _ctx(B, s.pos, s.vel, s.L, tpp_nlist=w, block_nlist=256)
+    ctx = _ctx(B, s.pos, s.vel, s.L, sort_period=sort_period, halo_cap=halo_cap)
     ctx.build_nlist(True)
     ctx.check()
     assert neighbor_sets_equal(orc, ctx, s.pos, s.L, 2.5, 0.4) == []
+    # every halo entry is used by some row of its tile and no row repeats one
+    nn, rows = ctx.neighbor_rows()
+    for r in rows:
+        assert len(np.unique(r)) == len(r)
+
+
+def test_halo_overflow_is_reported(B):
+    s = inputs.lj_small()
+    ctx = _ctx(B, s.pos, s.vel, s.L, halo_cap=64)
+    ctx.build_nlist(True)
+    code, req = ctx.sync_status()
+    assert code == 11 and req > 64
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 65, 500, 4097])
