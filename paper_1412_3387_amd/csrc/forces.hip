@@ -122,6 +122,13 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     __syncthreads();
 
     const double4 xi = a.pos[i];
+    // the row's own position, moved to the same frame as the halo images
+    double xs = xi.x, ys = xi.y, zs = xi.z;
+    if (!per_pair) {
+        xs = __fma_rn(-S.L[0], rint((xs - xref.x) * S.invL[0]), xs);
+        ys = __fma_rn(-S.L[1], rint((ys - xref.y) * S.invL[1]), ys);
+        zs = __fma_rn(-S.L[2], rint((zs - xref.z) * S.invL[2]), zs);
+    }
     double4 vi;
     if constexpr (POT == PAIR_DPD) vi = a.vel[i];
     int32_t ti = 0;
@@ -139,9 +146,9 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
 #pragma unroll 4
     for (int k = sl; k < n; k += W) {
         const int h = row[(int64_t)k * kTile];
-        double dx = xi.x - hx[h];
-        double dy = xi.y - hy[h];
-        double dz = xi.z - hz[h];
+        double dx = xs - hx[h];
+        double dy = ys - hy[h];
+        double dz = zs - hz[h];
         if (per_pair) {
             dx = min_image(dx, S.L[0], S.invL[0]);
             dy = min_image(dy, S.L[1], S.invL[1]);

@@ -9,8 +9,9 @@
 // in arbitrary order.  It also resets the counters for the next build.
 //
 // Neighbour list: one workgroup per tile of 64 consecutive rows (Morton
-// ordered rows make a tile a compact cluster).  The workgroup
-//   1. finds the box of cells that covers the stencils of all its rows,
+// ordered rows make a tile one or a few compact clusters).  The workgroup
+//   1. collects the stencil cells of all its rows and sorts out the
+//      distinct ones (bitonic sort in LDS), so any tile shape works,
 //   2. stages the members of those cells (positions and row numbers) in LDS,
 //      a chunk at a time,
 //   3. lets W = 4 lanes per particle stride over the members of the
@@ -26,7 +27,6 @@
 //
 // Row layout (uint16): entry k of row r of a system lives at
 // nl0 + (r / 64) * cap * 64 + k * 64 + r % 64.
-#include "device.h"
 #include "launch.h"
 
 namespace md {
@@ -34,8 +34,7 @@ namespace md {
 constexpr int kBuildThreads = 256;   // 64 rows x 4 lanes
 constexpr int kBuildW = 4;
 constexpr int kChunk = 512;          // members staged at once
-constexpr int kBoxMax = 512;         // cells in a tile's box
-constexpr int kSlotMax = 16384;      // members in a tile's box
+constexpr int kSlotMax = 16384;      // members of a tile's stencil cells
 constexpr int kRebuildGrid = 2048;   // blocks of the grid-stride rebuild kernels
 
 // ---------------------------------------------------------------------------
@@ -142,17 +141,64 @@ __device__ __forceinline__ int wrap_rel(int d, int bins)
     return d;
 }
 
+constexpr int kKeys = 2048;          // 64 rows x 27 stencil cells, padded
+
 struct BuildShared {
     double cx[kChunk], cy[kChunk], cz[kChunk];
     int32_t cj[kChunk];
-    int32_t bstart[kBoxMax + 1];
-    int32_t bcell[kBoxMax];
+    int32_t keys[kKeys];              // stencil cells, then distinct cells
+    int32_t ustart[kKeys + 1];        // first slot of each distinct cell
     uint32_t used[kSlotMax / 32];
     int32_t wpre[kSlotMax / 32 + 1];
     int32_t scan[kBuildThreads];
-    int32_t ext[6];       // min rel (3), max rel (3)
-    int32_t info[8];      // box lo (3), dims (3), nbox, nslot
+    int32_t ext[6];                   // min / max cell offset from the first row
+    int32_t info[4];                  // distinct cells, per-pair image flag
 };
+
+// Exclusive block scan of n <= 8 * kBuildThreads values held in LDS `a`
+// (in place); returns the total.  Uses sh.scan.
+__device__ __forceinline__ int block_scan8(int32_t *a, int n, int32_t *scan)
+{
+    const int tid = threadIdx.x;
+    const int b = 8 * tid;
+    int v[8];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k] = b + k < n ? a[b + k] : 0;
+        sum += v[k];
+    }
+    scan[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kBuildThreads; off <<= 1) {
+        const int add = tid >= off ? scan[tid - off] : 0;
+        __syncthreads();
+        scan[tid] += add;
+        __syncthreads();
+    }
+    int run = tid > 0 ? scan[tid - 1] : 0;
+    const int total = scan[kBuildThreads - 1];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (b + k < n) {
+            a[b + k] = run;
+            run += v[k];
+        }
+    __syncthreads();
+    return total;
+}
+
+// Index of the largest entry <= x in the ascending array a[0..n).
+__device__ __forceinline__ int upper_idx(const int32_t *a, int n, int x)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 template <bool EXCL>
 __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
@@ -165,6 +211,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 {
     if (*flag == 0) return;
     __shared__ BuildShared sh;
+    __shared__ int32_t ucount[kKeys];   // members of each distinct cell, scanned in place
     constexpr int W = kBuildW;
     constexpr int P = kWave / W;
     const int tid = threadIdx.x;
@@ -189,99 +236,96 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
         ci[0] = cell_coord(xi.x, S.lo[0], S.scale[0], S.bins[0]);
         ci[1] = cell_coord(xi.y, S.lo[1], S.scale[1], S.bins[1]);
         ci[2] = cell_coord(xi.z, S.lo[2], S.scale[2], S.bins[2]);
-        // reference cell: the tile's first row
         const double4 x0 = pos[S.row0 + r0];
         int c0[3];
         c0[0] = cell_coord(x0.x, S.lo[0], S.scale[0], S.bins[0]);
         c0[1] = cell_coord(x0.y, S.lo[1], S.scale[1], S.bins[1]);
         c0[2] = cell_coord(x0.z, S.lo[2], S.scale[2], S.bins[2]);
-        int rel[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) rel[a] = S.per[a] ? wrap_rel(ci[a] - c0[a], S.bins[a]) : ci[a] - c0[a];
 
-        // ---- 1. box of cells --------------------------------------------
+        // ---- 1. distinct stencil cells of the tile ---------------------------
         if (tid < 3) {
             sh.ext[tid] = INT32_MAX;
             sh.ext[3 + tid] = INT32_MIN;
         }
+        const int nst = S.nst[0] * S.nst[1] * S.nst[2];
+        for (int k = sl; k < 27; k += W) {
+            int key = INT32_MAX;
+            if (active && k < nst) {
+                const int ox = k % S.nst[0], oy = (k / S.nst[0]) % S.nst[1], oz = k / (S.nst[0] * S.nst[1]);
+                int cc[3] = {ci[0] + S.st[0][ox], ci[1] + S.st[1][oy], ci[2] + S.st[2][oz]};
+                bool inside = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (S.per[a]) cc[a] = cc[a] < 0 ? cc[a] + S.bins[a] : (cc[a] >= S.bins[a] ? cc[a] - S.bins[a] : cc[a]);
+                    else inside = inside && cc[a] >= 0 && cc[a] < S.bins[a];
+                }
+                if (inside) key = (cc[2] * S.bins[1] + cc[1]) * S.bins[0] + cc[0];
+            }
+            sh.keys[t * 27 + k] = key;
+        }
+        for (int k = 64 * 27 + tid; k < kKeys; k += kBuildThreads) sh.keys[k] = INT32_MAX;
         __syncthreads();
         if (active && sl == 0) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                atomicMin(&sh.ext[a], rel[a]);
-                atomicMax(&sh.ext[3 + a], rel[a]);
+                const int d = ci[a] - c0[a];
+                const int rel = S.per[a] ? wrap_rel(d, S.bins[a]) : d;
+                atomicMin(&sh.ext[a], rel);
+                atomicMax(&sh.ext[3 + a], rel);
             }
         }
-        __syncthreads();
-        if (tid == 0) {
-            int nbox = 1;
-            // one periodic image per halo entry serves every row of the tile
-            // while tile extent + list radius + drift stays below half a box
-            int pp = 0;
-            for (int a = 0; a < 3; ++a)
-                if (S.per[a] && (double)(sh.ext[3 + a] - sh.ext[a] + 3) * (S.L[a] / S.bins[a]) >= 0.5 * S.L[a])
-                    pp = 1;
-            sh.info[7] = pp;
-            for (int a = 0; a < 3; ++a) {
-                int lo = sh.ext[a] - 1, hi = sh.ext[3 + a] + 1;
-                if (S.per[a]) {
-                    if (hi - lo + 1 >= S.bins[a]) {
-                        lo = -c0[a];
-                        hi = S.bins[a] - 1 - c0[a];
+        // bitonic sort of the keys
+        for (int k = 2; k <= kKeys; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int e = tid; e < kKeys / 2; e += kBuildThreads) {
+                    const int a = ((e & ~(j - 1)) << 1) | (e & (j - 1));
+                    const int b = a | j;
+                    const int32_t ka = sh.keys[a], kb = sh.keys[b];
+                    if ((ka > kb) == ((a & k) == 0)) {
+                        sh.keys[a] = kb;
+                        sh.keys[b] = ka;
                     }
-                } else {
-                    lo = lo > -c0[a] ? lo : -c0[a];
-                    hi = hi < S.bins[a] - 1 - c0[a] ? hi : S.bins[a] - 1 - c0[a];
                 }
-                sh.info[a] = lo;
-                sh.info[3 + a] = hi - lo + 1;
-                nbox *= hi - lo + 1;
+                __syncthreads();
             }
-            sh.info[6] = nbox;
         }
+        // distinct keys: flag first occurrences, scan, compact
+        for (int k = tid; k < kKeys; k += kBuildThreads)
+            ucount[k] = (sh.keys[k] != INT32_MAX && (k == 0 || sh.keys[k] != sh.keys[k - 1])) ? 1 : 0;
         __syncthreads();
-        const int bl[3] = {sh.info[0], sh.info[1], sh.info[2]};
-        const int D[3] = {sh.info[3], sh.info[4], sh.info[5]};
-        const int nbox = sh.info[6];
-        if (nbox > kBoxMax) {
-            if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nbox);
-            if (active && sl == 0) nn[i] = 0;
-            if (tid == 0) halo_n[tile] = 0;
-            __syncthreads();
-            continue;
-        }
-        // ---- 2. member counts of the box cells and their prefix ------------
-        for (int b = tid; b < nbox; b += kBuildThreads) {
-            const int bx = b % D[0], by = (b / D[0]) % D[1], bz = b / (D[0] * D[1]);
-            int cc[3] = {c0[0] + bl[0] + bx, c0[1] + bl[1] + by, c0[2] + bl[2] + bz};
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                if (S.per[a]) cc[a] = ((cc[a] % S.bins[a]) + S.bins[a]) % S.bins[a];
-            const int pc = (cc[2] * S.bins[1] + cc[1]) * S.bins[0] + cc[0];
-            sh.bcell[b] = pc;
-            sh.bstart[b + 1] = cell_size[S.cell0 + pc];
-        }
-        if (tid == 0) sh.bstart[0] = 0;
-        __syncthreads();
-        // inclusive scan of bstart[1..nbox] (nbox <= 512 = 2 per thread)
         {
-            const int b0 = 2 * tid;
-            int v0 = b0 < nbox ? sh.bstart[b0 + 1] : 0;
-            int v1 = b0 + 1 < nbox ? sh.bstart[b0 + 2] : 0;
-            sh.scan[tid] = v0 + v1;
+            int flags8[8];
+            const int b = 8 * tid;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) flags8[k] = ucount[b + k];
             __syncthreads();
-            for (int off = 1; off < kBuildThreads; off <<= 1) {
-                const int add = tid >= off ? sh.scan[tid - off] : 0;
-                __syncthreads();
-                sh.scan[tid] += add;
-                __syncthreads();
+            const int nu = block_scan8(ucount, kKeys, sh.scan);
+            // ucount[k] now holds the distinct index of key k if flagged
+            int32_t kv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) kv[k] = sh.keys[b + k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (flags8[k]) sh.keys[ucount[b + k]] = kv[k];
+            if (tid == 0) {
+                sh.info[0] = nu;
+                int pp = 0;
+                for (int a = 0; a < 3; ++a)
+                    if (S.per[a] &&
+                        (double)(sh.ext[3 + a] - sh.ext[a] + 3) * (S.L[a] / S.bins[a]) >= 0.5 * S.L[a])
+                        pp = 1;
+                sh.info[1] = pp;
             }
-            const int before = tid > 0 ? sh.scan[tid - 1] : 0;
-            if (b0 < nbox) sh.bstart[b0 + 1] = before + v0;
-            if (b0 + 1 < nbox) sh.bstart[b0 + 2] = before + v0 + v1;
             __syncthreads();
         }
-        const int nslot = sh.bstart[nbox];
+        const int nu = sh.info[0];
+        // member counts of the distinct cells and their prefix
+        for (int u = tid; u < nu; u += kBuildThreads) ucount[u] = cell_size[S.cell0 + sh.keys[u]];
+        __syncthreads();
+        const int nslot = block_scan8(ucount, nu, sh.scan);
+        for (int u = tid; u < nu; u += kBuildThreads) sh.ustart[u] = ucount[u];
+        if (tid == 0) sh.ustart[nu] = nslot;
         if (nslot > kSlotMax) {
             if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nslot);
             if (active && sl == 0) nn[i] = 0;
@@ -291,7 +335,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
         }
         for (int q = tid; q < (nslot + 31) / 32; q += kBuildThreads) sh.used[q] = 0u;
 
-        // ---- 3. stencil scan, chunk by chunk --------------------------------
+        // ---- 2./3. stage chunks, scan each row's stencil ------------------------
         int32_t part[kMaxBondCap];
         if constexpr (EXCL) {
 #pragma unroll
@@ -301,23 +345,16 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
                 for (int b = 0; b < S.bond_cap && b < kMaxBondCap; ++b) part[b] = partners[prow + b];
             }
         }
-        int bi[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) bi[a] = rel[a] - bl[a];
         const int64_t rowbase = S.nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
         const double rl2 = S.rl2;
+        const bool few[3] = {S.per[0] && S.bins[0] < 3, S.per[1] && S.bins[1] < 3, S.per[2] && S.bins[2] < 3};
         int ntot = 0;
         for (int q0 = 0; q0 < nslot; q0 += kChunk) {
             const int q1 = q0 + kChunk < nslot ? q0 + kChunk : nslot;
             __syncthreads();
             for (int q = q0 + tid; q < q1; q += kBuildThreads) {
-                int lo = 0, hi = nbox;  // bstart[lo] <= q < bstart[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sh.bstart[mid] <= q) lo = mid;
-                    else hi = mid;
-                }
-                const int32_t j = cell_idx[(S.cell0 + sh.bcell[lo]) * cell_cap + (q - sh.bstart[lo])];
+                const int u = upper_idx(sh.ustart, nu, q);
+                const int32_t j = cell_idx[(S.cell0 + sh.keys[u]) * cell_cap + (q - sh.ustart[u])];
                 const double4 xj = pos[j];
                 sh.cx[q - q0] = xj.x;
                 sh.cy[q - q0] = xj.y;
@@ -326,101 +363,74 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
             }
             __syncthreads();
             if (!active) continue;
-            for (int oz = 0; oz < S.nst[2]; ++oz) {
-                const int dz = S.st[2][oz];
-                int bz = bi[2] + dz;
-                double mz = 0.0;
-                if (S.per[2]) {
-                    if (D[2] == S.bins[2]) bz = (bz % D[2] + D[2]) % D[2];
-                    const int pcz = ci[2] + dz;
-                    mz = pcz < 0 ? 1.0 : (pcz >= S.bins[2] ? -1.0 : 0.0);
-                } else if (bz < 0 || bz >= D[2]) {
-                    continue;
-                }
-                for (int oy = 0; oy < S.nst[1]; ++oy) {
-                    const int dy = S.st[1][oy];
-                    int by = bi[1] + dy;
-                    double my = 0.0;
-                    if (S.per[1]) {
-                        if (D[1] == S.bins[1]) by = (by % D[1] + D[1]) % D[1];
-                        const int pcy = ci[1] + dy;
-                        my = pcy < 0 ? 1.0 : (pcy >= S.bins[1] ? -1.0 : 0.0);
-                    } else if (by < 0 || by >= D[1]) {
-                        continue;
-                    }
-                    for (int ox = 0; ox < S.nst[0]; ++ox) {
-                        const int dx = S.st[0][ox];
-                        int bx = bi[0] + dx;
-                        double mx = 0.0;
-                        if (S.per[0]) {
-                            if (D[0] == S.bins[0]) bx = (bx % D[0] + D[0]) % D[0];
-                            const int pcx = ci[0] + dx;
-                            mx = pcx < 0 ? 1.0 : (pcx >= S.bins[0] ? -1.0 : 0.0);
-                        } else if (bx < 0 || bx >= D[0]) {
-                            continue;
-                        }
-                        const int b = (bz * D[1] + by) * D[0] + bx;
-                        int a0 = sh.bstart[b], a1 = sh.bstart[b + 1];
-                        a0 = a0 > q0 ? a0 : q0;
-                        a1 = a1 < q1 ? a1 : q1;
-                        for (int k0 = a0; k0 < a1; k0 += W) {
-                            const int q = k0 + sl;
-                            bool hit = false;
-                            if (q < a1) {
-                                const int32_t j = sh.cj[q - q0];
-                                if (j != (int32_t)i) {
-                                    double ddx = sh.cx[q - q0] - xi.x;
-                                    double ddy = sh.cy[q - q0] - xi.y;
-                                    double ddz = sh.cz[q - q0] - xi.z;
-                                    // bins < 3: several images share a cell; take the nearest
-                                    ddx = S.bins[0] < 3 && S.per[0] ? min_image(ddx, S.L[0], S.invL[0]) : __fma_rn(-S.L[0], mx, ddx);
-                                    ddy = S.bins[1] < 3 && S.per[1] ? min_image(ddy, S.L[1], S.invL[1]) : __fma_rn(-S.L[1], my, ddy);
-                                    ddz = S.bins[2] < 3 && S.per[2] ? min_image(ddz, S.L[2], S.invL[2]) : __fma_rn(-S.L[2], mz, ddz);
-                                    hit = norm2_exact(ddx, ddy, ddz) < rl2;
-                                    if constexpr (EXCL) {
-                                        if (hit) {
-                                            const int32_t tj = tag[j];
+            for (int k = 0; k < nst; ++k) {
+                const int ox = k % S.nst[0], oy = (k / S.nst[0]) % S.nst[1], oz = k / (S.nst[0] * S.nst[1]);
+                const int d[3] = {S.st[0][ox], S.st[1][oy], S.st[2][oz]};
+                int cc[3];
+                double m[3];
+                bool inside = true;
 #pragma unroll
-                                            for (int e = 0; e < kMaxBondCap; ++e) hit = hit && (part[e] != tj);
-                                        }
-                                    }
+                for (int a = 0; a < 3; ++a) {
+                    cc[a] = ci[a] + d[a];
+                    m[a] = 0.0;
+                    if (S.per[a]) {
+                        // image of the neighbour cell across the periodic face
+                        if (cc[a] < 0) {
+                            cc[a] += S.bins[a];
+                            m[a] = 1.0;
+                        } else if (cc[a] >= S.bins[a]) {
+                            cc[a] -= S.bins[a];
+                            m[a] = -1.0;
+                        }
+                    } else {
+                        inside = inside && cc[a] >= 0 && cc[a] < S.bins[a];
+                    }
+                }
+                if (!inside) continue;
+                const int key = (cc[2] * S.bins[1] + cc[1]) * S.bins[0] + cc[0];
+                const int u = upper_idx(sh.keys, nu, key);
+                int a0 = sh.ustart[u], a1 = sh.ustart[u + 1];
+                a0 = a0 > q0 ? a0 : q0;
+                a1 = a1 < q1 ? a1 : q1;
+                for (int k0 = a0; k0 < a1; k0 += W) {
+                    const int q = k0 + sl;
+                    bool hit = false;
+                    if (q < a1) {
+                        const int32_t j = sh.cj[q - q0];
+                        if (j != (int32_t)i) {
+                            double ddx = sh.cx[q - q0] - xi.x;
+                            double ddy = sh.cy[q - q0] - xi.y;
+                            double ddz = sh.cz[q - q0] - xi.z;
+                            // fewer than 3 cells: several images share a cell, take the nearest
+                            ddx = few[0] ? min_image(ddx, S.L[0], S.invL[0]) : __fma_rn(-S.L[0], m[0], ddx);
+                            ddy = few[1] ? min_image(ddy, S.L[1], S.invL[1]) : __fma_rn(-S.L[1], m[1], ddy);
+                            ddz = few[2] ? min_image(ddz, S.L[2], S.invL[2]) : __fma_rn(-S.L[2], m[2], ddz);
+                            hit = norm2_exact(ddx, ddy, ddz) < rl2;
+                            if constexpr (EXCL) {
+                                if (hit) {
+                                    const int32_t tj = tag[j];
+#pragma unroll
+                                    for (int e = 0; e < kMaxBondCap; ++e) hit = hit && (part[e] != tj);
                                 }
                             }
-                            const uint64_t mask = __ballot(hit) & seg;
-                            if (hit) {
-                                const int p = ntot + __popcll(mask & below);
-                                if (p < cap) nlist[rowbase + (int64_t)p * kTile] = (uint16_t)q;
-                                atomicOr(&sh.used[q >> 5], 1u << (q & 31));
-                            }
-                            ntot += __popcll(mask);
                         }
                     }
+                    const uint64_t mask = __ballot(hit) & seg;
+                    if (hit) {
+                        const int p = ntot + __popcll(mask & below);
+                        if (p < cap) nlist[rowbase + (int64_t)p * kTile] = (uint16_t)q;
+                        atomicOr(&sh.used[q >> 5], 1u << (q & 31));
+                    }
+                    ntot += __popcll(mask);
                 }
             }
         }
         __syncthreads();
         // ---- 4. halo numbering and row rewrite ---------------------------------
         const int nwords = (nslot + 31) / 32;
-        {
-            // exclusive prefix of popcounts over nwords (<= 512) words
-            const int w0 = 2 * tid;
-            const int v0 = w0 < nwords ? __popc(sh.used[w0]) : 0;
-            const int v1 = w0 + 1 < nwords ? __popc(sh.used[w0 + 1]) : 0;
-            sh.scan[tid] = v0 + v1;
-            __syncthreads();
-            for (int off = 1; off < kBuildThreads; off <<= 1) {
-                const int add = tid >= off ? sh.scan[tid - off] : 0;
-                __syncthreads();
-                sh.scan[tid] += add;
-                __syncthreads();
-            }
-            const int before = tid > 0 ? sh.scan[tid - 1] : 0;
-            if (w0 < nwords) sh.wpre[w0] = before;
-            if (w0 + 1 < nwords) sh.wpre[w0 + 1] = before + v0;
-            if (tid == kBuildThreads - 1) sh.wpre[nwords] = sh.scan[tid];
-            __syncthreads();
-        }
-        const int nhalo = sh.wpre[nwords];
+        for (int q = tid; q < nwords; q += kBuildThreads) sh.wpre[q] = __popc(sh.used[q]);
+        __syncthreads();
+        const int nhalo = block_scan8(sh.wpre, nwords, sh.scan);
         if (nhalo > halo_cap) {
             if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nhalo);
             if (active && sl == 0) nn[i] = 0;
@@ -433,17 +443,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
         for (int q = tid; q < nslot; q += kBuildThreads) {
             const uint32_t word = sh.used[q >> 5];
             if (word & (1u << (q & 31))) {
-                int lo = 0, hi = nbox;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sh.bstart[mid] <= q) lo = mid;
-                    else hi = mid;
-                }
+                const int u = upper_idx(sh.ustart, nu, q);
                 const int h = sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u));
-                hl[h] = cell_idx[(S.cell0 + sh.bcell[lo]) * cell_cap + (q - sh.bstart[lo])];
+                hl[h] = cell_idx[(S.cell0 + sh.keys[u]) * cell_cap + (q - sh.ustart[u])];
             }
         }
-        if (tid == 0) halo_n[tile] = sh.info[7] ? (int32_t)((uint32_t)nhalo | 0x80000000u) : nhalo;
+        if (tid == 0) halo_n[tile] = sh.info[1] ? (int32_t)((uint32_t)nhalo | 0x80000000u) : nhalo;
         __threadfence_block();
         __syncthreads();
         if (active) {
