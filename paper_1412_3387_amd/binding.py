@@ -361,7 +361,7 @@ class Context:
     def halo_sizes(self, sys: int = 0) -> np.ndarray:
         lay = self.layout(sys)
         tiles = (self.n_local[sys] + 63) // 64
-        return self._ws_view(lay.halo_n, tiles).cpu().numpy() & 0x7FFFFFFF
+        return self._ws_view(lay.halo_n, tiles).cpu().numpy() & 0xFFFF
 
     def cells(self, sys: int = 0):
         """(bins, sizes (ncell,), members list per cell in system-local rows)."""

@@ -69,14 +69,18 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
                                                 ForceLaunch a)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
+    // LDS: halo positions (and for DPD velocities and tags), then the tile's
+    // neighbour rows
     extern __shared__ double lds[];
     double *hx = lds;
     double *hy = hx + halo_cap;
     double *hz = hy + halo_cap;
-    double *hvx = hz + halo_cap;           // DPD only
+    double *hvx = hz + halo_cap;
     double *hvy = hvx + halo_cap;
     double *hvz = hvy + halo_cap;
-    int32_t *htag = reinterpret_cast<int32_t *>(hvz + halo_cap);
+    int32_t *htag = reinterpret_cast<int32_t *>(POT == PAIR_DPD ? hvz + halo_cap : hz + halo_cap);
+    uint16_t *srow = reinterpret_cast<uint16_t *>(POT == PAIR_DPD ? reinterpret_cast<double *>(htag + halo_cap)
+                                                                  : hz + halo_cap);
 
     constexpr int P = kWave / W;
     const int tid = threadIdx.x;
@@ -86,27 +90,38 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     const int sl = lane / P;
     const int tile = blockIdx.x;
     const int gw = tile * W + wv;
+    const int t = wv * P + pl;  // row slot in the tile
     if (a.flag_clear && tile == 0 && tid == 0) *a.flag_clear = 0;
     const int s = find_sys(tprefix, n_sys, tile);
     const SysDev &S = sys[s];
+    // per-system constants, held in registers for the whole launch
+    const double Lx = S.L[0], Ly = S.L[1], Lz = S.L[2];
+    const double iLx = S.invL[0], iLy = S.invL[1], iLz = S.invL[2];
+    const int64_t row0 = S.row0;
+    const int n_local = S.n_local;
+    const int64_t nl0 = S.nl0;
+    const double rc2 = S.rc2;
+    const T eps = (T)S.eps, sig2 = (T)S.sig2;
+    const double shift = S.shift;
     const int r0 = (tile - S.tile0) * kTile;
-    const int r = r0 + wv * P + pl;
-    const bool active = r < S.n_local;
-    const int64_t i = S.row0 + (active ? r : r0);
+    const int r = r0 + t;
+    const bool active = r < n_local;
+    const int64_t i = row0 + (active ? r : r0);
 
-    // ---- stage the halo -----------------------------------------------------
+    // ---- stage the halo and the rows -------------------------------------
     const int32_t hn = halo_n[tile];
-    const int nh = hn & 0x7FFFFFFF;
+    const int nh = hn & 0xFFFF;
+    const int kmax = (hn >> 16) & 0x7FFF;
     const bool per_pair = hn < 0;  // tile too wide for one image per halo entry
-    const double4 xref = a.pos[S.row0 + r0];
+    const double4 xref = a.pos[row0 + r0];
     const int32_t *hl = halo + (int64_t)tile * halo_cap;
     for (int h = tid; h < nh; h += W * kWave) {
         const int32_t j = hl[h];
         double4 x = a.pos[j];
         if (!per_pair) {
-            x.x = __fma_rn(-S.L[0], rint((x.x - xref.x) * S.invL[0]), x.x);
-            x.y = __fma_rn(-S.L[1], rint((x.y - xref.y) * S.invL[1]), x.y);
-            x.z = __fma_rn(-S.L[2], rint((x.z - xref.z) * S.invL[2]), x.z);
+            x.x = __fma_rn(-Lx, rint((x.x - xref.x) * iLx), x.x);
+            x.y = __fma_rn(-Ly, rint((x.y - xref.y) * iLy), x.y);
+            x.z = __fma_rn(-Lz, rint((x.z - xref.z) * iLz), x.z);
         }
         hx[h] = x.x;
         hy[h] = x.y;
@@ -119,15 +134,20 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
             htag[h] = a.tag[j];
         }
     }
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(nlist + nl0 + (int64_t)(r0 >> 6) * cap * kTile);
+        uint4 *dst = reinterpret_cast<uint4 *>(srow);
+        for (int e = tid; e < kmax * (kTile / 8); e += W * kWave) dst[e] = src[e];
+    }
     __syncthreads();
 
     const double4 xi = a.pos[i];
     // the row's own position, moved to the same frame as the halo images
     double xs = xi.x, ys = xi.y, zs = xi.z;
     if (!per_pair) {
-        xs = __fma_rn(-S.L[0], rint((xs - xref.x) * S.invL[0]), xs);
-        ys = __fma_rn(-S.L[1], rint((ys - xref.y) * S.invL[1]), ys);
-        zs = __fma_rn(-S.L[2], rint((zs - xref.z) * S.invL[2]), zs);
+        xs = __fma_rn(-Lx, rint((xs - xref.x) * iLx), xs);
+        ys = __fma_rn(-Ly, rint((ys - xref.y) * iLy), ys);
+        zs = __fma_rn(-Lz, rint((zs - xref.z) * iLz), zs);
     }
     double4 vi;
     if constexpr (POT == PAIR_DPD) vi = a.vel[i];
@@ -135,52 +155,67 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     if constexpr (POT == PAIR_DPD) ti = a.tag[i];
     int n = active ? nn[i] : 0;
     n = n < cap ? n : cap;
-    const uint16_t *row = nlist + S.nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
 
     T fx = 0, fy = 0, fz = 0;
     double e = 0.0, vir = 0.0;
-    const double rc2 = S.rc2;
-    const T eps = (T)S.eps, sig2 = (T)S.sig2;
-    const double shift = S.shift;
 
-#pragma unroll 4
-    for (int k = sl; k < n; k += W) {
-        const int h = row[(int64_t)k * kTile];
-        double dx = xs - hx[h];
-        double dy = ys - hy[h];
-        double dz = zs - hz[h];
-        if (per_pair) {
-            dx = min_image(dx, S.L[0], S.invL[0]);
-            dy = min_image(dy, S.L[1], S.invL[1]);
-            dz = min_image(dz, S.L[2], S.invL[2]);
+    // four neighbours per pass: all LDS reads of a pass issue before any use
+    constexpr int U = 4;
+    for (int k0 = sl; k0 < n; k0 += U * W) {
+        int hh[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kk = k0 + u * W;
+            ok[u] = kk < n;
+            hh[u] = ok[u] ? srow[kk * kTile + t] : 0;
         }
-        const double r2 = norm2_exact(dx, dy, dz);
-        if (r2 < rc2) {
-            T ff;
-            if constexpr (POT == PAIR_LJ || POT == PAIR_WCA) {
-                ff = lj_pair<T, LOG>(r2, eps, sig2, shift, e, vir);
-            } else {
-                if (r2 == 0.0) continue;
-                const T tr2 = (T)r2;
-                const T rr = tsqrt<T>(tr2);
-                const T rinv = recip<T>(rr);
-                const T w = (T)1 - rr * (T)S.dpd_inv_rc;
-                const T dvx = (T)(vi.x - hvx[h]), dvy = (T)(vi.y - hvy[h]), dvz = (T)(vi.z - hvz[h]);
-                const T rv = ((T)dx * dvx + (T)dy * dvy + (T)dz * dvz) * rinv;
-                const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)htag[h], S.dpd_seed, a.timestep);
-                const T u = (T)bits * (T)(1.0 / 16777216.0);
-                const T theta = (T)1.7320508075688772 * ((T)2 * u - (T)1);
-                const T mag = (T)S.dpd_A * w - (T)S.dpd_gamma * w * w * rv +
-                              (T)S.dpd_sigma * w * theta * (T)S.dpd_inv_sqrt_dt;
-                ff = mag * rinv;
-                if constexpr (LOG) {
-                    e += 0.5 * S.dpd_A * S.dpd_rc * (double)(w * w);
-                    vir += (double)(ff * tr2);
-                }
+        double dx[U], dy[U], dz[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dx[u] = xs - hx[hh[u]];
+            dy[u] = ys - hy[hh[u]];
+            dz[u] = zs - hz[hh[u]];
+        }
+        if (per_pair) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                dx[u] = min_image(dx[u], Lx, iLx);
+                dy[u] = min_image(dy[u], Ly, iLy);
+                dz[u] = min_image(dz[u], Lz, iLz);
             }
-            fx += ff * (T)dx;
-            fy += ff * (T)dy;
-            fz += ff * (T)dz;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double r2 = norm2_exact(dx[u], dy[u], dz[u]);
+            if (ok[u] && r2 < rc2) {
+                T ff;
+                if constexpr (POT == PAIR_LJ || POT == PAIR_WCA) {
+                    ff = lj_pair<T, LOG>(r2, eps, sig2, shift, e, vir);
+                } else {
+                    if (r2 == 0.0) continue;
+                    const int h = hh[u];
+                    const T tr2 = (T)r2;
+                    const T rr = tsqrt<T>(tr2);
+                    const T rinv = recip<T>(rr);
+                    const T w = (T)1 - rr * (T)S.dpd_inv_rc;
+                    const T dvx = (T)(vi.x - hvx[h]), dvy = (T)(vi.y - hvy[h]), dvz = (T)(vi.z - hvz[h]);
+                    const T rv = ((T)dx[u] * dvx + (T)dy[u] * dvy + (T)dz[u] * dvz) * rinv;
+                    const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)htag[h], S.dpd_seed, a.timestep);
+                    const T uu = (T)bits * (T)(1.0 / 16777216.0);
+                    const T theta = (T)1.7320508075688772 * ((T)2 * uu - (T)1);
+                    const T mag = (T)S.dpd_A * w - (T)S.dpd_gamma * w * w * rv +
+                                  (T)S.dpd_sigma * w * theta * (T)S.dpd_inv_sqrt_dt;
+                    ff = mag * rinv;
+                    if constexpr (LOG) {
+                        e += 0.5 * S.dpd_A * S.dpd_rc * (double)(w * w);
+                        vir += (double)(ff * tr2);
+                    }
+                }
+                fx += ff * (T)dx[u];
+                fy += ff * (T)dy[u];
+                fz += ff * (T)dz[u];
+            }
         }
     }
 
@@ -200,16 +235,16 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
         // bonds: FENE + WCA with partner rows indexed by tag
         if (S.bond_cap > 0) {
             const int32_t tg = a.tag[i];
-            const int64_t prow = (S.row0 + tg) * S.bond_cap;
+            const int64_t prow = (row0 + tg) * S.bond_cap;
             for (int b = 0; b < S.bond_cap; ++b) {
                 const int32_t tp = partners[prow + b];
                 if (tp < 0) continue;
-                const int64_t j = rtag[S.row0 + tp];
+                const int64_t j = rtag[row0 + tp];
                 const double4 xj = a.pos[j];
-                const double dx = min_image(xi.x - xj.x, S.L[0], S.invL[0]);
-                const double dy = min_image(xi.y - xj.y, S.L[1], S.invL[1]);
-                const double dz = min_image(xi.z - xj.z, S.L[2], S.invL[2]);
-                const double r2 = norm2_exact(dx, dy, dz);
+                const double ddx = min_image(xi.x - xj.x, Lx, iLx);
+                const double ddy = min_image(xi.y - xj.y, Ly, iLy);
+                const double ddz = min_image(xi.z - xj.z, Lz, iLz);
+                const double r2 = norm2_exact(ddx, ddy, ddz);
                 if (!(r2 < S.fene_R02)) {
                     latch(st, 8 /*BOND_STRETCH*/, 0);
                     continue;
@@ -224,9 +259,9 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
                     eb += e2;
                 }
                 if constexpr (LOG) vb = (double)(ff * (T)r2);
-                Fx += (double)(ff * (T)dx);
-                Fy += (double)(ff * (T)dy);
-                Fz += (double)(ff * (T)dz);
+                Fx += (double)(ff * (T)ddx);
+                Fy += (double)(ff * (T)ddy);
+                Fz += (double)(ff * (T)ddz);
                 ue += 0.5 * eb;
                 uw += 0.5 * vb;
             }
@@ -246,18 +281,19 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
             v.y += hdt * Fy;
             v.z += hdt * Fz;
             double4 x = xi;
-            x.x += S.dt * v.x;
-            x.y += S.dt * v.y;
-            x.z += S.dt * v.z;
-            if (S.per[0]) x.x = fold(x.x, S.lo[0], S.L[0]);
-            if (S.per[1]) x.y = fold(x.y, S.lo[1], S.L[1]);
-            if (S.per[2]) x.z = fold(x.z, S.lo[2], S.L[2]);
+            const double dt = S.dt;
+            x.x += dt * v.x;
+            x.y += dt * v.y;
+            x.z += dt * v.z;
+            if (S.per[0]) x.x = fold(x.x, S.lo[0], Lx);
+            if (S.per[1]) x.y = fold(x.y, S.lo[1], Ly);
+            if (S.per[2]) x.z = fold(x.z, S.lo[2], Lz);
             a.pos_out[i] = x;
             a.vel_out[i] = v;
             const double4 xb = xbuild[i];
-            const double bx = min_image(x.x - xb.x, S.L[0], S.invL[0]);
-            const double by = min_image(x.y - xb.y, S.L[1], S.invL[1]);
-            const double bz = min_image(x.z - xb.z, S.L[2], S.invL[2]);
+            const double bx = min_image(x.x - xb.x, Lx, iLx);
+            const double by = min_image(x.y - xb.y, Ly, iLy);
+            const double bz = min_image(x.z - xb.z, Lz, iLz);
             if ((bx * bx + by * by) + bz * bz > S.disp2) *a.flag_set = 1;
         } else {
             if (a.mode == MODE_LAST) a.vel_out[i] = v;
@@ -375,13 +411,16 @@ __global__ void k_rtag(const SysDev *__restrict__ sys, const int32_t *__restrict
 
 // ---------------------------------------------------------------------------
 
-size_t force_lds_bytes(int pair, int halo_cap) { return (size_t)halo_entry_bytes(pair) * (size_t)halo_cap; }
+size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap)
+{
+    return (size_t)halo_entry_bytes(pair) * (size_t)halo_cap + (size_t)nlist_cap * kTile * sizeof(uint16_t);
+}
 
 template <int W, bool MIXED, int POT, bool LOG>
 static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
 {
     if (L.tiles_local == 0) return;
-    const size_t lds = force_lds_bytes(POT, L.halo_cap);
+    const size_t lds = force_lds_bytes(POT, L.halo_cap, L.nlist_cap);
     hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(L.tiles_local), dim3(W * kWave), lds, L.stream,
                        L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
                        L.halo_cap, L.partners, L.rtag, L.xbuild, L.partials, L.status, F);

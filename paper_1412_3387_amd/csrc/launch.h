@@ -72,6 +72,6 @@ void launch_thermo_reduce(const LaunchCtx &L, int w, int log_row, double timeste
 void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value);
 void launch_rtag(const LaunchCtx &L, const int32_t *tag);
 void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag);
-size_t force_lds_bytes(int pair, int halo_cap);
+size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
 
 }  // namespace md

@@ -27,6 +27,9 @@
 //
 // Row layout (uint16): entry k of row r of a system lives at
 // nl0 + (r / 64) * cap * 64 + k * 64 + r % 64.
+// Tile header halo_n[tile]: bits 0-15 halo size, bits 16-30 the longest row
+// of the tile, bit 31 set when the tile is too wide for one periodic image
+// per halo entry.
 #include "launch.h"
 
 namespace md {
@@ -36,6 +39,8 @@ constexpr int kBuildW = 4;
 constexpr int kChunk = 512;          // members staged at once
 constexpr int kSlotMax = 16384;      // members of a tile's stencil cells
 constexpr int kRebuildGrid = 2048;   // blocks of the grid-stride rebuild kernels
+constexpr int kKeys = 2048;          // 64 rows x 27 stencil cells, padded
+constexpr int kStencil = 27;
 
 // ---------------------------------------------------------------------------
 // binning
@@ -141,22 +146,23 @@ __device__ __forceinline__ int wrap_rel(int d, int bins)
     return d;
 }
 
-constexpr int kKeys = 2048;          // 64 rows x 27 stencil cells, padded
-
 struct BuildShared {
     double cx[kChunk], cy[kChunk], cz[kChunk];
     int32_t cj[kChunk];
     int32_t keys[kKeys];              // stencil cells, then distinct cells
+    int32_t ucount[kKeys];            // flags / members of each distinct cell
     int32_t ustart[kKeys + 1];        // first slot of each distinct cell
     uint32_t used[kSlotMax / 32];
     int32_t wpre[kSlotMax / 32 + 1];
+    int16_t su[kTile][kStencil];      // distinct-cell index of each row's stencil cell (-1: none)
+    int8_t sm[kTile][kStencil];       // image code (mx+1) + 3 (my+1) + 9 (mz+1)
     int32_t scan[kBuildThreads];
     int32_t ext[6];                   // min / max cell offset from the first row
-    int32_t info[4];                  // distinct cells, per-pair image flag
+    int32_t info[4];                  // distinct cells, per-pair image flag, longest row
 };
 
 // Exclusive block scan of n <= 8 * kBuildThreads values held in LDS `a`
-// (in place); returns the total.  Uses sh.scan.
+// (in place); returns the total.
 __device__ __forceinline__ int block_scan8(int32_t *a, int n, int32_t *scan)
 {
     const int tid = threadIdx.x;
@@ -211,7 +217,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 {
     if (*flag == 0) return;
     __shared__ BuildShared sh;
-    __shared__ int32_t ucount[kKeys];   // members of each distinct cell, scanned in place
     constexpr int W = kBuildW;
     constexpr int P = kWave / W;
     const int tid = threadIdx.x;
@@ -227,53 +232,88 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
     for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int s = find_sys(tprefix, n_sys, tile);
         const SysDev &S = sys[s];
+        // per-system constants, held in registers for the whole tile
+        const double Lx = S.L[0], Ly = S.L[1], Lz = S.L[2];
+        const double iLx = S.invL[0], iLy = S.invL[1], iLz = S.invL[2];
+        const int bx = S.bins[0], by = S.bins[1], bz = S.bins[2];
+        const int px = S.per[0], py = S.per[1], pz = S.per[2];
+        const int64_t row0 = S.row0, cell0 = S.cell0, nl0 = S.nl0;
+        const int n_local = S.n_local;
+        const double rl2 = S.rl2;
         const int r0 = (tile - S.tile0) * kTile;
         const int r = r0 + t;
-        const bool active = r < S.n_local;
-        const int64_t i = S.row0 + (active ? r : r0);
+        const bool active = r < n_local;
+        const int64_t i = row0 + (active ? r : r0);
         const double4 xi = pos[i];
         int ci[3];
-        ci[0] = cell_coord(xi.x, S.lo[0], S.scale[0], S.bins[0]);
-        ci[1] = cell_coord(xi.y, S.lo[1], S.scale[1], S.bins[1]);
-        ci[2] = cell_coord(xi.z, S.lo[2], S.scale[2], S.bins[2]);
-        const double4 x0 = pos[S.row0 + r0];
-        int c0[3];
-        c0[0] = cell_coord(x0.x, S.lo[0], S.scale[0], S.bins[0]);
-        c0[1] = cell_coord(x0.y, S.lo[1], S.scale[1], S.bins[1]);
-        c0[2] = cell_coord(x0.z, S.lo[2], S.scale[2], S.bins[2]);
+        ci[0] = cell_coord(xi.x, S.lo[0], S.scale[0], bx);
+        ci[1] = cell_coord(xi.y, S.lo[1], S.scale[1], by);
+        ci[2] = cell_coord(xi.z, S.lo[2], S.scale[2], bz);
+        const double4 x0 = pos[row0 + r0];
+        const int c0[3] = {cell_coord(x0.x, S.lo[0], S.scale[0], bx), cell_coord(x0.y, S.lo[1], S.scale[1], by),
+                           cell_coord(x0.z, S.lo[2], S.scale[2], bz)};
 
         // ---- 1. distinct stencil cells of the tile ---------------------------
+        // stencil k = (oz * 3 + oy) * 3 + ox over the de-duplicated offsets
         if (tid < 3) {
             sh.ext[tid] = INT32_MAX;
             sh.ext[3 + tid] = INT32_MIN;
         }
-        const int nst = S.nst[0] * S.nst[1] * S.nst[2];
-        for (int k = sl; k < 27; k += W) {
+        if (tid == 0) sh.info[2] = 0;
+        for (int k = sl; k < kStencil; k += W) {
+            const int ox = k % 3, oy = (k / 3) % 3, oz = k / 9;
             int key = INT32_MAX;
-            if (active && k < nst) {
-                const int ox = k % S.nst[0], oy = (k / S.nst[0]) % S.nst[1], oz = k / (S.nst[0] * S.nst[1]);
-                int cc[3] = {ci[0] + S.st[0][ox], ci[1] + S.st[1][oy], ci[2] + S.st[2][oz]};
+            int code = 0;
+            if (active && ox < S.nst[0] && oy < S.nst[1] && oz < S.nst[2]) {
+                const int off[3] = {S.st[0][ox], S.st[1][oy], S.st[2][oz]};
+                const int bins[3] = {bx, by, bz};
+                const int per[3] = {px, py, pz};
+                int cc[3];
                 bool inside = true;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    if (S.per[a]) cc[a] = cc[a] < 0 ? cc[a] + S.bins[a] : (cc[a] >= S.bins[a] ? cc[a] - S.bins[a] : cc[a]);
-                    else inside = inside && cc[a] >= 0 && cc[a] < S.bins[a];
+                    cc[a] = ci[a] + off[a];
+                    int m = 0;
+                    if (per[a]) {
+                        // image of the neighbour cell across a periodic face
+                        if (cc[a] < 0) {
+                            cc[a] += bins[a];
+                            m = 1;
+                        } else if (cc[a] >= bins[a]) {
+                            cc[a] -= bins[a];
+                            m = -1;
+                        }
+                    } else {
+                        inside = inside && cc[a] >= 0 && cc[a] < bins[a];
+                    }
+                    code += (m + 1) * (a == 0 ? 1 : (a == 1 ? 3 : 9));
                 }
-                if (inside) key = (cc[2] * S.bins[1] + cc[1]) * S.bins[0] + cc[0];
+                if (inside) key = (cc[2] * by + cc[1]) * bx + cc[0];
             }
-            sh.keys[t * 27 + k] = key;
+            sh.keys[t * kStencil + k] = key;
+            sh.sm[t][k] = (int8_t)code;
         }
-        for (int k = 64 * 27 + tid; k < kKeys; k += kBuildThreads) sh.keys[k] = INT32_MAX;
+        for (int k = kTile * kStencil + tid; k < kKeys; k += kBuildThreads) sh.keys[k] = INT32_MAX;
         __syncthreads();
         if (active && sl == 0) {
+            const int bins[3] = {bx, by, bz};
+            const int per[3] = {px, py, pz};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int d = ci[a] - c0[a];
-                const int rel = S.per[a] ? wrap_rel(d, S.bins[a]) : d;
+                const int rel = per[a] ? wrap_rel(d, bins[a]) : d;
                 atomicMin(&sh.ext[a], rel);
                 atomicMax(&sh.ext[3 + a], rel);
             }
         }
+        // the key of every row's stencil cell, kept for the lookup below
+        int32_t mykeys[(kStencil + W - 1) / W];
+#pragma unroll
+        for (int q = 0; q < (kStencil + W - 1) / W; ++q) {
+            const int k = sl + q * W;
+            mykeys[q] = k < kStencil ? sh.keys[t * kStencil + k] : INT32_MAX;
+        }
+        __syncthreads();
         // bitonic sort of the keys
         for (int k = 2; k <= kKeys; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
@@ -290,42 +330,42 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
             }
         }
         // distinct keys: flag first occurrences, scan, compact
-        for (int k = tid; k < kKeys; k += kBuildThreads)
-            ucount[k] = (sh.keys[k] != INT32_MAX && (k == 0 || sh.keys[k] != sh.keys[k - 1])) ? 1 : 0;
-        __syncthreads();
-        {
-            int flags8[8];
-            const int b = 8 * tid;
+        int flags8[8];
+        int32_t kv[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) flags8[k] = ucount[b + k];
-            __syncthreads();
-            const int nu = block_scan8(ucount, kKeys, sh.scan);
-            // ucount[k] now holds the distinct index of key k if flagged
-            int32_t kv[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) kv[k] = sh.keys[b + k];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (flags8[k]) sh.keys[ucount[b + k]] = kv[k];
-            if (tid == 0) {
-                sh.info[0] = nu;
-                int pp = 0;
-                for (int a = 0; a < 3; ++a)
-                    if (S.per[a] &&
-                        (double)(sh.ext[3 + a] - sh.ext[a] + 3) * (S.L[a] / S.bins[a]) >= 0.5 * S.L[a])
-                        pp = 1;
-                sh.info[1] = pp;
-            }
-            __syncthreads();
+        for (int k = 0; k < 8; ++k) {
+            const int q = 8 * tid + k;
+            kv[k] = sh.keys[q];
+            flags8[k] = (kv[k] != INT32_MAX && (q == 0 || kv[k] != sh.keys[q - 1])) ? 1 : 0;
+            sh.ucount[q] = flags8[k];
         }
-        const int nu = sh.info[0];
-        // member counts of the distinct cells and their prefix
-        for (int u = tid; u < nu; u += kBuildThreads) ucount[u] = cell_size[S.cell0 + sh.keys[u]];
         __syncthreads();
-        const int nslot = block_scan8(ucount, nu, sh.scan);
-        for (int u = tid; u < nu; u += kBuildThreads) sh.ustart[u] = ucount[u];
+        const int nu = block_scan8(sh.ucount, kKeys, sh.scan);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (flags8[k]) sh.keys[sh.ucount[8 * tid + k]] = kv[k];
+        if (tid == 0) {
+            int pp = 0;
+            const double Ls[3] = {Lx, Ly, Lz};
+            const int bins[3] = {bx, by, bz};
+            const int per[3] = {px, py, pz};
+            for (int a = 0; a < 3; ++a)
+                if (per[a] && (double)(sh.ext[3 + a] - sh.ext[a] + 3) * (Ls[a] / bins[a]) >= 0.5 * Ls[a]) pp = 1;
+            sh.info[1] = pp;
+        }
+        __syncthreads();
+        // member counts of the distinct cells and their prefix
+        for (int u = tid; u < nu; u += kBuildThreads) sh.ucount[u] = cell_size[cell0 + sh.keys[u]];
+        __syncthreads();
+        const int nslot = block_scan8(sh.ucount, nu, sh.scan);
+        for (int u = tid; u < nu; u += kBuildThreads) sh.ustart[u] = sh.ucount[u];
         if (tid == 0) sh.ustart[nu] = nslot;
+        // each row's stencil cells as distinct-cell indices
+#pragma unroll
+        for (int q = 0; q < (kStencil + W - 1) / W; ++q) {
+            const int k = sl + q * W;
+            if (k < kStencil) sh.su[t][k] = mykeys[q] == INT32_MAX ? (int16_t)-1 : (int16_t)upper_idx(sh.keys, nu, mykeys[q]);
+        }
         if (nslot > kSlotMax) {
             if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nslot);
             if (active && sl == 0) nn[i] = 0;
@@ -341,20 +381,20 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 #pragma unroll
             for (int b = 0; b < kMaxBondCap; ++b) part[b] = -1;
             if (active) {
-                const int64_t prow = (S.row0 + tag[i]) * S.bond_cap;
+                const int64_t prow = (row0 + tag[i]) * S.bond_cap;
                 for (int b = 0; b < S.bond_cap && b < kMaxBondCap; ++b) part[b] = partners[prow + b];
             }
         }
-        const int64_t rowbase = S.nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
-        const double rl2 = S.rl2;
-        const bool few[3] = {S.per[0] && S.bins[0] < 3, S.per[1] && S.bins[1] < 3, S.per[2] && S.bins[2] < 3};
+        const int64_t rowbase = nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
+        const bool fx_ = px && bx < 3, fy_ = py && by < 3, fz_ = pz && bz < 3;
+        const bool few = fx_ || fy_ || fz_;
         int ntot = 0;
         for (int q0 = 0; q0 < nslot; q0 += kChunk) {
             const int q1 = q0 + kChunk < nslot ? q0 + kChunk : nslot;
             __syncthreads();
             for (int q = q0 + tid; q < q1; q += kBuildThreads) {
                 const int u = upper_idx(sh.ustart, nu, q);
-                const int32_t j = cell_idx[(S.cell0 + sh.keys[u]) * cell_cap + (q - sh.ustart[u])];
+                const int32_t j = cell_idx[(cell0 + sh.keys[u]) * cell_cap + (q - sh.ustart[u])];
                 const double4 xj = pos[j];
                 sh.cx[q - q0] = xj.x;
                 sh.cy[q - q0] = xj.y;
@@ -363,68 +403,65 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
             }
             __syncthreads();
             if (!active) continue;
-            for (int k = 0; k < nst; ++k) {
-                const int ox = k % S.nst[0], oy = (k / S.nst[0]) % S.nst[1], oz = k / (S.nst[0] * S.nst[1]);
-                const int d[3] = {S.st[0][ox], S.st[1][oy], S.st[2][oz]};
-                int cc[3];
-                double m[3];
-                bool inside = true;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    cc[a] = ci[a] + d[a];
-                    m[a] = 0.0;
-                    if (S.per[a]) {
-                        // image of the neighbour cell across the periodic face
-                        if (cc[a] < 0) {
-                            cc[a] += S.bins[a];
-                            m[a] = 1.0;
-                        } else if (cc[a] >= S.bins[a]) {
-                            cc[a] -= S.bins[a];
-                            m[a] = -1.0;
-                        }
-                    } else {
-                        inside = inside && cc[a] >= 0 && cc[a] < S.bins[a];
-                    }
-                }
-                if (!inside) continue;
-                const int key = (cc[2] * S.bins[1] + cc[1]) * S.bins[0] + cc[0];
-                const int u = upper_idx(sh.keys, nu, key);
+            for (int k = 0; k < kStencil; ++k) {
+                const int u = sh.su[t][k];
+                if (u < 0) continue;
+                const int code = sh.sm[t][k];
+                const double sx = Lx * (double)(code % 3 - 1);
+                const double sy = Ly * (double)((code / 3) % 3 - 1);
+                const double sz = Lz * (double)(code / 9 - 1);
                 int a0 = sh.ustart[u], a1 = sh.ustart[u + 1];
                 a0 = a0 > q0 ? a0 : q0;
                 a1 = a1 < q1 ? a1 : q1;
-                for (int k0 = a0; k0 < a1; k0 += W) {
-                    const int q = k0 + sl;
-                    bool hit = false;
-                    if (q < a1) {
-                        const int32_t j = sh.cj[q - q0];
-                        if (j != (int32_t)i) {
-                            double ddx = sh.cx[q - q0] - xi.x;
-                            double ddy = sh.cy[q - q0] - xi.y;
-                            double ddz = sh.cz[q - q0] - xi.z;
-                            // fewer than 3 cells: several images share a cell, take the nearest
-                            ddx = few[0] ? min_image(ddx, S.L[0], S.invL[0]) : __fma_rn(-S.L[0], m[0], ddx);
-                            ddy = few[1] ? min_image(ddy, S.L[1], S.invL[1]) : __fma_rn(-S.L[1], m[1], ddy);
-                            ddz = few[2] ? min_image(ddz, S.L[2], S.invL[2]) : __fma_rn(-S.L[2], m[2], ddz);
-                            hit = norm2_exact(ddx, ddy, ddz) < rl2;
-                            if constexpr (EXCL) {
-                                if (hit) {
-                                    const int32_t tj = tag[j];
+                for (int k0 = a0; k0 < a1; k0 += 2 * W) {
+                    bool hit[2];
+                    int qq[2];
+                    int32_t jj[2];
+                    double ddx[2], ddy[2], ddz[2];
 #pragma unroll
-                                    for (int e = 0; e < kMaxBondCap; ++e) hit = hit && (part[e] != tj);
-                                }
+                    for (int v = 0; v < 2; ++v) {
+                        qq[v] = k0 + sl + v * W;
+                        const int qs = (qq[v] < a1 ? qq[v] : a0) - q0;
+                        jj[v] = sh.cj[qs];
+                        ddx[v] = sh.cx[qs] - xi.x;
+                        ddy[v] = sh.cy[qs] - xi.y;
+                        ddz[v] = sh.cz[qs] - xi.z;
+                    }
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        if (few) {
+                            // fewer than 3 cells: several images share a cell, take the nearest
+                            ddx[v] = fx_ ? min_image(ddx[v], Lx, iLx) : ddx[v] - sx;
+                            ddy[v] = fy_ ? min_image(ddy[v], Ly, iLy) : ddy[v] - sy;
+                            ddz[v] = fz_ ? min_image(ddz[v], Lz, iLz) : ddz[v] - sz;
+                        } else {
+                            ddx[v] -= sx;
+                            ddy[v] -= sy;
+                            ddz[v] -= sz;
+                        }
+                        hit[v] = qq[v] < a1 && jj[v] != (int32_t)i && norm2_exact(ddx[v], ddy[v], ddz[v]) < rl2;
+                        if constexpr (EXCL) {
+                            if (hit[v]) {
+                                const int32_t tj = tag[jj[v]];
+#pragma unroll
+                                for (int b = 0; b < kMaxBondCap; ++b) hit[v] = hit[v] && (part[b] != tj);
                             }
                         }
                     }
-                    const uint64_t mask = __ballot(hit) & seg;
-                    if (hit) {
-                        const int p = ntot + __popcll(mask & below);
-                        if (p < cap) nlist[rowbase + (int64_t)p * kTile] = (uint16_t)q;
-                        atomicOr(&sh.used[q >> 5], 1u << (q & 31));
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        const uint64_t mask = __ballot(hit[v]) & seg;
+                        if (hit[v]) {
+                            const int p = ntot + __popcll(mask & below);
+                            if (p < cap) nlist[rowbase + (int64_t)p * kTile] = (uint16_t)qq[v];
+                            atomicOr(&sh.used[qq[v] >> 5], 1u << (qq[v] & 31));
+                        }
+                        ntot += __popcll(mask);
                     }
-                    ntot += __popcll(mask);
                 }
             }
         }
+        if (active && sl == 0) atomicMax(&sh.info[2], ntot < cap ? ntot : cap);
         __syncthreads();
         // ---- 4. halo numbering and row rewrite ---------------------------------
         const int nwords = (nslot + 31) / 32;
@@ -445,19 +482,24 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
             if (word & (1u << (q & 31))) {
                 const int u = upper_idx(sh.ustart, nu, q);
                 const int h = sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u));
-                hl[h] = cell_idx[(S.cell0 + sh.keys[u]) * cell_cap + (q - sh.ustart[u])];
+                hl[h] = cell_idx[(cell0 + sh.keys[u]) * cell_cap + (q - sh.ustart[u])];
             }
         }
-        if (tid == 0) halo_n[tile] = sh.info[1] ? (int32_t)((uint32_t)nhalo | 0x80000000u) : nhalo;
+        if (tid == 0)
+            halo_n[tile] = (int32_t)((uint32_t)nhalo | ((uint32_t)sh.info[2] << 16) | (sh.info[1] ? 0x80000000u : 0u));
         __threadfence_block();
         __syncthreads();
         if (active) {
             const int n = ntot < cap ? ntot : cap;
-            for (int k = sl; k < n; k += W) {
+            for (int k = sl; k < n; k += 2 * W) {
                 const int64_t a = rowbase + (int64_t)k * kTile;
-                const int q = nlist[a];
-                const uint32_t word = sh.used[q >> 5];
-                nlist[a] = (uint16_t)(sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u)));
+                const int64_t b = a + (int64_t)W * kTile;
+                const bool has_b = k + W < n;
+                const int qa = nlist[a];
+                const int qb = has_b ? nlist[b] : 0;
+                const uint32_t wa = sh.used[qa >> 5], wb = sh.used[qb >> 5];
+                nlist[a] = (uint16_t)(sh.wpre[qa >> 5] + __popc(wa & ((1u << (qa & 31)) - 1u)));
+                if (has_b) nlist[b] = (uint16_t)(sh.wpre[qb >> 5] + __popc(wb & ((1u << (qb & 31)) - 1u)));
             }
             if (sl == 0) {
                 nn[i] = n;

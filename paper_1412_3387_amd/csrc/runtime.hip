@@ -67,7 +67,8 @@ bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         if (!(q.r_buff >= 0) || !(q.dt > 0)) return false;
         if (q.pair != HOOMD_PAIR_WCA && !(q.r_cut > 0)) return false;
         if (q.pair != HOOMD_PAIR_DPD && !(q.sigma > 0)) return false;
-        if (q.nlist_cap < 1 || q.nlist_cap > (1 << 16)) return false;
+        // the rows of a tile share one workgroup's LDS with at least 64 halo entries
+        if (q.nlist_cap < 1 || (int64_t)q.nlist_cap * 128 + 64 * 52 > 65536) return false;
         if (q.cell_cap < 0 || q.cell_cap > 128) return false;
         if (q.halo_cap < 0 || q.halo_cap > 65535) return false;
         if (q.tpp_force < 0 || q.tpp_force > 16 || (q.tpp_force & (q.tpp_force - 1))) return false;
@@ -97,8 +98,13 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     for (int s = 0; s < n_sys; ++s) {
         Lo.nlist_cap = std::max(Lo.nlist_cap, p[s].nlist_cap);
         Lo.bond_cap = std::max(Lo.bond_cap, p[s].bond_cap);
+    }
+    for (int s = 0; s < n_sys; ++s) {
         // halo of a compact 64-row tile: density x (tile side + 2 r_list)^3
-        const int lds_max = (int)(65536 / force_lds_bytes(p[s].pair, 1)) / 64 * 64;
+        // one workgroup's LDS (64 KiB) holds the halo and the tile's rows
+        const int64_t row_bytes = (int64_t)force_lds_bytes(p[s].pair, 0, Lo.nlist_cap);
+        const int lds_max = (int)std::max<int64_t>(
+            (65536 - row_bytes) / (int64_t)force_lds_bytes(p[s].pair, 1, 0) / 64 * 64, 64);
         int hc = p[s].halo_cap;
         if (hc <= 0) {
             const double vol = boxes[s].L[0] * boxes[s].L[1] * boxes[s].L[2];
