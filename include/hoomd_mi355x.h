@@ -113,6 +113,8 @@ typedef struct {
     int32_t tpp_force;     /* lanes per particle, forces (0 = tuned)         */
     int32_t block_nlist;   /* threads per block (0 = tuned)                  */
     int32_t block_force;
+    int32_t use_graph;     /* 1: step() replays captured pairs of middle steps
+                              (HIP graph, captured once per context)          */
 } hoomd_params;
 
 /* Geometry of one system.  For a periodic box lo = 0 and L is the box.  For
@@ -145,11 +147,13 @@ typedef struct {
 size_t hoomd_workspace_bytes(const hoomd_params *params, int32_t n_sys, const hoomd_box *boxes);
 
 /* Create a context over caller-owned device arrays.  params and boxes hold
- * n_sys entries each (one per independent system; all systems share the
- * precision).  `stream` is a hipStream_t (NULL = the null stream).
- * Copies the bond table into per-particle partner rows, clears the status
- * word, and queues nothing else.  Errors: HOOMD_E_ARG, HOOMD_E_WORKSPACE,
- * HOOMD_E_DEVICE. */
+ * n_sys entries each (one per independent system).  All systems share the
+ * precision; LJ and WCA systems (with or without bonds) may be mixed in one
+ * context, DPD systems only with other DPD systems.  Every kernel covers all
+ * systems in one launch.  `stream` is a hipStream_t (NULL = the null
+ * stream).  Copies the descriptors and the bond table (as per-particle
+ * partner rows) to the device synchronously; validates tags of bonded
+ * systems.  Errors: HOOMD_E_ARG, HOOMD_E_WORKSPACE, HOOMD_E_DEVICE. */
 int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys,
                const hoomd_box *boxes, const hoomd_arrays *arrays, void *workspace,
                size_t workspace_bytes, void *stream);

@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("fene_K", C.c_double), ("fene_R0", C.c_double), ("nlist_cap", C.c_int32),
                 ("cell_cap", C.c_int32), ("halo_cap", C.c_int32), ("sort_period", C.c_int32), ("check_period", C.c_int32),
                 ("tpp_nlist", C.c_int32), ("tpp_force", C.c_int32), ("block_nlist", C.c_int32),
-                ("block_force", C.c_int32)]
+                ("block_force", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class Box(C.Structure):
@@ -152,6 +152,7 @@ class ModelParams:
     tpp_force: int = 0
     block_nlist: int = 0
     block_force: int = 0
+    use_graph: int = 1
 
     def list_radius(self) -> float:
         rc = 2.0 ** (1.0 / 6.0) * self.sigma if self.pair == PAIR_WCA else self.r_cut

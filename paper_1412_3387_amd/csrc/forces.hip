@@ -153,6 +153,9 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     if constexpr (POT == PAIR_DPD) vi = a.vel[i];
     int32_t ti = 0;
     if constexpr (POT == PAIR_DPD) ti = a.tag[i];
+    uint32_t step_key = a.timestep;
+    if constexpr (POT == PAIR_DPD)
+        if (a.timestep_ptr) step_key = *a.timestep_ptr;
     int n = active ? nn[i] : 0;
     n = n < cap ? n : cap;
 
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
                     const T w = (T)1 - rr * (T)S.dpd_inv_rc;
                     const T dvx = (T)(vi.x - hvx[h]), dvy = (T)(vi.y - hvy[h]), dvz = (T)(vi.z - hvz[h]);
                     const T rv = ((T)dx[u] * dvx + (T)dy[u] * dvy + (T)dz[u] * dvz) * rinv;
-                    const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)htag[h], S.dpd_seed, a.timestep);
+                    const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)htag[h], S.dpd_seed, step_key);
                     const T uu = (T)bits * (T)(1.0 / 16777216.0);
                     const T theta = (T)1.7320508075688772 * ((T)2 * uu - (T)1);
                     const T mag = (T)S.dpd_A * w - (T)S.dpd_gamma * w * w * rv +
@@ -438,7 +441,6 @@ static void force_pot(const LaunchCtx &L, const ForceLaunch &F)
 {
     switch (F.pair) {
     case PAIR_LJ: force_log<W, MIXED, PAIR_LJ>(L, F); break;
-    case PAIR_WCA: force_log<W, MIXED, PAIR_WCA>(L, F); break;
     default: force_log<W, MIXED, PAIR_DPD>(L, F); break;
     }
 }

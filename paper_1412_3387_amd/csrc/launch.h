@@ -41,6 +41,7 @@ struct LaunchCtx {
     bool has_bonds;
     int32_t *flag;                 // rebuild flag read by the rebuild kernels
     int32_t *build_count;
+    uint32_t *step_counter;        // advanced by the binning launch when set (graph steps)
     Status *status;
     double *partials;              // 3 doubles per wave
     double *thermo;                // 4 doubles per system
@@ -57,6 +58,7 @@ struct ForceLaunch {
     int32_t *flag_set;
     int32_t *flag_clear;
     uint32_t timestep;
+    const uint32_t *timestep_ptr;  // when set, the timestep is read from the device
     int32_t mode;
     int32_t log;      // accumulate energy / virial, write thermo partials
     int32_t energy;   // write the energy into force.w

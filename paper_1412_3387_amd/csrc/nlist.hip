@@ -50,8 +50,12 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
                                              const double4 *__restrict__ pos,
                                              int32_t *__restrict__ cell_count,
                                              int32_t *__restrict__ cell_idx, int cell_cap,
-                                             const int32_t *__restrict__ flag, Status *st)
+                                             const int32_t *__restrict__ flag, Status *st,
+                                             uint32_t *step_counter)
 {
+    // the binning launch follows every fused step launch: it also advances
+    // the device step counter read by graph-replayed steps
+    if (step_counter && blockIdx.x == 0 && threadIdx.x == 0) *step_counter += 1u;
     if (*flag == 0) return;
     const int lane = lane_id();
     const uint64_t lt = lanemask_lt();
@@ -522,7 +526,8 @@ void launch_bin(const LaunchCtx &L, const double4 *pos)
     if (L.tiles_all == 0) return;
     const int blocks = capped(((int64_t)L.tiles_all * kWave + 255) / 256);
     hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.tprefix_all, L.n_sys,
-                       L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.status);
+                       L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.status,
+                       L.step_counter);
 }
 
 void launch_cell_sort(const LaunchCtx &L)

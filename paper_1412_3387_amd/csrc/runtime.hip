@@ -261,9 +261,16 @@ struct hoomd_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used;
     std::vector<std::pair<size_t, size_t>> ev_force, ev_rebuild;
+    // captured pairs of middle steps, one per buffer parity
+    hipStream_t cap_stream;
+    hipGraphExec_t graph_exec[2];
+    int graph_tpp[2];
     ~hoomd_ctx()
     {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        for (int p = 0; p < 2; ++p)
+            if (graph_exec[p]) (void)hipGraphExecDestroy(graph_exec[p]);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 };
 
@@ -328,6 +335,57 @@ ForceLaunch base_force(hoomd_ctx *c)
     return F;
 }
 
+uint32_t *step_counter_ptr(hoomd_ctx *c) { return reinterpret_cast<uint32_t *>(flag_ptr(c, 5)); }
+
+// One middle step at buffer parity p: fused launch, then the rebuild queue.
+// Every argument depends only on p, so the pair (p, p^1) can be captured once
+// and replayed.
+void queue_mid_step(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V, bool dpd)
+{
+    ForceLaunch F = base_force(c);
+    F.pos = P[p];
+    F.pos_out = P[p ^ 1];
+    F.vel = V[dpd ? p : 0];
+    F.vel_out = V[dpd ? p ^ 1 : 0];
+    F.timestep_ptr = step_counter_ptr(c);
+    F.mode = MODE_MID;
+    F.flag_set = flag_ptr(c, p);
+    F.flag_clear = flag_ptr(c, p ^ 1);
+    launch_force(c->L, F, c->tpp_force, c->block_force);
+    queue_rebuild(c, P[p ^ 1], c->arr.tag, flag_ptr(c, p));
+}
+
+int ensure_step_graph(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V, bool dpd)
+{
+    if (c->graph_exec[p] && c->graph_tpp[p] == c->tpp_force) return HOOMD_OK;
+    if (c->graph_exec[p]) {
+        (void)hipGraphExecDestroy(c->graph_exec[p]);
+        c->graph_exec[p] = nullptr;
+    }
+    // capture on a private stream (the caller's may be the null stream, which
+    // cannot be captured); the graph is launched on the caller's stream
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return HOOMD_E_DEVICE;
+    const hipStream_t keep = c->L.stream;
+    c->L.stream = c->cap_stream;
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        queue_mid_step(c, p, P, V, dpd);
+        queue_mid_step(c, p ^ 1, P, V, dpd);
+        ok = hipStreamEndCapture(c->cap_stream, &g) == hipSuccess && g;
+    }
+    c->L.stream = keep;
+    if (ok) ok = hipGraphInstantiate(&c->graph_exec[p], g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        c->graph_exec[p] = nullptr;
+        return HOOMD_E_DEVICE;
+    }
+    c->graph_tpp[p] = c->tpp_force;
+    return HOOMD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -360,12 +418,14 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     c->ws = (char *)workspace;
     c->lay = lay;
     c->mixed = params[0].precision == HOOMD_MIXED;
-    c->pair_uniform = params[0].pair;
+    // LJ and WCA run the same kernel (WCA is LJ with its own cut-off and
+    // shift, carried per system); DPD needs its own and cannot be mixed in
+    c->pair_uniform = params[0].pair == HOOMD_PAIR_DPD ? PAIR_DPD : PAIR_LJ;
     for (int s = 1; s < n_sys; ++s)
-        if (params[s].pair != params[0].pair) c->pair_uniform = -1;
+        if ((params[s].pair == HOOMD_PAIR_DPD) != (c->pair_uniform == PAIR_DPD)) c->pair_uniform = -1;
     if (c->pair_uniform < 0) {
         delete c;
-        return HOOMD_E_ARG;  // mixed potentials in one context are not supported
+        return HOOMD_E_ARG;
     }
     c->built = false;
     c->last_log_rows = 0;
@@ -543,22 +603,48 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
     double4 *P[2] = {reinterpret_cast<double4 *>(c->arr.pos), ws_ptr<double4>(c, c->lay.pos_alt)};
     double4 *V[2] = {reinterpret_cast<double4 *>(c->arr.vel), ws_ptr<double4>(c, c->lay.vel_alt)};
     int32_t *tag = c->arr.tag;
-    int pc = 0, vc = 0;
     int log_row = 0;
     const int sort_period = c->prm[0].sort_period;
-    for (int32_t s = 0; s <= n_steps; ++s) {
+    const bool graphs = c->prm[0].use_graph && !c->profiling;
+    // the DPD key of each launch comes from a device counter that the
+    // binning launch after it advances, so graph replays see the right step
+    uint32_t *counter = step_counter_ptr(c);
+    launch_set_flag(c->L, reinterpret_cast<int32_t *>(counter), (int32_t)(uint32_t)t0);
+    c->L.step_counter = counter;
+    auto sorts_after = [&](int32_t s) {
+        return sort_period > 0 && ((t0 + (uint64_t)s + 1) % (uint64_t)sort_period) == 0;
+    };
+    auto logs_at = [&](int32_t s) { return log_every > 0 && (s % log_every == 0 || s == n_steps); };
+    int32_t s = 0;
+    while (s <= n_steps) {
         const uint64_t t = t0 + (uint64_t)s;
+        const int p = s & 1;  // parity of the position (and DPD velocity) buffers
+        // two middle steps with nothing eager in between replay as one graph
+        if (graphs && s > 0 && s + 1 < n_steps && !logs_at(s) && !logs_at(s + 1) && !sorts_after(s) &&
+            !sorts_after(s + 1)) {
+            if (ensure_step_graph(c, p, P, V, dpd) != HOOMD_OK) {
+                c->L.step_counter = nullptr;
+                return HOOMD_E_DEVICE;
+            }
+            if (hipGraphLaunch(c->graph_exec[p], c->stream) != hipSuccess) {
+                c->L.step_counter = nullptr;
+                return HOOMD_E_DEVICE;
+            }
+            s += 2;
+            continue;
+        }
         ForceLaunch F = base_force(c);
-        F.pos = P[pc];
-        F.pos_out = P[pc ^ 1];
-        F.vel = V[vc];
-        F.vel_out = dpd ? V[vc ^ 1] : V[vc];
+        F.pos = P[p];
+        F.pos_out = P[p ^ 1];
+        F.vel = V[dpd ? p : 0];
+        F.vel_out = V[dpd ? p ^ 1 : 0];
         F.tag = tag;
         F.timestep = (uint32_t)t;
+        F.timestep_ptr = counter;
         F.mode = s == 0 ? MODE_FIRST : (s == n_steps ? MODE_LAST : MODE_MID);
-        F.flag_set = F.mode == MODE_LAST ? nullptr : flag_ptr(c, s & 1);
-        F.flag_clear = F.mode == MODE_LAST ? nullptr : flag_ptr(c, (s + 1) & 1);
-        F.log = log_every > 0 && (s % log_every == 0 || s == n_steps);
+        F.flag_set = F.mode == MODE_LAST ? nullptr : flag_ptr(c, p);
+        F.flag_clear = F.mode == MODE_LAST ? nullptr : flag_ptr(c, p ^ 1);
+        F.log = logs_at(s);
         F.energy = F.mode == MODE_LAST ? 1 : 0;
         if (F.mode == MODE_LAST) F.log = F.log || log_every > 0;
         const size_t e0 = mark(c);
@@ -568,20 +654,26 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
             launch_thermo_reduce(c->L, c->tpp_force, log_row < kLogRows ? log_row : -1, (double)t);
             ++log_row;
         }
-        if (dpd) vc ^= 1;
         if (F.mode == MODE_LAST) break;
-        pc ^= 1;
-        int32_t *flag = flag_ptr(c, s & 1);
-        if (sort_period > 0 && ((t + 1) % (uint64_t)sort_period) == 0) {
-            rc = queue_morton_sort(c->L, c->sortb, P[pc], V[vc], tag, P[pc ^ 1], V[vc ^ 1]);
-            if (rc) return HOOMD_E_DEVICE;
+        int32_t *flag = flag_ptr(c, p);
+        if (sorts_after(s)) {
+            rc = queue_morton_sort(c->L, c->sortb, P[p ^ 1], V[dpd ? p ^ 1 : 0], tag, P[p],
+                                   V[dpd ? p : 1]);
+            if (rc) {
+                c->L.step_counter = nullptr;
+                return HOOMD_E_DEVICE;
+            }
             if (c->lay.bond_cap > 0) launch_rtag(c->L, tag);
             launch_set_flag(c->L, flag, 1);
         }
         const size_t r0 = mark(c);
-        queue_rebuild(c, P[pc], tag, flag);
+        queue_rebuild(c, P[p ^ 1], tag, flag);
         if (c->profiling) c->ev_rebuild.emplace_back(r0, mark(c));
+        ++s;
     }
+    c->L.step_counter = nullptr;
+    const int pc = n_steps & 1;
+    const int vc = dpd ? (n_steps + 1) & 1 : 0;
     // leave the final state in the caller's arrays
     if (pc == 1)
         HIP_OK(hipMemcpyAsync(c->arr.pos, P[1], sizeof(double4) * c->lay.rows, hipMemcpyDeviceToDevice, c->stream));

@@ -1,0 +1,83 @@
+"""GPU parity of the batched ensemble: many independent LJ and bead-spring
+systems of uneven size advanced by the same launches."""
+import numpy as np
+import pytest
+
+from paper_1412_3387_amd import inputs
+from tests.gpu_helpers import LJ, by_tag, frel, min_image_diff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1412_3387_amd import binding
+    binding.lib()
+    return binding
+
+
+def _batch(n_lj=5, n_poly=5):
+    return inputs.batch_ensemble(n_lj=n_lj, n_poly=n_poly, lj_range=(500, 3000), chain_range=(20, 60))
+
+
+def _params(B, sy, prec):
+    if sy.kind == "lj":
+        return B.ModelParams(precision=prec, pair=B.PAIR_LJ, tpp_force=4, sort_period=50)
+    return B.ModelParams(precision=prec, pair=B.PAIR_WCA, bond_cap=2, tpp_force=4, sort_period=50)
+
+
+def _systems(batch):
+    return [dict(pos=sy.pos, vel=sy.vel, L=sy.L, bonds=sy.bonds, tag=sy.tag) for sy in batch]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_forces_match_oracle(orc, B, prec):
+    batch = _batch()
+    ctx = B.Context([_params(B, sy, prec) for sy in batch], _systems(batch))
+    ctx.compute_forces(0, 1)
+    ctx.check()
+    th = ctx.thermo()
+    for k, sy in enumerate(batch):
+        x, v, f, tag = ctx.host_state(k)
+        f = f[np.argsort(tag)]
+        if sy.kind == "lj":
+            F, u, w, _ = orc.pair_forces("lj", sy.pos, sy.L, LJ)
+        else:
+            Fp, up, wp, _ = orc.pair_forces("wca", sy.pos, sy.L, [1.0, 1.0])
+            Fb, ub, wb, _ = orc.bond_forces(sy.pos, sy.L, sy.bonds, with_wca=False)
+            F, u, w = Fp + Fb, up + ub, wp + wb
+        assert frel(f[:, :3], F) <= (1e-12 if prec == 0 else 1e-5), (k, sy.kind, sy.n)
+        ref = orc.thermo(sy.vel, u, w)
+        assert abs(th[k, 1] - ref[1]) <= (1e-11 if prec == 0 else 1e-6) * abs(ref[1])
+
+
+def test_batch_step_equals_single_systems(B):
+    """Each system of a batch evolves exactly as it does alone."""
+    batch = _batch(3, 3)
+    ctx = B.Context([_params(B, sy, 1) for sy in batch], _systems(batch))
+    ctx.step(0, 30)
+    ctx.check()
+    for k, sy in enumerate(batch):
+        one = B.Context([_params(B, sy, 1)], _systems([sy]))
+        one.step(0, 30)
+        a = ctx.host_state(k)
+        b = one.host_state(0)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), (k, sy.kind)
+
+
+def test_batch_short_run_fp64(orc, B):
+    batch = _batch(2, 2)
+    ctx = B.Context([_params(B, sy, 0) for sy in batch], _systems(batch))
+    ctx.step(0, 20)
+    ctx.check()
+    for k, sy in enumerate(batch):
+        if sy.kind == "lj":
+            xo, vo, *_ = orc.run_nve("lj", sy.pos, sy.vel, sy.L, LJ, 0.005, 20)
+        else:
+            xo, vo, *_ = orc.run_nve("polymer", sy.pos, sy.vel, sy.L, [1.0, 1.0], 0.005, 20,
+                                     bonds=sy.bonds, bond_prm=[30.0, 1.5])
+        x, v, f, tag = ctx.host_state(k)
+        x, v = by_tag(tag, x, v)
+        assert np.max(np.abs(min_image_diff(x, xo, sy.L))) < 1e-9
+        assert np.max(np.abs(v - vo)) < 1e-8

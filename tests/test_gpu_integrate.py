@@ -153,3 +153,40 @@ def test_polymer_short_run(orc, B):
     x, v = by_tag(tag, x, v)
     assert np.max(np.abs(min_image_diff(x, xo, m.L))) < 1e-9
     assert np.max(np.abs(v - vo)) < 1e-8
+
+
+@pytest.mark.parametrize("pair", ["lj", "dpd"])
+def test_graph_replay_equals_eager(B, pair):
+    """Captured pairs of middle steps reproduce eager launches bit for bit,
+    across sorts, logged steps and several step() calls."""
+    if pair == "lj":
+        s = inputs.lj_fluid(5000, 23, 24)
+        kw = dict(precision=1, sort_period=7)
+    else:
+        s = inputs.dpd_fluid(4000, 31, 32)
+        kw = dict(precision=1, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=5,
+                  sort_period=9)
+    out = []
+    for g in (0, 1):
+        c = B.Context([B.ModelParams(use_graph=g, **kw)], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+        c.step(0, 23, log_every=10)
+        c.step(23, 18)
+        c.check()
+        out.append(c.host_state() + (c.thermo_log(),))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_energy_drift_mixed_not_worse_than_fp64(B):
+    """NVE drift over 10^4 steps of the 4,000-particle liquid: the mixed path
+    may not add drift beyond max(1e-4, 2x the FP64 drift)."""
+    s = inputs.lj_small()
+    drift = {}
+    for prec in (0, 1):
+        c = B.Context([B.ModelParams(precision=prec, sort_period=500)], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+        c.step(0, 10000, log_every=1000)
+        c.check()
+        log = c.thermo_log()[:, 0, :]
+        E = log[:, 1] + log[:, 2]
+        drift[prec] = abs(E[-1] - E[0]) / abs(E[0])
+    assert drift[1] <= max(1e-4, 2 * drift[0]), drift
