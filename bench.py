@@ -36,7 +36,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run_precision(B, inputs, torch, s, prec, steps, warmup, tune, fixed=None):
+def run_precision(B, inputs, torch, s, prec, steps, warmup, tune, fixed=None, prof_steps=1000):
+    """Two windows on one trajectory: the timed window runs the product path
+    as a user runs it (captured step pairs replayed) and gives the throughput;
+    the profiled window right after it launches the same kernels eagerly with
+    HIP events around every force launch and every rebuild, and gives the
+    per-launch durations."""
     kw = {}
     if fixed:
         kw = {k: int(fixed[k]) for k in ("tpp_nlist", "block_nlist", "tpp_force", "block_force")}
@@ -54,25 +59,35 @@ def run_precision(B, inputs, torch, s, prec, steps, warmup, tune, fixed=None):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     b0 = ctx.build_count()
-    ctx.profile(1)
     t0 = time.perf_counter()
     e0.record(stream)
     ctx.step(warmup, steps, log_every=steps)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = ctx.profile(2)
-    ctx.profile(0)
     ctx.check()
     gpu_ms = e0.elapsed_time(e1)
+    builds = ctx.build_count() - b0
     log = ctx.thermo_log()
     E0 = log[0, 0, 1] + log[0, 0, 2]
     E1 = log[-1, 0, 1] + log[-1, 0, 2]
     lay = ctx.layout()
     nn = ctx._ws_view(lay.nn, s.n)
     nbar = float(nn.double().mean().item())
-    builds = ctx.build_count() - b0
-    out = dict(ms=max(gpu_ms, 1e-9), wall=wall, prof=prof, nbar=nbar, builds=builds,
+    # profiled window
+    ps = max(1, min(prof_steps, steps))
+    b1 = ctx.build_count()
+    ctx.profile(1)
+    e0.record(stream)
+    ctx.step(warmup + steps, ps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    prof = ctx.profile(2)
+    ctx.profile(0)
+    ctx.check()
+    prof_ms = e0.elapsed_time(e1)
+    out = dict(ms=max(gpu_ms, 1e-9), wall=wall, prof=prof, prof_steps=ps, prof_ms=prof_ms,
+               prof_builds=ctx.build_count() - b1, nbar=nbar, builds=builds,
                drift=abs(E1 - E0) / abs(E0), T_end=float(log[-1, 0, 4]),
                tuning=dict(tpp_nlist=tuning.tpp_nlist, block_nlist=tuning.block_nlist,
                            tpp_force=tuning.tpp_force, block_force=tuning.block_force))
@@ -80,6 +95,96 @@ def run_precision(B, inputs, torch, s, prec, steps, warmup, tune, fixed=None):
     del ctx
     torch.cuda.empty_cache()
     return out
+
+
+def force_check(B, torch, s):
+    """Mixed-precision forces against the FP64 path on the starting
+    configuration: max over particles of |F_mixed - F_fp64| / F_rms."""
+    import numpy as np
+    out = {}
+    for prec in (B.FP64, B.MIXED):
+        p = B.ModelParams(precision=prec, pair=B.PAIR_LJ, r_cut=2.5, r_buff=0.4, dt=0.005,
+                          sort_period=500)
+        ctx = B.Context([p], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+        ctx.build_nlist(True)
+        ctx.compute_forces(0, 0)
+        ctx.check()
+        x, v, f, tag = ctx.host_state()
+        F = np.empty((s.n, 3))
+        F[tag] = f[:, :3]
+        out[prec] = F
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    ref = out[B.FP64]
+    frms = float(np.sqrt(np.mean(ref ** 2)))
+    err = float(np.max(np.linalg.norm(out[B.MIXED] - ref, axis=1))) / frms
+    return {"max_err_over_Frms": err, "tolerance": 1e-5, "pass": err <= 1e-5, "F_rms": frms}
+
+
+COPY_BYTES = 1 << 30
+
+
+def pmc_pass(B, inputs, torch, s, fixed, steps):
+    """Workload for the hardware-counter passes: a plain streaming kernel of
+    known size (an elementwise negation reading and writing COPY_BYTES each),
+    then eager mixed-precision steps of the LJ bulk system."""
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+    kw = {k: int(fixed[k]) for k in ("tpp_nlist", "block_nlist", "tpp_force", "block_force")} if fixed else {}
+    p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_LJ, r_cut=2.5, r_buff=0.4, dt=0.005,
+                      sort_period=500, use_graph=0, **kw)
+    ctx = B.Context([p], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+    ctx.build_nlist(True)
+    ctx.step(0, steps)
+    ctx.check()
+    lay = ctx.layout()
+    nbar = float(ctx._ws_view(lay.nn, s.n).double().mean().item())
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"pmc_pass": True, "n": s.n, "steps": steps, "copy_bytes": COPY_BYTES,
+                      "mean_row": nbar}), flush=True)
+
+
+def _counter_rows(path):
+    """Per-dispatch counter sums from a rocprofv3 counter_collection.csv."""
+    import csv
+    per = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name", "")
+            did = row.get("Dispatch_Id") or row.get("Correlation_Id")
+            key = (did, name)
+            per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    return per
+
+
+def reduce_pmc(fetch_csv, write_csv, out_path, n):
+    """HBM bytes per fused force launch from a FETCH_SIZE pass and a
+    WRITE_SIZE pass (KiB per dispatch), each scaled by what the same counter
+    reads for the streaming kernel of known size."""
+    res = {"kernel_hash": kernel_hash(), "n": n}
+    for label, path in (("fetch", fetch_csv), ("write", write_csv)):
+        per = _counter_rows(path)
+        copy = [v for (d, k), v in per.items() if "neg" in k]
+        force = [v for (d, k), v in per.items() if "k_force" in k]
+        if not copy or not force:
+            raise SystemExit(f"{path}: no copy ({len(copy)}) or force ({len(force)}) dispatches")
+        copy_kib = sorted(copy)[len(copy) // 2]
+        scale = (COPY_BYTES / 1024.0) / copy_kib
+        force_kib = sum(force) / len(force)
+        res[label] = {"copy_kib_per_dispatch": copy_kib, "scale": scale,
+                      "force_kib_per_dispatch": force_kib, "force_dispatches": len(force),
+                      "bytes_per_launch": force_kib * 1024.0 * scale}
+    res["bytes_per_launch"] = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
 
 
 def cpu_baseline(s, seconds):
@@ -110,7 +215,7 @@ def cpu_baseline(s, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--no-tune", action="store_true")
@@ -121,7 +226,17 @@ def main():
                     help="write the lanes/block sizes chosen per precision to this JSON file")
     ap.add_argument("--tuning-from", default=None,
                     help="use lanes/block sizes from a file written by --tuning-out (no tuning)")
+    ap.add_argument("--prof-steps", type=int, default=1000,
+                    help="steps of the eager window timed per launch after the timed window")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="run the workload of a hardware-counter pass instead of the benchmark")
+    ap.add_argument("--reduce-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter_collection.csv of a FETCH_SIZE and a WRITE_SIZE pass "
+                         "into the per-launch traffic file and exit")
     args = ap.parse_args()
+    if args.reduce_pmc:
+        reduce_pmc(args.reduce_pmc[0], args.reduce_pmc[1], TRAFFIC_FILE, args.n)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only (the hot path of one subdomain); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -140,13 +255,16 @@ def main():
     if args.tuning_from:
         with open(args.tuning_from) as f:
             fixed = json.load(f)
+    if args.pmc_pass:
+        pmc_pass(B, inputs, torch, s, fixed.get("mixed"), args.steps)
+        return
     mixed = run_precision(B, inputs, torch, s, B.MIXED, args.steps, args.warmup, not args.no_tune,
-                          fixed.get("mixed"))
+                          fixed.get("mixed"), args.prof_steps)
     print(f"[bench] mixed done {mixed['ms']:.1f} ms", file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
         fp64 = run_precision(B, inputs, torch, s, B.FP64, args.steps, args.warmup, not args.no_tune,
-                             fixed.get("fp64"))
+                             fixed.get("fp64"), args.prof_steps)
         print(f"[bench] fp64 done {fp64['ms']:.1f} ms", file=sys.stderr, flush=True)
     if args.tuning_out:
         with open(args.tuning_out, "w") as f:
@@ -155,12 +273,20 @@ def main():
     K = args.steps
     value = s.n * K / (mixed["ms"] / 1e3)
     pr = mixed["prof"]
+    PS = mixed["prof_steps"]
     force_avg_ms = pr.force_ms / max(pr.force_launches, 1)
-    # algorithmic bytes of one fused force launch per particle: neighbour row
-    # (4 n) + its length (4) + own position (32) + velocity in and out (64) +
-    # new position (32) + position at the last build (32)
-    bytes_per_particle = 4.0 * mixed["nbar"] + 4 + 32 + 64 + 32 + 32
-    achieved = s.n * bytes_per_particle / (force_avg_ms / 1e3) / 1e9
+    # algorithmic bytes of one fused force launch per particle, with 4-byte
+    # neighbour indices and 24-byte vectors: the neighbour row and its length
+    # (4 n + 4), position, velocity and position at the last build read
+    # (3 x 24), position and velocity written (2 x 24); neighbour gathers are
+    # served by caches and not counted
+    bytes_per_particle = 4.0 * mixed["nbar"] + 4 + 3 * 24 + 2 * 24
+    alg_bytes_per_launch = s.n * bytes_per_particle
+    achieved = alg_bytes_per_launch / (force_avg_ms / 1e3) / 1e9
+    # compulsory bytes of a whole step in the two-pass model (separate force
+    # and integration passes, FP32 force array, rebuild every 10 steps)
+    step_bytes = (4.0 * mixed["nbar"] + 4 + 24 + 12) + (24 + 24 + 12 + 24 + 24 + 24) \
+        + (84 + 4.0 * mixed["nbar"]) / 10.0
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -188,10 +314,17 @@ def main():
         "T_end": mixed["T_end"],
         "rebuilds": mixed["builds"],
         "tuning": mixed["tuning"],
-        "phase_ms_per_step": {"force": pr.force_ms / K, "rebuild": pr.rebuild_ms / K},
+        "profiled_window": {"steps": PS, "ms_per_step": mixed["prof_ms"] / PS,
+                            "rebuilds": mixed["prof_builds"],
+                            "force_ms_per_step": pr.force_ms / PS,
+                            "rebuild_ms_per_step": pr.rebuild_ms / PS,
+                            "rebuild_ms_each": pr.rebuild_ms / max(pr.rebuild_launches, 1)},
+        "step_alg_bytes_per_particle": step_bytes,
+        "step_frac_of_hbm": step_bytes * s.n * K / (mixed["ms"] / 1e3) / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "kernel": "k_force (fused force + velocity Verlet)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes_per_launch,
                      "avg_launch_us": force_avg_ms * 1e3,
                      "alg_bytes_per_particle": bytes_per_particle, "mean_row": mixed["nbar"]},
     }
@@ -201,6 +334,7 @@ def main():
                         "tuning": fp64["tuning"],
                         "force_avg_us": fp64["prof"].force_ms / max(fp64["prof"].force_launches, 1) * 1e3}
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
+    line["force_check"] = force_check(B, torch, s)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
