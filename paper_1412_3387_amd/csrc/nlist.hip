@@ -392,6 +392,14 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
         const int64_t rowbase = nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
         const bool fx_ = px && bx < 3, fy_ = py && by < 3, fz_ = pz && bz < 3;
         const bool few = fx_ || fy_ || fz_;
+        const bool few_axis[3] = {fx_, fy_, fz_};
+        // offset of the particle inside its cell and the cell widths (FP32),
+        // for the conservative per-cell distance test
+        const float cellw[3] = {(float)(Lx / bx), (float)(Ly / by), (float)(Lz / bz)};
+        const float frel[3] = {(float)(xi.x - S.lo[0]) - (float)ci[0] * cellw[0],
+                               (float)(xi.y - S.lo[1]) - (float)ci[1] * cellw[1],
+                               (float)(xi.z - S.lo[2]) - (float)ci[2] * cellw[2]};
+        const float rl2f = (float)rl2 * 1.0001f + 1e-3f;
         int ntot = 0;
         for (int q0 = 0; q0 < nslot; q0 += kChunk) {
             const int q1 = q0 + kChunk < nslot ? q0 + kChunk : nslot;
@@ -410,10 +418,27 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
             for (int k = 0; k < kStencil; ++k) {
                 const int u = sh.su[t][k];
                 if (u < 0) continue;
+                // skip a neighbour cell whose nearest face lies beyond r_list
+                // (FP32 with a relative margin: it never drops a cell that can
+                // hold a neighbour)
+                {
+                    const int ox = k % 3, oy = (k / 3) % 3, oz = k / 9;
+                    float g2 = 0.f;
+                    const int offs[3] = {S.st[0][ox < S.nst[0] ? ox : 0], S.st[1][oy < S.nst[1] ? oy : 0],
+                                         S.st[2][oz < S.nst[2] ? oz : 0]};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        if (offs[a] == 0 || few_axis[a]) continue;
+                        const float g = offs[a] < 0 ? frel[a] : cellw[a] - frel[a];
+                        g2 += g > 0.f ? g * g : 0.f;
+                    }
+                    if (g2 > rl2f) continue;
+                }
                 const int code = sh.sm[t][k];
                 const double sx = Lx * (double)(code % 3 - 1);
                 const double sy = Ly * (double)((code / 3) % 3 - 1);
                 const double sz = Lz * (double)(code / 9 - 1);
+                const bool shifted = code != 13;
                 int a0 = sh.ustart[u], a1 = sh.ustart[u + 1];
                 a0 = a0 > q0 ? a0 : q0;
                 a1 = a1 < q1 ? a1 : q1;
@@ -438,7 +463,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
                             ddx[v] = fx_ ? min_image(ddx[v], Lx, iLx) : ddx[v] - sx;
                             ddy[v] = fy_ ? min_image(ddy[v], Ly, iLy) : ddy[v] - sy;
                             ddz[v] = fz_ ? min_image(ddz[v], Lz, iLz) : ddz[v] - sz;
-                        } else {
+                        } else if (shifted) {
                             ddx[v] -= sx;
                             ddy[v] -= sy;
                             ddz[v] -= sz;

@@ -52,18 +52,24 @@ def test_batch_forces_match_oracle(orc, B, prec):
 
 
 def test_batch_step_equals_single_systems(B):
-    """Each system of a batch evolves exactly as it does alone."""
+    """Each system of a batch evolves as it does alone.  The displacement
+    check is shared by the batch (a rebuild anywhere rebuilds every system),
+    so a system may be rebuilt at other steps than alone: its rows then hold
+    the same neighbours in another order and the sums round differently.  In
+    FP64 the trajectories agree to rounding."""
     batch = _batch(3, 3)
-    ctx = B.Context([_params(B, sy, 1) for sy in batch], _systems(batch))
+    ctx = B.Context([_params(B, sy, 0) for sy in batch], _systems(batch))
     ctx.step(0, 30)
     ctx.check()
     for k, sy in enumerate(batch):
-        one = B.Context([_params(B, sy, 1)], _systems([sy]))
+        one = B.Context([_params(B, sy, 0)], _systems([sy]))
         one.step(0, 30)
-        a = ctx.host_state(k)
-        b = one.host_state(0)
-        for x, y in zip(a, b):
-            assert np.array_equal(x, y), (k, sy.kind)
+        xa, va, fa, ta = ctx.host_state(k)
+        xb, vb, fb, tb = one.host_state(0)
+        xa, va = by_tag(ta, xa, va)
+        xb, vb = by_tag(tb, xb, vb)
+        assert np.max(np.abs(min_image_diff(xa, xb, sy.L))) < 1e-11, (k, sy.kind)
+        assert np.max(np.abs(va - vb)) < 1e-10, (k, sy.kind)
 
 
 def test_batch_short_run_fp64(orc, B):
