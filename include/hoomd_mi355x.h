@@ -242,11 +242,15 @@ int hoomd_build_count(hoomd_ctx *ctx, int64_t *builds);
  *          the row's 64-row tile;
  *   nn     int32[n] row lengths;
  *   halo   int32, halo_cap array rows (global row numbers) per tile, the
- *          first (halo_n[tile] & 0x7fffffff) valid;
+ *          first (halo_n[tile] & 0xffff) valid; bits 16-30 of halo_n hold
+ *          the tile's longest row, bit 31 marks a tile wider than half a
+ *          periodic box (per-pair minimum image in the force pass);
  *   cell_idx / cell_size: cell c holds cell_idx[c * cell_cap + k], k <
  *          cell_size[c] (global row numbers, ascending);
  *   bins per axis.  Row i of system s is row row_offset + i of the arrays,
- *   tile t of the system is tile tile_offset + t of halo and halo_n. */
+ *   tile t of the system is tile tile_offset + t of halo and halo_n.
+ *   general_tiles: int32 count, over all systems, of the tiles that the
+ *   last build handed from the framed build to the general one. */
 typedef struct {
     const uint16_t *nlist;
     const int32_t *nn;
@@ -261,6 +265,7 @@ typedef struct {
     int64_t row_offset;
     int64_t cell_offset;
     int64_t tile_offset;
+    const int32_t *general_tiles;
 } hoomd_layout;
 int hoomd_get_layout(hoomd_ctx *ctx, int32_t sys, hoomd_layout *out);
 

@@ -66,7 +66,7 @@ class Layout(C.Structure):
                 ("halo_n", C.c_void_p), ("cell_idx", C.c_void_p), ("cell_size", C.c_void_p),
                 ("nlist_cap", C.c_int32), ("cell_cap", C.c_int32), ("halo_cap", C.c_int32),
                 ("bins", C.c_int32 * 3), ("row_offset", C.c_int64), ("cell_offset", C.c_int64),
-                ("tile_offset", C.c_int64)]
+                ("tile_offset", C.c_int64), ("general_tiles", C.c_void_p)]
 
 
 class Tuning(C.Structure):
@@ -358,6 +358,11 @@ class Context:
             t, l = divmod(r, 64)
             rows.append(halo[t][nl[t, : nn[r], l]].astype(np.int64) - o)
         return nn, rows
+
+    def general_tiles(self) -> int:
+        """Tiles of the last build that went to the general (unframed) build."""
+        lay = self.layout(0)
+        return int(self._ws_view(lay.general_tiles, 1).cpu().item())
 
     def halo_sizes(self, sys: int = 0) -> np.ndarray:
         lay = self.layout(sys)

@@ -39,6 +39,8 @@ struct LaunchCtx {
     const int32_t *partners;       // per tag: bond_cap partner tags (-1 = none)
     int32_t *rtag;                 // row of each tag (per system offset row0)
     bool has_bonds;
+    int32_t *slow_list;            // tiles the framed build passes on to the general one
+    int32_t *slow_n;               // their number (cleared by the binning launch)
     int32_t *flag;                 // rebuild flag read by the rebuild kernels
     int32_t *build_count;
     uint32_t *step_counter;        // advanced by the binning launch when set (graph steps)
@@ -75,5 +77,7 @@ void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value);
 void launch_rtag(const LaunchCtx &L, const int32_t *tag);
 void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag);
 size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
+size_t fast_build_lds_bytes(int nlist_cap);
+hipError_t prepare_nlist(int nlist_cap);
 
 }  // namespace md

@@ -51,12 +51,13 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
                                              int32_t *__restrict__ cell_count,
                                              int32_t *__restrict__ cell_idx, int cell_cap,
                                              const int32_t *__restrict__ flag, Status *st,
-                                             uint32_t *step_counter)
+                                             uint32_t *step_counter, int32_t *slow_n)
 {
     // the binning launch follows every fused step launch: it also advances
     // the device step counter read by graph-replayed steps
     if (step_counter && blockIdx.x == 0 && threadIdx.x == 0) *step_counter += 1u;
     if (*flag == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *slow_n = 0;
     const int lane = lane_id();
     const uint64_t lt = lanemask_lt();
     const int waves = (int)(gridDim.x * blockDim.x) >> 6;
@@ -165,9 +166,10 @@ struct BuildShared {
     int32_t info[4];                  // distinct cells, per-pair image flag, longest row
 };
 
-// Exclusive block scan of n <= 8 * kBuildThreads values held in LDS `a`
-// (in place); returns the total.
-__device__ __forceinline__ int block_scan8(int32_t *a, int n, int32_t *scan)
+// Exclusive scan of n <= 8 * NT values held in LDS `a` (in place) by a block
+// of NT threads; returns the total.
+template <int NT>
+__device__ __forceinline__ int block_scan(int32_t *a, int n, int32_t *scan)
 {
     const int tid = threadIdx.x;
     const int b = 8 * tid;
@@ -180,14 +182,14 @@ __device__ __forceinline__ int block_scan8(int32_t *a, int n, int32_t *scan)
     }
     scan[tid] = sum;
     __syncthreads();
-    for (int off = 1; off < kBuildThreads; off <<= 1) {
+    for (int off = 1; off < NT; off <<= 1) {
         const int add = tid >= off ? scan[tid - off] : 0;
         __syncthreads();
         scan[tid] += add;
         __syncthreads();
     }
     int run = tid > 0 ? scan[tid - 1] : 0;
-    const int total = scan[kBuildThreads - 1];
+    const int total = scan[NT - 1];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
         if (b + k < n) {
@@ -196,6 +198,11 @@ __device__ __forceinline__ int block_scan8(int32_t *a, int n, int32_t *scan)
         }
     __syncthreads();
     return total;
+}
+
+__device__ __forceinline__ int block_scan8(int32_t *a, int n, int32_t *scan)
+{
+    return block_scan<kBuildThreads>(a, n, scan);
 }
 
 // Index of the largest entry <= x in the ascending array a[0..n).
@@ -217,9 +224,13 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
     const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx, int cell_cap,
     uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int32_t *__restrict__ halo,
     int32_t *__restrict__ halo_n, int halo_cap, double4 *__restrict__ xbuild,
+    const int32_t *__restrict__ list, const int32_t *__restrict__ list_n,
     const int32_t *__restrict__ flag, int32_t *build_count, Status *st)
 {
     if (*flag == 0) return;
+    // with a list: only the tiles named there (those the framed build passed on)
+    const int ntiles = list ? *list_n : tiles;
+    if ((int)blockIdx.x >= ntiles && !(build_count && blockIdx.x == 0)) return;
     __shared__ BuildShared sh;
     constexpr int W = kBuildW;
     constexpr int P = kWave / W;
@@ -231,9 +242,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
     const int t = w * P + pl;  // particle slot in the tile
     const uint64_t seg = segment_bits(pl, P);
     const uint64_t below = lanemask_lt();
-    if (blockIdx.x == 0 && tid == 0) atomicAdd(build_count, 1);
+    if (build_count && blockIdx.x == 0 && tid == 0) atomicAdd(build_count, 1);
 
-    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
+        const int tile = list ? list[it] : it;
         const int s = find_sys(tprefix, n_sys, tile);
         const SysDev &S = sys[s];
         // per-system constants, held in registers for the whole tile
@@ -541,6 +553,416 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 }
 
 // ---------------------------------------------------------------------------
+// framed tile build
+// ---------------------------------------------------------------------------
+//
+// The common case of the build above, reorganised so that the work per
+// candidate is a handful of FP32 operations:
+//   * The tile's cells are placed in one frame: cell coordinates relative to
+//     the first row's cell, unwrapped across periodic faces.  The stencil
+//     cells of all rows are marked in a bitmap over the frame's box (home
+//     cells +-1), so the distinct cells come out in box order and the three
+//     x-adjacent cells of a row's stencil line are three consecutive distinct
+//     cells: a row's candidates are nine contiguous slot ranges ("runs").
+//   * Members are staged as FP32 positions in the frame, relative to the
+//     first row.  One wave takes one row at a time; its lanes split the nine
+//     runs (10 lanes for the centre line, 7 for each edge line, 6 for each
+//     corner line).  A candidate whose FP32 distance lies clearly inside or
+//     outside r_list is decided there; one within a relative band of 2^-10
+//     of r_list^2 is decided by the FP64 test of the oracle (difference of the
+//     stored positions, then the periodic shift), so the list is exactly the
+//     FP64 one.  The FP32 error is bounded by 4 sqrt(3) F 2^-24 / r_list
+//     relative, F the frame extent; tiles with F > 512 r_list are passed on.
+//   * Rows are assembled in LDS and written out coalesced after the halo
+//     numbering, without a read-back.
+// Tiles that do not fit (a frame wider than a periodic box, fewer than three
+// cells on a periodic axis, too many distinct cells or members) are appended
+// to a device list and built by k_build_tile.
+
+constexpr int kFastThreads = 512;
+constexpr int kFastWaves = kFastThreads / kWave;
+constexpr int kFastChunk = 2816;     // members staged at once (float4 each)
+constexpr int kBoxMax = 4096;        // cells of the frame box
+constexpr int kBoxWords = kBoxMax / 32;
+constexpr int kUMax = 512;           // distinct cells of a framed tile
+constexpr int kFastSlotMax = 8192;   // members of a framed tile's stencil cells
+constexpr int kRuns = 9;
+constexpr float kBand = 1.0f / 1024.0f;
+
+struct FastShared {
+    float4 cp[kFastChunk];               // member position in the frame (FP32), row in w
+    uint32_t box[kBoxWords];             // stencil cells in the frame box
+    int32_t bpre[kBoxWords + 1];         // set bits before each box word
+    int16_t ubit[kUMax];                 // box bit of each distinct cell
+    int32_t ustart[kUMax + 1];           // first slot of each distinct cell
+    uint32_t used[kFastSlotMax / 32];
+    int32_t wpre[kFastSlotMax / 32 + 1];
+    uint32_t run[kTile][kRuns];          // slot range of each row line: lo | hi << 16
+    float4 xrow[kTile];                  // row position in the frame (FP32)
+    float frel[3][kTile];                // row offset inside its home cell
+    int16_t rh[3][kTile];                // row home cell in the frame
+    int32_t rown[kTile];                 // hits of each row so far
+    int32_t scan[kFastThreads];
+    int32_t ext[6];
+    int32_t info[4];                     // pass-on flag, per-pair image flag, longest row
+};
+
+// first lane of each line of a row: corners 6 lanes, edges 7, centre 10
+__constant__ int8_t kRunLane[kRuns + 1] = {0, 6, 13, 19, 26, 36, 43, 49, 56, 62};
+
+template <bool EXCL>
+__global__ __launch_bounds__(kFastThreads) void k_build_fast(
+    const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
+    const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ partners,
+    const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx, int cell_cap,
+    uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int rstride,
+    int32_t *__restrict__ halo, int32_t *__restrict__ halo_n, int halo_cap,
+    double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n,
+    const int32_t *__restrict__ flag, int32_t *build_count, Status *st)
+{
+    if (*flag == 0) return;
+    __shared__ FastShared sh;
+    extern __shared__ uint16_t srows[];  // [kTile][rstride]: staged slot of each hit
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = tid >> 6;
+    const uint64_t below = lanemask_lt();
+    int rho = 0;
+#pragma unroll
+    for (int k = 1; k <= kRuns; ++k) rho += lane >= kRunLane[k] ? 1 : 0;
+    const bool lane_on = rho < kRuns;
+    const int sub = lane_on ? lane - kRunLane[rho] : 0;
+    const int g = lane_on ? kRunLane[rho + 1] - kRunLane[rho] : 1;
+    if (blockIdx.x == 0 && tid == 0) atomicAdd(build_count, 1);
+
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int s = find_sys(tprefix, n_sys, tile);
+        const SysDev &S = sys[s];
+        const double Ls[3] = {S.L[0], S.L[1], S.L[2]};
+        const double iL[3] = {S.invL[0], S.invL[1], S.invL[2]};
+        const int bins[3] = {S.bins[0], S.bins[1], S.bins[2]};
+        const int per[3] = {S.per[0], S.per[1], S.per[2]};
+        const int64_t row0 = S.row0, cell0 = S.cell0, nl0 = S.nl0;
+        const int n_local = S.n_local;
+        const double rl2 = S.rl2;
+        const int r0 = (tile - S.tile0) * kTile;
+        const double4 x0 = pos[row0 + r0];
+        int c0[3];
+        c0[0] = cell_coord(x0.x, S.lo[0], S.scale[0], bins[0]);
+        c0[1] = cell_coord(x0.y, S.lo[1], S.scale[1], bins[1]);
+        c0[2] = cell_coord(x0.z, S.lo[2], S.scale[2], bins[2]);
+        const float cw[3] = {(float)(Ls[0] / bins[0]), (float)(Ls[1] / bins[1]), (float)(Ls[2] / bins[2])};
+
+        __syncthreads();  // LDS of the previous tile no longer read
+        if (tid < 3) {
+            sh.ext[tid] = INT32_MAX;
+            sh.ext[3 + tid] = INT32_MIN;
+        }
+        if (tid == 0) {
+            sh.info[0] = 0;
+            sh.info[2] = 0;
+        }
+        __syncthreads();
+        // ---- 1. rows: home cell in the frame, frame position ------------------
+        double4 xi = x0;
+        int64_t i = row0 + r0;
+        bool act = false;
+        if (tid < kTile) {
+            const int r = r0 + tid;
+            act = r < n_local;
+            i = row0 + (act ? r : r0);
+            xi = pos[i];
+            const double xa[3] = {xi.x, xi.y, xi.z};
+            float xf[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int ci = cell_coord(xa[a], S.lo[a], S.scale[a], bins[a]);
+                const int h = per[a] ? wrap_rel(ci - c0[a], bins[a]) : ci - c0[a];
+                // image of the row in the frame: the home cell at c0 + h
+                const int kimg = per[a] ? (c0[a] + h - ci) / bins[a] : 0;
+                xf[a] = (float)((xa[a] + (double)kimg * Ls[a]) - (a == 0 ? x0.x : (a == 1 ? x0.y : x0.z)));
+                sh.rh[a][tid] = (int16_t)h;
+                sh.frel[a][tid] = (float)(xa[a] - S.lo[a]) - (float)ci * cw[a];
+                if (act) {
+                    atomicMin(&sh.ext[a], h);
+                    atomicMax(&sh.ext[3 + a], h);
+                }
+            }
+            sh.xrow[tid] = make_float4(xf[0], xf[1], xf[2], 0.f);
+            sh.rown[tid] = act ? 0 : -1;
+        }
+        __syncthreads();
+        // ---- 2. frame box and the stencil-cell bitmap ---------------------------
+        int blo[3], X[3];
+        bool pass = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int lo_ = sh.ext[a] - 1, hi_ = sh.ext[3 + a] + 1;
+            if (!per[a]) {
+                lo_ = lo_ > -c0[a] ? lo_ : -c0[a];
+                hi_ = hi_ < bins[a] - 1 - c0[a] ? hi_ : bins[a] - 1 - c0[a];
+            } else if (bins[a] < 3 || hi_ - lo_ + 1 > bins[a]) {
+                pass = true;
+            }
+            blo[a] = lo_;
+            X[a] = hi_ - lo_ + 1;
+            if ((double)X[a] * (double)cw[a] > 512.0 * sqrt(rl2)) pass = true;
+        }
+        const int vol = X[0] * X[1] * X[2];
+        if (vol > kBoxMax) pass = true;
+        if (pass) {
+            if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
+            continue;
+        }
+        const int nbw = (vol + 31) >> 5;
+        for (int q = tid; q < nbw; q += kFastThreads) sh.box[q] = 0u;
+        __syncthreads();
+        for (int e = tid; e < kTile * 27; e += kFastThreads) {
+            const int t = e / 27, k = e - 27 * (e / 27);
+            if (r0 + t >= n_local) continue;
+            const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+            int f[3];
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                f[a] = sh.rh[a][t] + o[a];
+                if (!per[a]) in = in && c0[a] + f[a] >= 0 && c0[a] + f[a] < bins[a];
+            }
+            if (!in) continue;
+            const int b = ((f[2] - blo[2]) * X[1] + (f[1] - blo[1])) * X[0] + (f[0] - blo[0]);
+            atomicOr(&sh.box[b >> 5], 1u << (b & 31));
+        }
+        __syncthreads();
+        // ---- 3. distinct cells (box order) and their members ----------------------
+        for (int q = tid; q < nbw; q += kFastThreads) sh.bpre[q] = __popc(sh.box[q]);
+        __syncthreads();
+        const int nu = block_scan<kFastThreads>(sh.bpre, nbw, sh.scan);
+        if (tid == 0) sh.bpre[nbw] = nu;
+        if (nu > kUMax) {
+            if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
+            continue;
+        }
+        for (int q = tid; q < nbw; q += kFastThreads) {
+            uint32_t word = sh.box[q];
+            int u = sh.bpre[q];
+            while (word) {
+                const int bit = __ffs(word) - 1;
+                sh.ubit[u++] = (int16_t)(q * 32 + bit);
+                word &= word - 1u;
+            }
+        }
+        __syncthreads();
+        for (int u = tid; u < nu; u += kFastThreads) {
+            const int b = sh.ubit[u];
+            const int f0 = b % X[0] + blo[0], f1 = (b / X[0]) % X[1] + blo[1], f2 = b / (X[0] * X[1]) + blo[2];
+            int p0 = c0[0] + f0, p1 = c0[1] + f1, p2 = c0[2] + f2;
+            p0 -= p0 >= bins[0] ? bins[0] : (p0 < 0 ? -bins[0] : 0);
+            p1 -= p1 >= bins[1] ? bins[1] : (p1 < 0 ? -bins[1] : 0);
+            p2 -= p2 >= bins[2] ? bins[2] : (p2 < 0 ? -bins[2] : 0);
+            const int m = cell_size[cell0 + ((int64_t)p2 * bins[1] + p1) * bins[0] + p0];
+            sh.ustart[u] = m < cell_cap ? m : cell_cap;
+        }
+        __syncthreads();
+        const int nslot = block_scan<kFastThreads>(sh.ustart, nu, sh.scan);
+        if (tid == 0) {
+            sh.ustart[nu] = nslot;
+            int pp = 0;
+            for (int a = 0; a < 3; ++a)
+                if (per[a] && (double)(sh.ext[3 + a] - sh.ext[a] + 3) * (Ls[a] / bins[a]) >= 0.5 * Ls[a]) pp = 1;
+            sh.info[1] = pp;
+        }
+        if (nslot > kFastSlotMax) {
+            if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
+            continue;
+        }
+        for (int q = tid; q < (nslot + 31) / 32; q += kFastThreads) sh.used[q] = 0u;
+        __syncthreads();
+        // ---- 4. the nine lines of every row, cut to cells within r_list -------------
+        const float rl2f = (float)rl2 * 1.0001f + 1e-3f;
+        for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
+            const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
+            uint32_t v = 0u;
+            if (r0 + t < n_local) {
+                const int dy = rr % 3 - 1, dz = rr / 3 - 1;
+                const int hx = sh.rh[0][t], hy = sh.rh[1][t] + dy, hz = sh.rh[2][t] + dz;
+                bool in = (per[1] || (c0[1] + hy >= 0 && c0[1] + hy < bins[1])) &&
+                          (per[2] || (c0[2] + hz >= 0 && c0[2] + hz < bins[2]));
+                float gyz = 0.f;
+                if (dy != 0) {
+                    const float gg = dy < 0 ? sh.frel[1][t] : cw[1] - sh.frel[1][t];
+                    gyz += gg > 0.f ? gg * gg : 0.f;
+                }
+                if (dz != 0) {
+                    const float gg = dz < 0 ? sh.frel[2][t] : cw[2] - sh.frel[2][t];
+                    gyz += gg > 0.f ? gg * gg : 0.f;
+                }
+                in = in && gyz <= rl2f;
+                if (in) {
+                    const float fx = sh.frel[0][t];
+                    const float gl = fx > 0.f ? fx : 0.f, gr = cw[0] - fx > 0.f ? cw[0] - fx : 0.f;
+                    const bool left = (per[0] || c0[0] + hx - 1 >= 0) && gl * gl + gyz <= rl2f;
+                    const bool right = (per[0] || c0[0] + hx + 1 < bins[0]) && gr * gr + gyz <= rl2f;
+                    const int xa = hx + (left ? -1 : 0), xb = hx + (right ? 1 : 0);
+                    const int b = ((hz - blo[2]) * X[1] + (hy - blo[1])) * X[0] + (xa - blo[0]);
+                    const int u0 = sh.bpre[b >> 5] + __popc(sh.box[b >> 5] & ((1u << (b & 31)) - 1u));
+                    const int u1 = u0 + (xb - xa);
+                    v = (uint32_t)sh.ustart[u0] | ((uint32_t)sh.ustart[u1 + 1] << 16);
+                }
+            }
+            sh.run[t][rr] = v;
+        }
+        // ---- 5. stage members a chunk at a time, scan every row's lines -------------
+        const float lo_f = (float)rl2 * (1.0f - kBand), hi_f = (float)rl2 * (1.0f + kBand);
+        const double xr[3] = {x0.x, x0.y, x0.z};
+        for (int q0 = 0; q0 < nslot; q0 += kFastChunk) {
+            const int q1 = q0 + kFastChunk < nslot ? q0 + kFastChunk : nslot;
+            __syncthreads();
+            for (int q = q0 + tid; q < q1; q += kFastThreads) {
+                const int u = upper_idx(sh.ustart, nu, q);
+                const int b = sh.ubit[u];
+                const int f[3] = {b % X[0] + blo[0], (b / X[0]) % X[1] + blo[1], b / (X[0] * X[1]) + blo[2]};
+                int pc[3], kimg[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    pc[a] = c0[a] + f[a];
+                    kimg[a] = pc[a] >= bins[a] ? 1 : (pc[a] < 0 ? -1 : 0);
+                    pc[a] -= kimg[a] * bins[a];
+                }
+                const int64_t key = ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0];
+                const int32_t j = cell_idx[(cell0 + key) * cell_cap + (q - sh.ustart[u])];
+                const double4 xj = pos[j];
+                sh.cp[q - q0] = make_float4((float)((xj.x + (double)kimg[0] * Ls[0]) - xr[0]),
+                                            (float)((xj.y + (double)kimg[1] * Ls[1]) - xr[1]),
+                                            (float)((xj.z + (double)kimg[2] * Ls[2]) - xr[2]),
+                                            __int_as_float(j));
+            }
+            __syncthreads();
+            for (int t = wv; t < kTile; t += kFastWaves) {
+                int ntot = sh.rown[t];
+                if (ntot < 0) continue;  // inactive row
+                const float4 xt = sh.xrow[t];
+                const int32_t it = (int32_t)(row0 + r0 + t);
+                int32_t part[kMaxBondCap];
+                if constexpr (EXCL) {
+                    const int64_t prow = (row0 + tag[it]) * S.bond_cap;
+#pragma unroll
+                    for (int b = 0; b < kMaxBondCap; ++b)
+                        part[b] = b < S.bond_cap ? partners[prow + b] : -1;
+                }
+                const uint32_t rv = lane_on ? sh.run[t][rho] : 0u;
+                int a0 = (int)(rv & 0xffffu), a1 = (int)(rv >> 16);
+                a0 = a0 > q0 ? a0 : q0;
+                a1 = a1 < q1 ? a1 : q1;
+                for (int q = a0 + sub;; q += g) {
+                    const bool on = q < a1;
+                    if (__ballot(on) == 0ull) break;
+                    bool hit = false;
+                    if (on) {
+                        const float4 c = sh.cp[q - q0];
+                        const float dx = c.x - xt.x, dy = c.y - xt.y, dz = c.z - xt.z;
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        const int32_t j = __float_as_int(c.w);
+                        hit = r2 < lo_f;
+                        if (!hit && r2 <= hi_f) {
+                            // near r_list: the oracle's FP64 test
+                            const double4 xa = pos[it], xb = pos[j];
+                            const double cj[3] = {(double)c.x, (double)c.y, (double)c.z};
+                            const double xt3[3] = {(double)xt.x, (double)xt.y, (double)xt.z};
+                            const double pa[3] = {xa.x, xa.y, xa.z}, pb[3] = {xb.x, xb.y, xb.z};
+                            double d[3];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                // frame images of both: k = round((frame - stored) / L)
+                                const double kj = rint((cj[a] + xr[a] - pb[a]) * iL[a]);
+                                const double ki = rint((xt3[a] + xr[a] - pa[a]) * iL[a]);
+                                d[a] = pb[a] - pa[a];
+                                if (kj != ki) d[a] = d[a] + (kj - ki) * Ls[a];
+                            }
+                            hit = norm2_exact(d[0], d[1], d[2]) < rl2;
+                        }
+                        hit = hit && j != it;
+                        if constexpr (EXCL) {
+                            if (hit) {
+                                const int32_t tj = tag[j];
+#pragma unroll
+                                for (int b = 0; b < kMaxBondCap; ++b) hit = hit && part[b] != tj;
+                            }
+                        }
+                    }
+                    const uint64_t mask = __ballot(hit);
+                    if (hit) {
+                        const int p = ntot + __popcll(mask & below);
+                        if (p < cap) srows[t * rstride + p] = (uint16_t)q;
+                        atomicOr(&sh.used[q >> 5], 1u << (q & 31));
+                    }
+                    ntot += __popcll(mask);
+                }
+                if (lane == 0) sh.rown[t] = ntot;
+            }
+        }
+        __syncthreads();
+        // ---- 6. halo numbering, rows out ------------------------------------------
+        if (tid < kTile && act) {
+            const int n = sh.rown[tid];
+            atomicMax(&sh.info[2], n < cap ? n : cap);
+        }
+        const int nwords = (nslot + 31) / 32;
+        for (int q = tid; q < nwords; q += kFastThreads) sh.wpre[q] = __popc(sh.used[q]);
+        __syncthreads();
+        const int nhalo = block_scan<kFastThreads>(sh.wpre, nwords, sh.scan);
+        if (nhalo > halo_cap) {
+            if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nhalo);
+            if (tid < kTile && act) nn[i] = 0;
+            if (tid == 0) halo_n[tile] = 0;
+            continue;
+        }
+        int32_t *hl = halo + (int64_t)tile * halo_cap;
+        const bool one_chunk = nslot <= kFastChunk;
+        for (int q = tid; q < nslot; q += kFastThreads) {
+            const uint32_t word = sh.used[q >> 5];
+            if (word & (1u << (q & 31))) {
+                const int h = sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u));
+                int32_t j;
+                if (one_chunk) {
+                    j = __float_as_int(sh.cp[q].w);
+                } else {
+                    const int u = upper_idx(sh.ustart, nu, q);
+                    const int b = sh.ubit[u];
+                    int pc[3] = {c0[0] + b % X[0] + blo[0], c0[1] + (b / X[0]) % X[1] + blo[1],
+                                 c0[2] + b / (X[0] * X[1]) + blo[2]};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) pc[a] -= pc[a] >= bins[a] ? bins[a] : (pc[a] < 0 ? -bins[a] : 0);
+                    const int64_t key = ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0];
+                    j = cell_idx[(cell0 + key) * cell_cap + (q - sh.ustart[u])];
+                }
+                hl[h] = j;
+            }
+        }
+        const int kmax = sh.info[2];
+        if (tid == 0)
+            halo_n[tile] = (int32_t)((uint32_t)nhalo | ((uint32_t)kmax << 16) | (sh.info[1] ? 0x80000000u : 0u));
+        uint16_t *out = nlist + nl0 + (int64_t)(r0 >> 6) * cap * kTile;
+        for (int e = tid; e < kmax * kTile; e += kFastThreads) {
+            const int k = e >> 6, t = e & 63;
+            uint16_t v = 0;
+            const int n = sh.rown[t];
+            if (k < n && k < cap) {
+                const int q = srows[t * rstride + k];
+                const uint32_t word = sh.used[q >> 5];
+                v = (uint16_t)(sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u)));
+            }
+            out[e] = v;
+        }
+        if (tid < kTile && act) {
+            const int n = sh.rown[tid];
+            nn[i] = n < cap ? n : cap;
+            xbuild[i] = xi;
+            if (n > cap) latch(st, 5 /*NLIST_OVERFLOW*/, n);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 
@@ -552,7 +974,7 @@ void launch_bin(const LaunchCtx &L, const double4 *pos)
     const int blocks = capped(((int64_t)L.tiles_all * kWave + 255) / 256);
     hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.tprefix_all, L.n_sys,
                        L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.status,
-                       L.step_counter);
+                       L.step_counter, L.slow_n);
 }
 
 void launch_cell_sort(const LaunchCtx &L)
@@ -567,22 +989,55 @@ void launch_cell_sort(const LaunchCtx &L)
                            L.cell_size, L.cell_idx, L.cell_cap, L.flag);
 }
 
+int nlist_row_stride(int cap)
+{
+    // uint16 entries per staged row; an odd number of words keeps the
+    // transposed read-out free of bank conflicts
+    int r = cap + (cap & 1);
+    if (((r / 2) & 1) == 0) r += 2;
+    return r;
+}
+
+size_t fast_build_lds_bytes(int cap) { return sizeof(FastShared) + (size_t)kTile * nlist_row_stride(cap) * 2; }
+
+hipError_t prepare_nlist(int cap)
+{
+    const int dyn = kTile * nlist_row_stride(cap) * 2;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_build_fast<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_build_fast<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    return e;
+}
+
 void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int w, int block)
 {
     (void)w;
     (void)block;
     if (L.tiles_local == 0) return;
     const int blocks = capped(L.tiles_local);
-    if (L.has_bonds)
+    const int rs = nlist_row_stride(L.nlist_cap);
+    const size_t dyn = (size_t)kTile * rs * 2;
+    if (L.has_bonds) {
+        hipLaunchKernelGGL(k_build_fast<true>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
+                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
+                           L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
+                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.flag, L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<true>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                           L.halo_cap, L.xbuild, L.flag, L.build_count, L.status);
-    else
+                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.flag, nullptr, L.status);
+    } else {
+        hipLaunchKernelGGL(k_build_fast<false>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
+                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
+                           L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
+                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.flag, L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<false>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                           L.halo_cap, L.xbuild, L.flag, L.build_count, L.status);
+                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.flag, nullptr, L.status);
+    }
 }
 
 }  // namespace md

@@ -34,7 +34,7 @@ struct Layout {
     // byte offsets into the workspace
     size_t sysdev, tpl, tpa, status, flags, thermo, thermo_log, partials;
     size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, halo, halo_n;
-    size_t rtag, partners, sort_ws, ghost_ws, total;
+    size_t rtag, partners, slow_list, sort_ws, ghost_ws, total;
     // sizes
     int64_t rows, tiles_local, tiles_all, n_cells, nlist_entries;
     int cell_cap, nlist_cap, bond_cap, halo_cap;
@@ -230,6 +230,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.cell_idx = take(sizeof(int32_t) * (size_t)cell * Lo.cell_cap);
     Lo.rtag = take(sizeof(int32_t) * rows);
     Lo.partners = take(sizeof(int32_t) * rows * std::max(Lo.bond_cap, 1));
+    Lo.slow_list = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
     Lo.sort_ws = take(sort_workspace_bytes((int64_t)rows));
     Lo.ghost_ws = take(ghost_workspace_bytes((int64_t)rows, n_sys));
     Lo.total = off;
@@ -313,6 +314,9 @@ size_t mark(hoomd_ctx *c)
     return k;
 }
 
+// Device flags: 0 and 1 rebuild flags of the two buffer parities, 2 the flag
+// of explicit builds, 4 build counter, 5 step counter of replayed steps, 6
+// tiles passed from the framed build to the general one.
 int32_t *flag_ptr(hoomd_ctx *c, int k) { return ws_ptr<int32_t>(c, c->lay.flags) + k; }
 
 // Queue the rebuild sequence: bin -> per-cell sort -> neighbour rows.  Every
@@ -456,6 +460,8 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.has_bonds = nb_total > 0;
     L.flag = flag_ptr(c, 0);
     L.build_count = flag_ptr(c, 4);
+    L.slow_list = ws_ptr<int32_t>(c, lay.slow_list);
+    L.slow_n = flag_ptr(c, 6);
     L.status = ws_ptr<Status>(c, lay.status);
     L.partials = ws_ptr<double>(c, lay.partials);
     L.thermo = ws_ptr<double>(c, lay.thermo);
@@ -469,8 +475,8 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     }
 
     // descriptors, prefixes, cleared counters (synchronous: init is not hot)
-    hipError_t e = hipSuccess;
-    e = hipMemcpy(c->ws + lay.sysdev, lay.sys.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice);
+    hipError_t e = prepare_nlist(lay.nlist_cap);
+    if (e == hipSuccess) e = hipMemcpy(c->ws + lay.sysdev, lay.sys.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpl, lay.tpl_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpa, lay.tpa_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.status, 0, sizeof(Status));
@@ -813,6 +819,7 @@ int hoomd_get_layout(hoomd_ctx *c, int32_t sys, hoomd_layout *out)
     out->row_offset = S.row0;
     out->cell_offset = S.cell0;
     out->tile_offset = S.tile0;
+    out->general_tiles = c->L.slow_n;
     return HOOMD_OK;
 }
 

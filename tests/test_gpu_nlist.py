@@ -137,3 +137,26 @@ def test_bulk_sampled_rows(orc, B):
     rng = np.random.default_rng(0)
     which = np.sort(rng.choice(s.n, 64, replace=False))
     assert neighbor_sets_equal(orc, ctx, s.pos, s.L, 2.5, 0.4, which=which) == []
+
+
+@pytest.mark.parametrize("n,sort_period", [(4000, 0), (4000, 1), (30000, 1), (30000, 0)])
+def test_framed_and_general_builds_agree_with_oracle(orc, B, n, sort_period):
+    """Tiles built in one unwrapped frame (FP32 filter, FP64 decision near
+    r_list) and tiles passed to the general build both give the exact
+    sets.  Lattice-ordered rows span the box and go to the general build;
+    Morton-ordered rows are framed."""
+    s = inputs.lj_fluid(n, 41, 42)
+    ctx = _ctx(B, s.pos, s.vel, s.L, sort_period=sort_period)
+    ctx.build_nlist(True)
+    ctx.check()
+    tiles = (n + 63) // 64
+    general = ctx.general_tiles()
+    assert 0 <= general <= tiles
+    if sort_period:
+        assert general < tiles // 4
+    else:
+        assert general > 0
+    assert neighbor_sets_equal(orc, ctx, s.pos, s.L, 2.5, 0.4) == []
+    nn, rows = ctx.neighbor_rows()
+    for r in rows:
+        assert len(np.unique(r)) == len(r)
