@@ -59,6 +59,32 @@ struct SysDev {
     double dt, hdt;
 };
 
+// Workgroup b of a launch runs on accelerator die b % kDies, and each die has
+// its own L2.  Neighbouring tiles share most of their halo, so the tiles are
+// handed out so that the workgroups of one die walk one contiguous run of
+// them (Morton-ordered rows make that run one compact region of space).
+constexpr int kDies = 8;
+
+// Tile of workgroup b in a launch of nb workgroups, one tile each.
+__device__ __forceinline__ int die_tile(int b, int nb)
+{
+    const int x = b % kDies, l = b / kDies;
+    const int per = nb / kDies, rem = nb % kDies;
+    return x * per + (x < rem ? x : rem) + l;
+}
+
+// Items [first, end) with stride step of workgroup b when nb workgroups loop
+// over n items: the dies that have workgroups split the items into
+// contiguous runs.
+__device__ __forceinline__ void die_range(int b, int nb, int64_t n, int64_t &first, int64_t &end, int &step)
+{
+    const int D = nb < kDies ? nb : kDies;
+    const int x = b % D, l = b / D;
+    step = nb / D + (x < nb % D ? 1 : 0);
+    first = n * x / D + l;
+    end = n * (x + 1) / D;
+}
+
 // System owning a tile: largest s with prefix[s] <= tile (prefix has n_sys+1
 // entries, prefix[0] = 0).  Called with a wave-uniform tile.
 __device__ __forceinline__ int find_sys(const int32_t *__restrict__ prefix, int n_sys, int tile)

@@ -39,21 +39,28 @@ template <> __device__ __forceinline__ double tlog<double>(double x) { return lo
 // LJ-family pair term for one neighbour inside the cut-off.  Returns the
 // force divided by r (F_i = ff * (x_i - x_j)); adds energy and virial.
 template <typename T, bool LOG>
-__device__ __forceinline__ T lj_pair(double r2, T eps, T sig2, double shift, double &e, double &vir)
+__device__ __forceinline__ T lj_pair(double r2, T eps, T sig2, double shift, double &e, double &vir,
+                                    bool in = true)
 {
     const T r2inv = recip<T>((T)r2);
     const T s2 = sig2 * r2inv;
     const T s6 = s2 * s2 * s2;
     const T ff = (T)24 * eps * s6 * ((T)2 * s6 - (T)1) * r2inv;
     if constexpr (LOG) {
-        e += (double)((T)4 * eps * s6 * (s6 - (T)1)) - shift;
-        vir += (double)(ff * (T)r2);
+        if (in) {
+            e += (double)((T)4 * eps * s6 * (s6 - (T)1)) - shift;
+            vir += (double)(ff * (T)r2);
+        }
     }
     return ff;
 }
 
 // Bytes of LDS per halo entry.
 __host__ __device__ constexpr int halo_entry_bytes(int pot) { return pot == PAIR_DPD ? 52 : 24; }
+
+// Rows may be read this many entries past their end (two passes of the
+// widest split): the neighbour list is padded by as many tile columns.
+constexpr int kRowOverRead = 2 * 4 * 16;
 
 template <int W, bool MIXED, int POT, bool LOG>
 __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
@@ -72,15 +79,12 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     // LDS: halo positions (and for DPD velocities and tags), then the tile's
     // neighbour rows
     extern __shared__ double lds[];
-    double *hx = lds;
-    double *hy = hx + halo_cap;
-    double *hz = hy + halo_cap;
-    double *hvx = hz + halo_cap;
-    double *hvy = hvx + halo_cap;
-    double *hvz = hvy + halo_cap;
-    int32_t *htag = reinterpret_cast<int32_t *>(POT == PAIR_DPD ? hvz + halo_cap : hz + halo_cap);
-    uint16_t *srow = reinterpret_cast<uint16_t *>(POT == PAIR_DPD ? reinterpret_cast<double *>(htag + halo_cap)
-                                                                  : hz + halo_cap);
+    // LDS holds the halo only: positions interleaved per entry (one address
+    // for x, y, z), then for DPD the velocities and tags.  Rows stream from
+    // global memory one pass ahead of their use.
+    double *hxyz = lds;
+    double *hv = hxyz + 3 * halo_cap;
+    int32_t *htag = reinterpret_cast<int32_t *>(hv + 3 * halo_cap);
 
     constexpr int P = kWave / W;
     const int tid = threadIdx.x;
@@ -88,10 +92,10 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     const int wv = tid >> 6;
     const int pl = lane % P;
     const int sl = lane / P;
-    const int tile = blockIdx.x;
+    const int tile = die_tile(blockIdx.x, gridDim.x);
     const int gw = tile * W + wv;
     const int t = wv * P + pl;  // row slot in the tile
-    if (a.flag_clear && tile == 0 && tid == 0) *a.flag_clear = 0;
+    if (a.flag_clear && blockIdx.x == 0 && tid == 0) *a.flag_clear = 0;
     const int s = find_sys(tprefix, n_sys, tile);
     const SysDev &S = sys[s];
     // per-system constants, held in registers for the whole launch
@@ -108,13 +112,28 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     const bool active = r < n_local;
     const int64_t i = row0 + (active ? r : r0);
 
-    // ---- stage the halo and the rows -------------------------------------
+    // ---- the row's first pass, then the halo ------------------------------
+    constexpr int U = 4;
     const int32_t hn = halo_n[tile];
     const int nh = hn & 0xFFFF;
-    const int kmax = (hn >> 16) & 0x7FFF;
     const bool per_pair = hn < 0;  // tile too wide for one image per halo entry
+    int n = active ? nn[i] : 0;
+    n = n < cap ? n : cap;
+    // entry k of this row at rowp[k * 64]; the list is padded so that reads up
+    // to two passes past any row's end stay inside it (their values are masked)
+    const uint16_t *rowp = nlist + nl0 + (int64_t)(r0 >> 6) * cap * kTile + t;
+    int hnext[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) hnext[u] = rowp[(int64_t)(sl + u * W) * kTile];
     const double4 xref = a.pos[row0 + r0];
     const int32_t *hl = halo + (int64_t)tile * halo_cap;
+    // a tile without neighbours still has a finite halo entry 0 (read by
+    // masked lanes)
+    if (nh == 0 && tid == 0) {
+        hxyz[0] = xref.x;
+        hxyz[1] = xref.y;
+        hxyz[2] = xref.z;
+    }
     for (int h = tid; h < nh; h += W * kWave) {
         const int32_t j = hl[h];
         double4 x = a.pos[j];
@@ -123,21 +142,16 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
             x.y = __fma_rn(-Ly, rint((x.y - xref.y) * iLy), x.y);
             x.z = __fma_rn(-Lz, rint((x.z - xref.z) * iLz), x.z);
         }
-        hx[h] = x.x;
-        hy[h] = x.y;
-        hz[h] = x.z;
+        hxyz[3 * h] = x.x;
+        hxyz[3 * h + 1] = x.y;
+        hxyz[3 * h + 2] = x.z;
         if constexpr (POT == PAIR_DPD) {
             const double4 v = a.vel[j];
-            hvx[h] = v.x;
-            hvy[h] = v.y;
-            hvz[h] = v.z;
+            hv[3 * h] = v.x;
+            hv[3 * h + 1] = v.y;
+            hv[3 * h + 2] = v.z;
             htag[h] = a.tag[j];
         }
-    }
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(nlist + nl0 + (int64_t)(r0 >> 6) * cap * kTile);
-        uint4 *dst = reinterpret_cast<uint4 *>(srow);
-        for (int e = tid; e < kmax * (kTile / 8); e += W * kWave) dst[e] = src[e];
     }
     __syncthreads();
 
@@ -156,71 +170,84 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     uint32_t step_key = a.timestep;
     if constexpr (POT == PAIR_DPD)
         if (a.timestep_ptr) step_key = *a.timestep_ptr;
-    int n = active ? nn[i] : 0;
-    n = n < cap ? n : cap;
-
     T fx = 0, fy = 0, fz = 0;
     double e = 0.0, vir = 0.0;
 
-    // four neighbours per pass: all LDS reads of a pass issue before any use
-    constexpr int U = 4;
-    for (int k0 = sl; k0 < n; k0 += U * W) {
-        int hh[U];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int kk = k0 + u * W;
-            ok[u] = kk < n;
-            hh[u] = ok[u] ? srow[kk * kTile + t] : 0;
-        }
-        double dx[U], dy[U], dz[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            dx[u] = xs - hx[hh[u]];
-            dy[u] = ys - hy[hh[u]];
-            dz[u] = zs - hz[hh[u]];
-        }
-        if (per_pair) {
+    // four neighbours per pass: all LDS reads of a pass issue before any use.
+    // The per-pair image branch is taken once per tile, outside the loop.
+    auto pair_loop = [&](auto per_pair_tag) {
+        constexpr bool PP = decltype(per_pair_tag)::value;
+        for (int k0 = sl; k0 < n; k0 += U * W) {
+            int hh[U];
+            bool ok[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                dx[u] = min_image(dx[u], Lx, iLx);
-                dy[u] = min_image(dy[u], Ly, iLy);
-                dz[u] = min_image(dz[u], Lz, iLz);
+                const int kk = k0 + u * W;
+                ok[u] = kk < n;
+                // past the row's end: stale or foreign values, masked
+                hh[u] = ok[u] ? hnext[u] : 0;
+                hnext[u] = rowp[(int64_t)(kk + U * W) * kTile];
             }
-        }
+            double dx[U], dy[U], dz[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double r2 = norm2_exact(dx[u], dy[u], dz[u]);
-            if (ok[u] && r2 < rc2) {
-                T ff;
-                if constexpr (POT == PAIR_LJ || POT == PAIR_WCA) {
-                    ff = lj_pair<T, LOG>(r2, eps, sig2, shift, e, vir);
-                } else {
-                    if (r2 == 0.0) continue;
-                    const int h = hh[u];
-                    const T tr2 = (T)r2;
-                    const T rr = tsqrt<T>(tr2);
-                    const T rinv = recip<T>(rr);
-                    const T w = (T)1 - rr * (T)S.dpd_inv_rc;
-                    const T dvx = (T)(vi.x - hvx[h]), dvy = (T)(vi.y - hvy[h]), dvz = (T)(vi.z - hvz[h]);
-                    const T rv = ((T)dx[u] * dvx + (T)dy[u] * dvy + (T)dz[u] * dvz) * rinv;
-                    const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)htag[h], S.dpd_seed, step_key);
-                    const T uu = (T)bits * (T)(1.0 / 16777216.0);
-                    const T theta = (T)1.7320508075688772 * ((T)2 * uu - (T)1);
-                    const T mag = (T)S.dpd_A * w - (T)S.dpd_gamma * w * w * rv +
-                                  (T)S.dpd_sigma * w * theta * (T)S.dpd_inv_sqrt_dt;
-                    ff = mag * rinv;
-                    if constexpr (LOG) {
-                        e += 0.5 * S.dpd_A * S.dpd_rc * (double)(w * w);
-                        vir += (double)(ff * tr2);
-                    }
+            for (int u = 0; u < U; ++u) {
+                const double *hp = hxyz + 3 * hh[u];
+                dx[u] = xs - hp[0];
+                dy[u] = ys - hp[1];
+                dz[u] = zs - hp[2];
+            }
+            if constexpr (PP) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    dx[u] = min_image(dx[u], Lx, iLx);
+                    dy[u] = min_image(dy[u], Ly, iLy);
+                    dz[u] = min_image(dz[u], Lz, iLz);
                 }
-                fx += ff * (T)dx[u];
-                fy += ff * (T)dy[u];
-                fz += ff * (T)dz[u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double r2 = norm2_exact(dx[u], dy[u], dz[u]);
+                if constexpr (POT == PAIR_LJ || POT == PAIR_WCA) {
+                    // branch-free: lanes outside the cut-off add zero
+                    const bool in = ok[u] && r2 < rc2;
+                    T ff = lj_pair<T, LOG>(in ? r2 : 1.0, eps, sig2, shift, e, vir, in);
+                    ff = in ? ff : (T)0;
+                    fx += ff * (T)dx[u];
+                    fy += ff * (T)dy[u];
+                    fz += ff * (T)dz[u];
+                    continue;
+                }
+                if (ok[u] && r2 < rc2) {
+                    T ff;
+                    {
+                        if (r2 == 0.0) continue;
+                        const int h = hh[u];
+                        const T tr2 = (T)r2;
+                        const T rr = tsqrt<T>(tr2);
+                        const T rinv = recip<T>(rr);
+                        const T w = (T)1 - rr * (T)S.dpd_inv_rc;
+                        const T dvx = (T)(vi.x - hv[3 * h]), dvy = (T)(vi.y - hv[3 * h + 1]), dvz = (T)(vi.z - hv[3 * h + 2]);
+                        const T rv = ((T)dx[u] * dvx + (T)dy[u] * dvy + (T)dz[u] * dvz) * rinv;
+                        const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)htag[h], S.dpd_seed, step_key);
+                        const T uu = (T)bits * (T)(1.0 / 16777216.0);
+                        const T theta = (T)1.7320508075688772 * ((T)2 * uu - (T)1);
+                        const T mag = (T)S.dpd_A * w - (T)S.dpd_gamma * w * w * rv +
+                                      (T)S.dpd_sigma * w * theta * (T)S.dpd_inv_sqrt_dt;
+                        ff = mag * rinv;
+                        if constexpr (LOG) {
+                            e += 0.5 * S.dpd_A * S.dpd_rc * (double)(w * w);
+                            vir += (double)(ff * tr2);
+                        }
+                    }
+                    fx += ff * (T)dx[u];
+                    fy += ff * (T)dy[u];
+                    fz += ff * (T)dz[u];
+                }
             }
         }
-    }
+    };
+    if (per_pair) pair_loop(std::true_type{});
+    else pair_loop(std::false_type{});
 
     fx = segment_sum<W>(fx);
     fy = segment_sum<W>(fy);
@@ -414,9 +441,14 @@ __global__ void k_rtag(const SysDev *__restrict__ sys, const int32_t *__restrict
 
 // ---------------------------------------------------------------------------
 
+int force_row_over_read() { return kRowOverRead; }
+
+int force_halo_entry_bytes(int pair) { return halo_entry_bytes(pair); }
+
 size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap)
 {
-    return (size_t)halo_entry_bytes(pair) * (size_t)halo_cap + (size_t)nlist_cap * kTile * sizeof(uint16_t);
+    (void)nlist_cap;
+    return (size_t)halo_entry_bytes(pair) * (size_t)(halo_cap > 1 ? halo_cap : 1);
 }
 
 template <int W, bool MIXED, int POT, bool LOG>

@@ -77,6 +77,8 @@ void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value);
 void launch_rtag(const LaunchCtx &L, const int32_t *tag);
 void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag);
 size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
+int force_row_over_read();
+int force_halo_entry_bytes(int pair);
 size_t fast_build_lds_bytes(int nlist_cap);
 hipError_t prepare_nlist(int nlist_cap);
 

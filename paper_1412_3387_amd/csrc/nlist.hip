@@ -200,6 +200,48 @@ __device__ __forceinline__ int block_scan(int32_t *a, int n, int32_t *scan)
     return total;
 }
 
+// The same with wave-level shuffles: two barriers instead of 2 log2(NT).
+template <int NT>
+__device__ __forceinline__ int block_scan_w(int32_t *a, int n, int32_t *wsum)
+{
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid >> 6;
+    const int b = 8 * tid;
+    int v[8];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k] = b + k < n ? a[b + k] : 0;
+        sum += v[k];
+    }
+    int inc = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        const int x = wsum[q];
+        before += q < w ? x : 0;
+        total += x;
+    }
+    int run = before + inc - sum;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (b + k < n) {
+            a[b + k] = run;
+            run += v[k];
+        }
+    __syncthreads();
+    return total;
+}
+
 __device__ __forceinline__ int block_scan8(int32_t *a, int n, int32_t *scan)
 {
     return block_scan<kBuildThreads>(a, n, scan);
@@ -244,7 +286,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
     const uint64_t below = lanemask_lt();
     if (build_count && blockIdx.x == 0 && tid == 0) atomicAdd(build_count, 1);
 
-    for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
+    int64_t tfirst = blockIdx.x, tend = ntiles;
+    int tstep = gridDim.x;
+    if (!list) die_range(blockIdx.x, gridDim.x, ntiles, tfirst, tend, tstep);
+    for (int it = (int)tfirst; it < tend; it += tstep) {
         const int tile = list ? list[it] : it;
         const int s = find_sys(tprefix, n_sys, tile);
         const SysDev &S = sys[s];
@@ -565,13 +610,13 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 //     x-adjacent cells of a row's stencil line are three consecutive distinct
 //     cells: a row's candidates are nine contiguous slot ranges ("runs").
 //   * Members are staged as FP32 positions in the frame, relative to the
-//     first row.  One wave takes one row at a time; its lanes split the nine
-//     runs (10 lanes for the centre line, 7 for each edge line, 6 for each
-//     corner line).  A candidate whose FP32 distance lies clearly inside or
-//     outside r_list is decided there; one within a relative band of 2^-10
-//     of r_list^2 is decided by the FP64 test of the oracle (difference of the
-//     stored positions, then the periodic shift), so the list is exactly the
-//     FP64 one.  The FP32 error is bounded by 4 sqrt(3) F 2^-24 / r_list
+//     first row.  One wave takes one row at a time; its 64 lanes split the
+//     nine runs in proportion to their lengths (at least one lane each), so
+//     a row takes about (members / 55) + 1 passes.  A candidate whose FP32
+//     distance lies clearly inside or outside r_list is decided there; one
+//     within a relative band of 2^-10 of r_list^2 is decided by the exact
+//     FP64 test (difference of the stored positions, then the periodic
+//     shift), so the list is exactly the FP64 one.  The FP32 error is bounded by 4 sqrt(3) F 2^-24 / r_list
 //     relative, F the frame extent; tiles with F > 512 r_list are passed on.
 //   * Rows are assembled in LDS and written out coalesced after the halo
 //     numbering, without a read-back.
@@ -588,6 +633,7 @@ constexpr int kUMax = 512;           // distinct cells of a framed tile
 constexpr int kFastSlotMax = 8192;   // members of a framed tile's stencil cells
 constexpr int kRuns = 9;
 constexpr float kBand = 1.0f / 1024.0f;
+constexpr int kStageBatch = 2;       // members staged per thread per pass
 
 struct FastShared {
     float4 cp[kFastChunk];               // member position in the frame (FP32), row in w
@@ -607,11 +653,8 @@ struct FastShared {
     int32_t info[4];                     // pass-on flag, per-pair image flag, longest row
 };
 
-// first lane of each line of a row: corners 6 lanes, edges 7, centre 10
-__constant__ int8_t kRunLane[kRuns + 1] = {0, 6, 13, 19, 26, 36, 43, 49, 56, 62};
-
 template <bool EXCL>
-__global__ __launch_bounds__(kFastThreads) void k_build_fast(
+__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_build_fast(
     const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
     const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ partners,
     const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx, int cell_cap,
@@ -627,15 +670,12 @@ __global__ __launch_bounds__(kFastThreads) void k_build_fast(
     const int lane = lane_id();
     const int wv = tid >> 6;
     const uint64_t below = lanemask_lt();
-    int rho = 0;
-#pragma unroll
-    for (int k = 1; k <= kRuns; ++k) rho += lane >= kRunLane[k] ? 1 : 0;
-    const bool lane_on = rho < kRuns;
-    const int sub = lane_on ? lane - kRunLane[rho] : 0;
-    const int g = lane_on ? kRunLane[rho + 1] - kRunLane[rho] : 1;
     if (blockIdx.x == 0 && tid == 0) atomicAdd(build_count, 1);
 
-    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    int64_t tfirst, tend;
+    int tstep;
+    die_range(blockIdx.x, gridDim.x, tiles, tfirst, tend, tstep);
+    for (int tile = (int)tfirst; tile < tend; tile += tstep) {
         const int s = find_sys(tprefix, n_sys, tile);
         const SysDev &S = sys[s];
         const double Ls[3] = {S.L[0], S.L[1], S.L[2]};
@@ -736,7 +776,7 @@ __global__ __launch_bounds__(kFastThreads) void k_build_fast(
         // ---- 3. distinct cells (box order) and their members ----------------------
         for (int q = tid; q < nbw; q += kFastThreads) sh.bpre[q] = __popc(sh.box[q]);
         __syncthreads();
-        const int nu = block_scan<kFastThreads>(sh.bpre, nbw, sh.scan);
+        const int nu = block_scan_w<kFastThreads>(sh.bpre, nbw, sh.scan);
         if (tid == 0) sh.bpre[nbw] = nu;
         if (nu > kUMax) {
             if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
@@ -763,7 +803,7 @@ __global__ __launch_bounds__(kFastThreads) void k_build_fast(
             sh.ustart[u] = m < cell_cap ? m : cell_cap;
         }
         __syncthreads();
-        const int nslot = block_scan<kFastThreads>(sh.ustart, nu, sh.scan);
+        const int nslot = block_scan_w<kFastThreads>(sh.ustart, nu, sh.scan);
         if (tid == 0) {
             sh.ustart[nu] = nslot;
             int pp = 0;
@@ -817,85 +857,145 @@ __global__ __launch_bounds__(kFastThreads) void k_build_fast(
         for (int q0 = 0; q0 < nslot; q0 += kFastChunk) {
             const int q1 = q0 + kFastChunk < nslot ? q0 + kFastChunk : nslot;
             __syncthreads();
-            for (int q = q0 + tid; q < q1; q += kFastThreads) {
-                const int u = upper_idx(sh.ustart, nu, q);
-                const int b = sh.ubit[u];
-                const int f[3] = {b % X[0] + blo[0], (b / X[0]) % X[1] + blo[1], b / (X[0] * X[1]) + blo[2]};
-                int pc[3], kimg[3];
+            // staging, kStageBatch members per thread with their loads in flight together
+            for (int qb = q0 + tid; qb < q1; qb += kFastThreads * kStageBatch) {
+                int32_t jj[kStageBatch];
+                int8_t kk[kStageBatch][3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    pc[a] = c0[a] + f[a];
-                    kimg[a] = pc[a] >= bins[a] ? 1 : (pc[a] < 0 ? -1 : 0);
-                    pc[a] -= kimg[a] * bins[a];
+                for (int v = 0; v < kStageBatch; ++v) {
+                    const int q = qb + v * kFastThreads;
+                    jj[v] = -1;
+                    if (q < q1) {
+                        const int u = upper_idx(sh.ustart, nu, q);
+                        const int bb = sh.ubit[u];
+                        const int f[3] = {bb % X[0] + blo[0], (bb / X[0]) % X[1] + blo[1],
+                                          bb / (X[0] * X[1]) + blo[2]};
+                        int pc[3];
+#pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            pc[ax] = c0[ax] + f[ax];
+                            const int ki = pc[ax] >= bins[ax] ? 1 : (pc[ax] < 0 ? -1 : 0);
+                            pc[ax] -= ki * bins[ax];
+                            kk[v][ax] = (int8_t)ki;
+                        }
+                        const int64_t key = ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0];
+                        jj[v] = cell_idx[(cell0 + key) * cell_cap + (q - sh.ustart[u])];
+                    }
                 }
-                const int64_t key = ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0];
-                const int32_t j = cell_idx[(cell0 + key) * cell_cap + (q - sh.ustart[u])];
-                const double4 xj = pos[j];
-                sh.cp[q - q0] = make_float4((float)((xj.x + (double)kimg[0] * Ls[0]) - xr[0]),
-                                            (float)((xj.y + (double)kimg[1] * Ls[1]) - xr[1]),
-                                            (float)((xj.z + (double)kimg[2] * Ls[2]) - xr[2]),
-                                            __int_as_float(j));
+                double4 xj[kStageBatch];
+#pragma unroll
+                for (int v = 0; v < kStageBatch; ++v) xj[v] = pos[jj[v] >= 0 ? jj[v] : row0 + r0];
+#pragma unroll
+                for (int v = 0; v < kStageBatch; ++v) {
+                    const int q = qb + v * kFastThreads;
+                    if (jj[v] >= 0)
+                        sh.cp[q - q0] = make_float4((float)((xj[v].x + (double)kk[v][0] * Ls[0]) - xr[0]),
+                                                    (float)((xj[v].y + (double)kk[v][1] * Ls[1]) - xr[1]),
+                                                    (float)((xj[v].z + (double)kk[v][2] * Ls[2]) - xr[2]),
+                                                    __int_as_float(jj[v]));
+                }
             }
             __syncthreads();
             for (int t = wv; t < kTile; t += kFastWaves) {
                 int ntot = sh.rown[t];
                 if (ntot < 0) continue;  // inactive row
+                // the row's nine lines cut to this chunk; lane r < 9 holds line r
+                int len = 0, ra0 = 0;
+                if (lane < kRuns) {
+                    const uint32_t rv = sh.run[t][lane];
+                    int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
+                    x0_ = x0_ > q0 ? x0_ : q0;
+                    x1_ = x1_ < q1 ? x1_ : q1;
+                    ra0 = x0_;
+                    len = x1_ > x0_ ? x1_ - x0_ : 0;
+                }
+                // lanes to lines: line r takes lanes [B_r, B_r+1) with B_r = r + about
+                // 55 P_r / T (P_r the members before line r, T all of them): every
+                // line keeps at least one lane and longer lines get more.  The line
+                // data are wave-uniform: read lane by lane into scalars.
+                int lens[kRuns], a0s[kRuns];
+                int tot = 0;
+#pragma unroll
+                for (int r = 0; r < kRuns; ++r) {
+                    lens[r] = __builtin_amdgcn_readlane(len, r);
+                    a0s[r] = __builtin_amdgcn_readlane(ra0, r);
+                    tot += lens[r];
+                }
+                if (tot == 0) continue;
+                const uint32_t inv = 65536u / (uint32_t)tot;  // floor(2^16 / T)
+                int base = 0, end = 0, gsz = 1, pre = 0, b0 = 0;
+#pragma unroll
+                for (int r = 0; r < kRuns; ++r) {
+                    const int pn = pre + lens[r];
+                    const int b1 = r == kRuns - 1 ? kWave : r + 1 + (int)((55u * (uint32_t)pn * inv) >> 16);
+                    if (lane >= b0 && lane < b1) {
+                        base = a0s[r] + (lane - b0);
+                        end = a0s[r] + lens[r];
+                        gsz = b1 - b0;
+                    }
+                    b0 = b1;
+                    pre = pn;
+                }
                 const float4 xt = sh.xrow[t];
                 const int32_t it = (int32_t)(row0 + r0 + t);
                 int32_t part[kMaxBondCap];
                 if constexpr (EXCL) {
                     const int64_t prow = (row0 + tag[it]) * S.bond_cap;
 #pragma unroll
-                    for (int b = 0; b < kMaxBondCap; ++b)
-                        part[b] = b < S.bond_cap ? partners[prow + b] : -1;
+                    for (int bnd = 0; bnd < kMaxBondCap; ++bnd)
+                        part[bnd] = bnd < S.bond_cap ? partners[prow + bnd] : -1;
                 }
-                const uint32_t rv = lane_on ? sh.run[t][rho] : 0u;
-                int a0 = (int)(rv & 0xffffu), a1 = (int)(rv >> 16);
-                a0 = a0 > q0 ? a0 : q0;
-                a1 = a1 < q1 ? a1 : q1;
-                for (int q = a0 + sub;; q += g) {
-                    const bool on = q < a1;
-                    if (__ballot(on) == 0ull) break;
-                    bool hit = false;
-                    if (on) {
-                        const float4 c = sh.cp[q - q0];
-                        const float dx = c.x - xt.x, dy = c.y - xt.y, dz = c.z - xt.z;
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        const int32_t j = __float_as_int(c.w);
-                        hit = r2 < lo_f;
-                        if (!hit && r2 <= hi_f) {
-                            // near r_list: the oracle's FP64 test
-                            const double4 xa = pos[it], xb = pos[j];
-                            const double cj[3] = {(double)c.x, (double)c.y, (double)c.z};
-                            const double xt3[3] = {(double)xt.x, (double)xt.y, (double)xt.z};
-                            const double pa[3] = {xa.x, xa.y, xa.z}, pb[3] = {xb.x, xb.y, xb.z};
-                            double d[3];
+                uint16_t *myrow = srows + t * rstride;
+                // candidate test: FP32 in the frame, the exact FP64 test near r_list
+                auto near = [&](const float4 c, bool on) -> bool {
+                    const float dx = c.x - xt.x, dy = c.y - xt.y, dz = c.z - xt.z;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const int32_t j = __float_as_int(c.w);
+                    bool hit = on && r2 < lo_f && j != it;
+                    if (on && r2 >= lo_f && r2 <= hi_f) {
+                        const double4 xa = pos[it], xb = pos[j];
+                        const double cj[3] = {(double)c.x, (double)c.y, (double)c.z};
+                        const double xt3[3] = {(double)xt.x, (double)xt.y, (double)xt.z};
+                        const double pa[3] = {xa.x, xa.y, xa.z}, pb[3] = {xb.x, xb.y, xb.z};
+                        double d[3];
 #pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                // frame images of both: k = round((frame - stored) / L)
-                                const double kj = rint((cj[a] + xr[a] - pb[a]) * iL[a]);
-                                const double ki = rint((xt3[a] + xr[a] - pa[a]) * iL[a]);
-                                d[a] = pb[a] - pa[a];
-                                if (kj != ki) d[a] = d[a] + (kj - ki) * Ls[a];
-                            }
-                            hit = norm2_exact(d[0], d[1], d[2]) < rl2;
+                        for (int ax = 0; ax < 3; ++ax) {
+                            // frame images of both: k = round((frame - stored) / L)
+                            const double kj = rint((cj[ax] + xr[ax] - pb[ax]) * iL[ax]);
+                            const double ki = rint((xt3[ax] + xr[ax] - pa[ax]) * iL[ax]);
+                            d[ax] = pb[ax] - pa[ax];
+                            if (kj != ki) d[ax] = d[ax] + (kj - ki) * Ls[ax];
                         }
-                        hit = hit && j != it;
-                        if constexpr (EXCL) {
-                            if (hit) {
-                                const int32_t tj = tag[j];
+                        hit = norm2_exact(d[0], d[1], d[2]) < rl2 && j != it;
+                    }
+                    if constexpr (EXCL) {
+                        if (hit) {
+                            const int32_t tj = tag[j];
 #pragma unroll
-                                for (int b = 0; b < kMaxBondCap; ++b) hit = hit && part[b] != tj;
-                            }
+                            for (int bnd = 0; bnd < kMaxBondCap; ++bnd) hit = hit && part[bnd] != tj;
                         }
                     }
+                    return hit;
+                };
+                auto append = [&](bool hit, int q) {
                     const uint64_t mask = __ballot(hit);
+                    const int p = ntot + __popcll(mask & below);
                     if (hit) {
-                        const int p = ntot + __popcll(mask & below);
-                        if (p < cap) srows[t * rstride + p] = (uint16_t)q;
+                        if (p < cap) myrow[p] = (uint16_t)q;
                         atomicOr(&sh.used[q >> 5], 1u << (q & 31));
                     }
                     ntot += __popcll(mask);
+                };
+                for (int qa = base;; qa += 2 * gsz) {
+                    const int qb = qa + gsz;
+                    const bool ona = qa < end, onb = qb < end;
+                    if (__ballot(ona) == 0ull) break;
+                    const float4 ca = sh.cp[(ona ? qa : q0) - q0];
+                    const float4 cb = sh.cp[(onb ? qb : q0) - q0];
+                    const bool ha = near(ca, ona);
+                    const bool hb = near(cb, onb);
+                    append(ha, qa);
+                    append(hb, qb);
                 }
                 if (lane == 0) sh.rown[t] = ntot;
             }
@@ -909,7 +1009,7 @@ __global__ __launch_bounds__(kFastThreads) void k_build_fast(
         const int nwords = (nslot + 31) / 32;
         for (int q = tid; q < nwords; q += kFastThreads) sh.wpre[q] = __popc(sh.used[q]);
         __syncthreads();
-        const int nhalo = block_scan<kFastThreads>(sh.wpre, nwords, sh.scan);
+        const int nhalo = block_scan_w<kFastThreads>(sh.wpre, nwords, sh.scan);
         if (nhalo > halo_cap) {
             if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nhalo);
             if (tid < kTile && act) nn[i] = 0;

@@ -68,7 +68,8 @@ bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         if (q.pair != HOOMD_PAIR_WCA && !(q.r_cut > 0)) return false;
         if (q.pair != HOOMD_PAIR_DPD && !(q.sigma > 0)) return false;
         // the rows of a tile share one workgroup's LDS with at least 64 halo entries
-        if (q.nlist_cap < 1 || (int64_t)q.nlist_cap * 128 + 64 * 52 > 65536) return false;
+        // the framed build assembles a tile's rows in LDS
+        if (q.nlist_cap < 1 || q.nlist_cap > 512) return false;
         if (q.cell_cap < 0 || q.cell_cap > 128) return false;
         if (q.halo_cap < 0 || q.halo_cap > 65535) return false;
         if (q.tpp_force < 0 || q.tpp_force > 16 || (q.tpp_force & (q.tpp_force - 1))) return false;
@@ -102,9 +103,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     for (int s = 0; s < n_sys; ++s) {
         // halo of a compact 64-row tile: density x (tile side + 2 r_list)^3
         // one workgroup's LDS (64 KiB) holds the halo and the tile's rows
-        const int64_t row_bytes = (int64_t)force_lds_bytes(p[s].pair, 0, Lo.nlist_cap);
-        const int lds_max = (int)std::max<int64_t>(
-            (65536 - row_bytes) / (int64_t)force_lds_bytes(p[s].pair, 1, 0) / 64 * 64, 64);
+        const int lds_max = (int)std::max<int64_t>(65536 / (int64_t)force_halo_entry_bytes(p[s].pair) / 64 * 64, 64);
         int hc = p[s].halo_cap;
         if (hc <= 0) {
             const double vol = boxes[s].L[0] * boxes[s].L[1] * boxes[s].L[2];
@@ -221,7 +220,9 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.pos_alt = take(sizeof(double4) * rows);
     Lo.vel_alt = take(sizeof(double4) * rows);
     Lo.xbuild = take(sizeof(double4) * rows);
-    Lo.nlist = take(sizeof(uint16_t) * (size_t)std::max<int64_t>(nl, 1));
+    // padded: the force pass reads up to force_row_over_read() entries past
+    // any row's end
+    Lo.nlist = take(sizeof(uint16_t) * ((size_t)std::max<int64_t>(nl, 1) + (size_t)force_row_over_read() * kTile));
     Lo.halo = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1) * Lo.halo_cap);
     Lo.halo_n = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
     Lo.nn = take(sizeof(int32_t) * rows);
