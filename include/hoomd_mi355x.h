@@ -104,9 +104,12 @@ typedef struct {
     double fene_K, fene_R0;/* FENE + WCA(eps, sigma) bond term              */
     int32_t nlist_cap;     /* neighbour row capacity (entries per particle)  */
     int32_t cell_cap;      /* cell capacity (0 = derived from the density)   */
-    int32_t halo_cap;      /* halo entries per 64-row tile (0 = derived: from
-                              the density when sort_period > 0, else the LDS
-                              limit, since unsorted rows make wide tiles)    */
+    int32_t halo_cap;      /* halo list entries per 64-row tile, <= 65535
+                              (0 = derived: from the density when
+                              sort_period > 0, else 8192).  The force pass
+                              stages up to about 1.25x the expected halo in
+                              LDS and reads any further entries from global
+                              memory, so this bounds memory, not speed      */
     int32_t sort_period;   /* Morton sort every this many steps (0 = never)  */
     int32_t check_period;  /* displacement check every k steps (>= 1)        */
     int32_t tpp_nlist;     /* lanes per particle, neighbour list (0 = tuned) */

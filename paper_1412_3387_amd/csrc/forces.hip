@@ -69,6 +69,7 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
                                                 const int32_t *__restrict__ nn, int cap,
                                                 const int32_t *__restrict__ halo,
                                                 const int32_t *__restrict__ halo_n, int halo_cap,
+                                                int halo_lds,
                                                 const int32_t *__restrict__ partners,
                                                 const int32_t *__restrict__ rtag,
                                                 const double4 *__restrict__ xbuild,
@@ -83,8 +84,8 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     // for x, y, z), then for DPD the velocities and tags.  Rows stream from
     // global memory one pass ahead of their use.
     double *hxyz = lds;
-    double *hv = hxyz + 3 * halo_cap;
-    int32_t *htag = reinterpret_cast<int32_t *>(hv + 3 * halo_cap);
+    double *hv = hxyz + 3 * halo_lds;
+    int32_t *htag = reinterpret_cast<int32_t *>(hv + 3 * halo_lds);
 
     constexpr int P = kWave / W;
     const int tid = threadIdx.x;
@@ -127,6 +128,22 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     for (int u = 0; u < U; ++u) hnext[u] = rowp[(int64_t)(sl + u * W) * kTile];
     const double4 xref = a.pos[row0 + r0];
     const int32_t *hl = halo + (int64_t)tile * halo_cap;
+    // halo entry h: its position moved to the image nearest the tile's first
+    // row (unless the tile needs per-pair images)
+    auto halo_pos = [&](int h, double &px, double &py, double &pz) {
+        const double4 x = a.pos[hl[h]];
+        px = x.x;
+        py = x.y;
+        pz = x.z;
+        if (!per_pair) {
+            px = __fma_rn(-Lx, rint((px - xref.x) * iLx), px);
+            py = __fma_rn(-Ly, rint((py - xref.y) * iLy), py);
+            pz = __fma_rn(-Lz, rint((pz - xref.z) * iLz), pz);
+        }
+    };
+    // the first halo_lds entries are staged in LDS; a tile with more reads
+    // the rest from global memory (rare: halo_lds is sized for occupancy)
+    const int ns = nh < halo_lds ? nh : halo_lds;
     // a tile without neighbours still has a finite halo entry 0 (read by
     // masked lanes)
     if (nh == 0 && tid == 0) {
@@ -134,18 +151,14 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
         hxyz[1] = xref.y;
         hxyz[2] = xref.z;
     }
-    for (int h = tid; h < nh; h += W * kWave) {
-        const int32_t j = hl[h];
-        double4 x = a.pos[j];
-        if (!per_pair) {
-            x.x = __fma_rn(-Lx, rint((x.x - xref.x) * iLx), x.x);
-            x.y = __fma_rn(-Ly, rint((x.y - xref.y) * iLy), x.y);
-            x.z = __fma_rn(-Lz, rint((x.z - xref.z) * iLz), x.z);
-        }
-        hxyz[3 * h] = x.x;
-        hxyz[3 * h + 1] = x.y;
-        hxyz[3 * h + 2] = x.z;
+    for (int h = tid; h < ns; h += W * kWave) {
+        double px, py, pz;
+        halo_pos(h, px, py, pz);
+        hxyz[3 * h] = px;
+        hxyz[3 * h + 1] = py;
+        hxyz[3 * h + 2] = pz;
         if constexpr (POT == PAIR_DPD) {
+            const int32_t j = hl[h];
             const double4 v = a.vel[j];
             hv[3 * h] = v.x;
             hv[3 * h + 1] = v.y;
@@ -175,8 +188,9 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
 
     // four neighbours per pass: all LDS reads of a pass issue before any use.
     // The per-pair image branch is taken once per tile, outside the loop.
-    auto pair_loop = [&](auto per_pair_tag) {
+    auto pair_loop = [&](auto per_pair_tag, auto spill_tag) {
         constexpr bool PP = decltype(per_pair_tag)::value;
+        constexpr bool OVF = decltype(spill_tag)::value;
         for (int k0 = sl; k0 < n; k0 += U * W) {
             int hh[U];
             bool ok[U];
@@ -191,10 +205,18 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
             double dx[U], dy[U], dz[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double *hp = hxyz + 3 * hh[u];
-                dx[u] = xs - hp[0];
-                dy[u] = ys - hp[1];
-                dz[u] = zs - hp[2];
+                double px, py, pz;
+                if (!OVF || hh[u] < halo_lds) {
+                    const double *hp = hxyz + 3 * hh[u];
+                    px = hp[0];
+                    py = hp[1];
+                    pz = hp[2];
+                } else {
+                    halo_pos(hh[u], px, py, pz);
+                }
+                dx[u] = xs - px;
+                dy[u] = ys - py;
+                dz[u] = zs - pz;
             }
             if constexpr (PP) {
 #pragma unroll
@@ -226,9 +248,24 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
                         const T rr = tsqrt<T>(tr2);
                         const T rinv = recip<T>(rr);
                         const T w = (T)1 - rr * (T)S.dpd_inv_rc;
-                        const T dvx = (T)(vi.x - hv[3 * h]), dvy = (T)(vi.y - hv[3 * h + 1]), dvz = (T)(vi.z - hv[3 * h + 2]);
+                        double vx, vy, vz;
+                        int32_t tj;
+                        if (!OVF || h < halo_lds) {
+                            vx = hv[3 * h];
+                            vy = hv[3 * h + 1];
+                            vz = hv[3 * h + 2];
+                            tj = htag[h];
+                        } else {
+                            const int32_t j = hl[h];
+                            const double4 vj = a.vel[j];
+                            vx = vj.x;
+                            vy = vj.y;
+                            vz = vj.z;
+                            tj = a.tag[j];
+                        }
+                        const T dvx = (T)(vi.x - vx), dvy = (T)(vi.y - vy), dvz = (T)(vi.z - vz);
                         const T rv = ((T)dx[u] * dvx + (T)dy[u] * dvy + (T)dz[u] * dvz) * rinv;
-                        const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)htag[h], S.dpd_seed, step_key);
+                        const uint32_t bits = dpd_bits((uint32_t)ti, (uint32_t)tj, S.dpd_seed, step_key);
                         const T uu = (T)bits * (T)(1.0 / 16777216.0);
                         const T theta = (T)1.7320508075688772 * ((T)2 * uu - (T)1);
                         const T mag = (T)S.dpd_A * w - (T)S.dpd_gamma * w * w * rv +
@@ -246,8 +283,13 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
             }
         }
     };
-    if (per_pair) pair_loop(std::true_type{});
-    else pair_loop(std::false_type{});
+    if (nh > halo_lds) {
+        if (per_pair) pair_loop(std::true_type{}, std::true_type{});
+        else pair_loop(std::false_type{}, std::true_type{});
+    } else {
+        if (per_pair) pair_loop(std::true_type{}, std::false_type{});
+        else pair_loop(std::false_type{}, std::false_type{});
+    }
 
     fx = segment_sum<W>(fx);
     fy = segment_sum<W>(fy);
@@ -455,10 +497,10 @@ template <int W, bool MIXED, int POT, bool LOG>
 static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
 {
     if (L.tiles_local == 0) return;
-    const size_t lds = force_lds_bytes(POT, L.halo_cap, L.nlist_cap);
+    const size_t lds = force_lds_bytes(POT, L.halo_lds, L.nlist_cap);
     hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(L.tiles_local), dim3(W * kWave), lds, L.stream,
                        L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                       L.halo_cap, L.partners, L.rtag, L.xbuild, L.partials, L.status, F);
+                       L.halo_cap, L.halo_lds, L.partners, L.rtag, L.xbuild, L.partials, L.status, F);
 }
 
 template <int W, bool MIXED, int POT>

@@ -35,6 +35,7 @@ struct LaunchCtx {
     int32_t *halo;                 // halo_cap row numbers per tile
     int32_t *halo_n;               // halo size per tile (top bit: per-pair images)
     int halo_cap;
+    int halo_lds;                  // halo entries the force pass stages in LDS
     double4 *xbuild;
     const int32_t *partners;       // per tag: bond_cap partner tags (-1 = none)
     int32_t *rtag;                 // row of each tag (per system offset row0)

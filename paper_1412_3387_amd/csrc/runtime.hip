@@ -37,7 +37,7 @@ struct Layout {
     size_t rtag, partners, slow_list, sort_ws, ghost_ws, total;
     // sizes
     int64_t rows, tiles_local, tiles_all, n_cells, nlist_entries;
-    int cell_cap, nlist_cap, bond_cap, halo_cap;
+    int cell_cap, nlist_cap, bond_cap, halo_cap, halo_lds;
     std::vector<SysDev> sys;
     std::vector<int32_t> tpl_host, tpa_host;
 };
@@ -96,26 +96,35 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.tpl_host.push_back(0);
     Lo.tpa_host.push_back(0);
     Lo.halo_cap = 64;
+    Lo.halo_lds = 64;
     for (int s = 0; s < n_sys; ++s) {
         Lo.nlist_cap = std::max(Lo.nlist_cap, p[s].nlist_cap);
         Lo.bond_cap = std::max(Lo.bond_cap, p[s].bond_cap);
     }
     for (int s = 0; s < n_sys; ++s) {
-        // halo of a compact 64-row tile: density x (tile side + 2 r_list)^3
-        // one workgroup's LDS (64 KiB) holds the halo and the tile's rows
-        const int lds_max = (int)std::max<int64_t>(65536 / (int64_t)force_halo_entry_bytes(p[s].pair) / 64 * 64, 64);
+        // Halo of a compact 64-row tile (Morton-ordered rows): about the
+        // density times (tile side + 2 r_list)^3.  The per-tile halo list in
+        // global memory gets a wide margin; the force pass stages at most
+        // halo_lds entries in LDS (sized for four or more workgroups per CU)
+        // and reads any further entries from global memory.
+        const int entry = force_halo_entry_bytes(p[s].pair);
+        const int lds_budget = std::max(32768 / entry / 64 * 64, 64);
+        const double vol = boxes[s].L[0] * boxes[s].L[1] * boxes[s].L[2];
+        const double rho = (double)std::max<int64_t>(boxes[s].n_cap, 1) / vol;
+        const double side = std::cbrt(64.0 / rho);
+        const double rl = pair_cut(p[s]) + p[s].r_buff;
+        const double est = rho * std::pow(side + 2.0 * rl, 3.0);
+        const int64_t rows_up = (boxes[s].n_cap + 63) / 64 * 64;
         int hc = p[s].halo_cap;
         if (hc <= 0) {
-            const double vol = boxes[s].L[0] * boxes[s].L[1] * boxes[s].L[2];
-            const double rho = (double)std::max<int64_t>(boxes[s].n_cap, 1) / vol;
-            const double side = std::cbrt(64.0 / rho);
-            const double rl = pair_cut(p[s]) + p[s].r_buff;
-            const double est = rho * std::pow(side + 2.0 * rl, 3.0);
-            hc = p[s].sort_period > 0 ? (int)std::ceil((1.6 * est + 64.0) / 64.0) * 64 : lds_max;
-            hc = (int)std::min<int64_t>(hc, (boxes[s].n_cap + 63) / 64 * 64);
+            hc = p[s].sort_period > 0 ? (int)std::ceil((2.5 * est + 64.0) / 64.0) * 64 : 8192;
+            hc = (int)std::min<int64_t>(hc, rows_up);
         }
-        hc = std::min(std::max(hc, 64), lds_max);
+        hc = std::min(std::max(hc, 64), 65535);
+        int hl = p[s].sort_period > 0 ? (int)std::ceil(1.25 * est / 64.0) * 64 : lds_budget;
+        hl = std::min(std::max(hl, 64), std::min(lds_budget, hc));
         Lo.halo_cap = std::max(Lo.halo_cap, hc);
+        Lo.halo_lds = std::max(Lo.halo_lds, hl);
     }
     for (int s = 0; s < n_sys; ++s) {
         const hoomd_params &q = p[s];
@@ -453,6 +462,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.halo = ws_ptr<int32_t>(c, lay.halo);
     L.halo_n = ws_ptr<int32_t>(c, lay.halo_n);
     L.halo_cap = lay.halo_cap;
+    L.halo_lds = std::min(lay.halo_lds, lay.halo_cap);
     L.nn = ws_ptr<int32_t>(c, lay.nn);
     L.nlist_cap = lay.nlist_cap;
     L.xbuild = ws_ptr<double4>(c, lay.xbuild);
