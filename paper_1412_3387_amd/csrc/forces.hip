@@ -61,25 +61,25 @@ __host__ __device__ constexpr int halo_entry_bytes(int pot) { return pot == PAIR
 // Rows may be read this many entries past their end (two passes of the
 // widest split): the neighbour list is padded by as many tile columns.
 constexpr int kRowOverRead = 2 * 4 * 16;
+constexpr int kRareGrid = 256;  // workgroups of the launch over the rare tiles
 
-template <int W, bool MIXED, int POT, bool LOG>
-__global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
-                                                const int32_t *__restrict__ tprefix, int n_sys,
-                                                const uint16_t *__restrict__ nlist,
-                                                const int32_t *__restrict__ nn, int cap,
-                                                const int32_t *__restrict__ halo,
-                                                const int32_t *__restrict__ halo_n, int halo_cap,
-                                                int halo_lds,
-                                                const int32_t *__restrict__ partners,
-                                                const int32_t *__restrict__ rtag,
-                                                const double4 *__restrict__ xbuild,
-                                                double *__restrict__ partials, Status *st,
-                                                ForceLaunch a)
+// One tile of the fused step.  RARE selects the code for tiles with a
+// per-pair image or a halo larger than the LDS staging area; the main
+// launch leaves those to a second, small launch, so that its own code needs
+// fewer registers (more waves per CU).
+template <int W, bool MIXED, int POT, bool LOG, bool RARE>
+__device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *__restrict__ sys,
+                                           const int32_t *__restrict__ tprefix, int n_sys,
+                                           const uint16_t *__restrict__ nlist,
+                                           const int32_t *__restrict__ nn, int cap,
+                                           const int32_t *__restrict__ halo,
+                                           const int32_t *__restrict__ halo_n, int halo_cap, int halo_lds,
+                                           const int32_t *__restrict__ partners,
+                                           const int32_t *__restrict__ rtag,
+                                           const double4 *__restrict__ xbuild,
+                                           double *__restrict__ partials, Status *st, const ForceLaunch &a)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
-    // LDS: halo positions (and for DPD velocities and tags), then the tile's
-    // neighbour rows
-    extern __shared__ double lds[];
     // LDS holds the halo only: positions interleaved per entry (one address
     // for x, y, z), then for DPD the velocities and tags.  Rows stream from
     // global memory one pass ahead of their use.
@@ -93,10 +93,8 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
     const int wv = tid >> 6;
     const int pl = lane % P;
     const int sl = lane / P;
-    const int tile = die_tile(blockIdx.x, gridDim.x);
     const int gw = tile * W + wv;
     const int t = wv * P + pl;  // row slot in the tile
-    if (a.flag_clear && blockIdx.x == 0 && tid == 0) *a.flag_clear = 0;
     const int s = find_sys(tprefix, n_sys, tile);
     const SysDev &S = sys[s];
     // per-system constants, held in registers for the whole launch
@@ -283,12 +281,16 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
             }
         }
     };
-    if (nh > halo_lds) {
-        if (per_pair) pair_loop(std::true_type{}, std::true_type{});
-        else pair_loop(std::false_type{}, std::true_type{});
+    if constexpr (RARE) {
+        if (nh > halo_lds) {
+            if (per_pair) pair_loop(std::true_type{}, std::true_type{});
+            else pair_loop(std::false_type{}, std::true_type{});
+        } else {
+            if (per_pair) pair_loop(std::true_type{}, std::false_type{});
+            else pair_loop(std::false_type{}, std::false_type{});
+        }
     } else {
-        if (per_pair) pair_loop(std::true_type{}, std::false_type{});
-        else pair_loop(std::false_type{}, std::false_type{});
+        pair_loop(std::false_type{}, std::false_type{});
     }
 
     fx = segment_sum<W>(fx);
@@ -392,6 +394,41 @@ __global__ __launch_bounds__(1024) void k_force(const SysDev *__restrict__ sys,
             partials[3 * (int64_t)gw + 1] = e3;
             partials[3 * (int64_t)gw + 2] = w3;
         }
+    }
+}
+
+#define FORCE_ARGS                                                                                       \
+    const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys,                      \
+        const uint16_t *__restrict__ nlist, const int32_t *__restrict__ nn, int cap,                     \
+        const int32_t *__restrict__ halo, const int32_t *__restrict__ halo_n, int halo_cap, int halo_lds, \
+        const int32_t *__restrict__ partners, const int32_t *__restrict__ rtag,                          \
+        const double4 *__restrict__ xbuild, double *__restrict__ partials, Status *st,                   \
+        const int32_t *__restrict__ rare_list, const int32_t *__restrict__ rare_n, ForceLaunch a
+#define FORCE_PASS sys, tprefix, n_sys, nlist, nn, cap, halo, halo_n, halo_cap, halo_lds, partners, rtag, \
+                   xbuild, partials, st, a
+
+// Main launch: one workgroup per tile; rare tiles return at once.
+template <int W, bool MIXED, int POT, bool LOG>
+__global__ __launch_bounds__(1024) void k_force(FORCE_ARGS)
+{
+    extern __shared__ double lds[];
+    if (a.flag_clear && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
+    const int tile = die_tile(blockIdx.x, gridDim.x);
+    const int32_t hn = halo_n[tile];
+    if (hn < 0 || (hn & 0xFFFF) > halo_lds) return;
+    force_tile<W, MIXED, POT, LOG, false>(tile, lds, FORCE_PASS);
+}
+
+// The tiles the last build listed as rare (per-pair images or a halo larger
+// than the staging area).
+template <int W, bool MIXED, int POT, bool LOG>
+__global__ __launch_bounds__(1024) void k_force_rare(FORCE_ARGS)
+{
+    extern __shared__ double lds[];
+    const int cnt = *rare_n;
+    for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
+        force_tile<W, MIXED, POT, LOG, true>(rare_list[k], lds, FORCE_PASS);
+        __syncthreads();
     }
 }
 
@@ -500,7 +537,13 @@ static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
     const size_t lds = force_lds_bytes(POT, L.halo_lds, L.nlist_cap);
     hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(L.tiles_local), dim3(W * kWave), lds, L.stream,
                        L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                       L.halo_cap, L.halo_lds, L.partners, L.rtag, L.xbuild, L.partials, L.status, F);
+                       L.halo_cap, L.halo_lds, L.partners, L.rtag, L.xbuild, L.partials, L.status,
+                       L.rare_list, L.rare_n, F);
+    const int rb = L.tiles_local < kRareGrid ? L.tiles_local : kRareGrid;
+    hipLaunchKernelGGL((k_force_rare<W, MIXED, POT, LOG>), dim3(rb), dim3(W * kWave), lds, L.stream,
+                       L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
+                       L.halo_cap, L.halo_lds, L.partners, L.rtag, L.xbuild, L.partials, L.status,
+                       L.rare_list, L.rare_n, F);
 }
 
 template <int W, bool MIXED, int POT>

@@ -29,6 +29,7 @@ struct LaunchCtx {
     int32_t *cell_count;
     int32_t *cell_size;
     int32_t *cell_idx;
+    float4 *cell_xf;               // member position from the cell corner (FP32), row bits in w
     uint16_t *nlist;               // halo indices, tile-major rows
     int32_t *nn;
     int nlist_cap;
@@ -42,6 +43,8 @@ struct LaunchCtx {
     bool has_bonds;
     int32_t *slow_list;            // tiles the framed build passes on to the general one
     int32_t *slow_n;               // their number (cleared by the binning launch)
+    int32_t *rare_list;            // tiles the force pass handles in its second launch
+    int32_t *rare_n;               // their number (cleared by the binning launch)
     int32_t *flag;                 // rebuild flag read by the rebuild kernels
     int32_t *build_count;
     uint32_t *step_counter;        // advanced by the binning launch when set (graph steps)
@@ -70,7 +73,7 @@ struct ForceLaunch {
 };
 
 void launch_bin(const LaunchCtx &L, const double4 *pos);
-void launch_cell_sort(const LaunchCtx &L);
+void launch_cell_sort(const LaunchCtx &L, const double4 *pos);
 void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int w, int block);
 void launch_force(const LaunchCtx &L, const ForceLaunch &F, int w, int block);
 void launch_thermo_reduce(const LaunchCtx &L, int w, int log_row, double timestep);

@@ -51,13 +51,16 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
                                              int32_t *__restrict__ cell_count,
                                              int32_t *__restrict__ cell_idx, int cell_cap,
                                              const int32_t *__restrict__ flag, Status *st,
-                                             uint32_t *step_counter, int32_t *slow_n)
+                                             uint32_t *step_counter, int32_t *slow_n, int32_t *rare_n)
 {
     // the binning launch follows every fused step launch: it also advances
     // the device step counter read by graph-replayed steps
     if (step_counter && blockIdx.x == 0 && threadIdx.x == 0) *step_counter += 1u;
     if (*flag == 0) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *slow_n = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *slow_n = 0;
+        *rare_n = 0;
+    }
     const int lane = lane_id();
     const uint64_t lt = lanemask_lt();
     const int waves = (int)(gridDim.x * blockDim.x) >> 6;
@@ -95,13 +98,29 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
     }
 }
 
+// System owning a cell (largest s with sys[s].cell0 <= c).
+__device__ __forceinline__ int find_sys_cell(const SysDev *__restrict__ sys, int n_sys, int64_t c)
+{
+    int lo = 0, hi = n_sys;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sys[mid].cell0 <= c) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // One wave per cell: members ranked by row index, sizes published, counters
-// cleared.  cell_cap <= 64 * CPL.
+// cleared.  Next to each member's row the list keeps its position relative
+// to the cell's lower corner in FP32 (row bits in w), so that the framed
+// build stages a cell with one coalesced read.  cell_cap <= 64 * CPL.
 template <int CPL>
-__global__ __launch_bounds__(256) void k_cell_sort(int64_t n_cells, int32_t *__restrict__ cell_count,
+__global__ __launch_bounds__(256) void k_cell_sort(const SysDev *__restrict__ sys, int n_sys,
+                                                   const double4 *__restrict__ pos, int64_t n_cells,
+                                                   int32_t *__restrict__ cell_count,
                                                    int32_t *__restrict__ cell_size,
-                                                   int32_t *__restrict__ cell_idx, int cell_cap,
-                                                   const int32_t *__restrict__ flag)
+                                                   int32_t *__restrict__ cell_idx, float4 *__restrict__ cell_xf,
+                                                   int cell_cap, const int32_t *__restrict__ flag)
 {
     if (*flag == 0) return;
     const int lane = lane_id();
@@ -127,10 +146,22 @@ __global__ __launch_bounds__(256) void k_cell_sort(int64_t n_cells, int32_t *__r
                 for (int q = 0; q < CPL; ++q) rank[q] += other < v[q] ? 1 : 0;
             }
         }
+        const SysDev &S = sys[find_sys_cell(sys, n_sys, c)];
+        const int64_t key = c - S.cell0;
+        const int cx = (int)(key % S.bins[0]), cy = (int)((key / S.bins[0]) % S.bins[1]),
+                  cz = (int)(key / ((int64_t)S.bins[0] * S.bins[1]));
+        const double ox = S.lo[0] + (double)cx * (S.L[0] / S.bins[0]);
+        const double oy = S.lo[1] + (double)cy * (S.L[1] / S.bins[1]);
+        const double oz = S.lo[2] + (double)cz * (S.L[2] / S.bins[2]);
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const int k = q * kWave + lane;
-            if (k < m) cell_idx[c * cell_cap + rank[q]] = v[q];
+            if (k < m) {
+                cell_idx[c * cell_cap + rank[q]] = v[q];
+                const double4 x = pos[v[q]];
+                cell_xf[c * cell_cap + rank[q]] =
+                    make_float4((float)(x.x - ox), (float)(x.y - oy), (float)(x.z - oz), __int_as_float(v[q]));
+            }
         }
         if (lane == 0) {
             cell_size[c] = m;
@@ -266,7 +297,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
     const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx, int cell_cap,
     uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int32_t *__restrict__ halo,
     int32_t *__restrict__ halo_n, int halo_cap, double4 *__restrict__ xbuild,
-    const int32_t *__restrict__ list, const int32_t *__restrict__ list_n,
+    const int32_t *__restrict__ list, const int32_t *__restrict__ list_n, int halo_lds,
+    int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n,
     const int32_t *__restrict__ flag, int32_t *build_count, Status *st)
 {
     if (*flag == 0) return;
@@ -571,8 +603,11 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
                 hl[h] = cell_idx[(cell0 + sh.keys[u]) * cell_cap + (q - sh.ustart[u])];
             }
         }
-        if (tid == 0)
+        if (tid == 0) {
             halo_n[tile] = (int32_t)((uint32_t)nhalo | ((uint32_t)sh.info[2] << 16) | (sh.info[1] ? 0x80000000u : 0u));
+            // per-pair images or a halo beyond the force pass's LDS staging
+            if (sh.info[1] || nhalo > halo_lds) rare_list[atomicAdd(rare_n, 1)] = tile;
+        }
         __threadfence_block();
         __syncthreads();
         if (active) {
@@ -610,14 +645,19 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 //     x-adjacent cells of a row's stencil line are three consecutive distinct
 //     cells: a row's candidates are nine contiguous slot ranges ("runs").
 //   * Members are staged as FP32 positions in the frame, relative to the
-//     first row.  One wave takes one row at a time; its 64 lanes split the
+//     first row: the cell list keeps each member's position from its cell's
+//     corner in FP32, and staging adds the corner's frame position (one
+//     coalesced read per member).  One wave takes one row at a time; its 64
+//     lanes split the
 //     nine runs in proportion to their lengths (at least one lane each), so
 //     a row takes about (members / 55) + 1 passes.  A candidate whose FP32
 //     distance lies clearly inside or outside r_list is decided there; one
 //     within a relative band of 2^-10 of r_list^2 is decided by the exact
 //     FP64 test (difference of the stored positions, then the periodic
-//     shift), so the list is exactly the FP64 one.  The FP32 error is bounded by 4 sqrt(3) F 2^-24 / r_list
-//     relative, F the frame extent; tiles with F > 512 r_list are passed on.
+//     shift), so the list is exactly the FP64 one.  Three roundings of
+//     magnitude at most F (the frame extent) per coordinate bound the FP32
+//     error of r^2 by about 6 sqrt(3) F 2^-24 / r_list relative; tiles with
+//     F > 512 r_list are passed on.
 //   * Rows are assembled in LDS and written out coalesced after the halo
 //     numbering, without a read-back.
 // Tiles that do not fit (a frame wider than a periodic box, fewer than three
@@ -626,20 +666,20 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 
 constexpr int kFastThreads = 512;
 constexpr int kFastWaves = kFastThreads / kWave;
-constexpr int kFastChunk = 2816;     // members staged at once (float4 each)
+constexpr int kFastChunk = 2560;     // members staged at once (float4 each)
 constexpr int kBoxMax = 4096;        // cells of the frame box
 constexpr int kBoxWords = kBoxMax / 32;
-constexpr int kUMax = 512;           // distinct cells of a framed tile
+constexpr int kUMax = 256;           // distinct cells of a framed tile
 constexpr int kFastSlotMax = 8192;   // members of a framed tile's stencil cells
 constexpr int kRuns = 9;
 constexpr float kBand = 1.0f / 1024.0f;
-constexpr int kStageBatch = 2;       // members staged per thread per pass
 
 struct FastShared {
     float4 cp[kFastChunk];               // member position in the frame (FP32), row in w
     uint32_t box[kBoxWords];             // stencil cells in the frame box
     int32_t bpre[kBoxWords + 1];         // set bits before each box word
-    int16_t ubit[kUMax];                 // box bit of each distinct cell
+    int32_t ucell[kUMax];                // box bit, then cell index, of each distinct cell
+    float4 uoff[kUMax];                  // frame position of each distinct cell's corner (FP32)
     int32_t ustart[kUMax + 1];           // first slot of each distinct cell
     uint32_t used[kFastSlotMax / 32];
     int32_t wpre[kFastSlotMax / 32 + 1];
@@ -649,6 +689,7 @@ struct FastShared {
     int16_t rh[3][kTile];                // row home cell in the frame
     int32_t rown[kTile];                 // hits of each row so far
     int32_t scan[kFastThreads];
+    double xref[3];                      // first row's position: the frame reference
     int32_t ext[6];
     int32_t info[4];                     // pass-on flag, per-pair image flag, longest row
 };
@@ -657,10 +698,12 @@ template <bool EXCL>
 __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_build_fast(
     const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
     const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ partners,
-    const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx, int cell_cap,
+    const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx,
+    const float4 *__restrict__ cell_xf, int cell_cap,
     uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int rstride,
     int32_t *__restrict__ halo, int32_t *__restrict__ halo_n, int halo_cap,
     double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n,
+    int halo_lds, int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n,
     const int32_t *__restrict__ flag, int32_t *build_count, Status *st)
 {
     if (*flag == 0) return;
@@ -686,25 +729,13 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         const int n_local = S.n_local;
         const double rl2 = S.rl2;
         const int r0 = (tile - S.tile0) * kTile;
-        const double4 x0 = pos[row0 + r0];
-        int c0[3];
-        c0[0] = cell_coord(x0.x, S.lo[0], S.scale[0], bins[0]);
-        c0[1] = cell_coord(x0.y, S.lo[1], S.scale[1], bins[1]);
-        c0[2] = cell_coord(x0.z, S.lo[2], S.scale[2], bins[2]);
         const float cw[3] = {(float)(Ls[0] / bins[0]), (float)(Ls[1] / bins[1]), (float)(Ls[2] / bins[2])};
 
         __syncthreads();  // LDS of the previous tile no longer read
-        if (tid < 3) {
-            sh.ext[tid] = INT32_MAX;
-            sh.ext[3 + tid] = INT32_MIN;
-        }
-        if (tid == 0) {
-            sh.info[0] = 0;
-            sh.info[2] = 0;
-        }
-        __syncthreads();
         // ---- 1. rows: home cell in the frame, frame position ------------------
-        double4 xi = x0;
+        // one round trip: the first row's position (the frame reference) is
+        // shared through LDS
+        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
         int64_t i = row0 + r0;
         bool act = false;
         if (tid < kTile) {
@@ -712,6 +743,24 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             act = r < n_local;
             i = row0 + (act ? r : r0);
             xi = pos[i];
+            if (tid == 0) {
+                sh.xref[0] = xi.x;
+                sh.xref[1] = xi.y;
+                sh.xref[2] = xi.z;
+            }
+        } else if (tid < kTile + 3) {
+            sh.ext[tid - kTile] = INT32_MAX;
+            sh.ext[3 + tid - kTile] = INT32_MIN;
+        } else if (tid == kTile + 3) {
+            sh.info[0] = 0;
+            sh.info[2] = 0;
+        }
+        __syncthreads();
+        const double xr[3] = {sh.xref[0], sh.xref[1], sh.xref[2]};
+        int c0[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c0[a] = cell_coord(xr[a], S.lo[a], S.scale[a], bins[a]);
+        if (tid < kTile) {
             const double xa[3] = {xi.x, xi.y, xi.z};
             float xf[3];
 #pragma unroll
@@ -720,7 +769,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 const int h = per[a] ? wrap_rel(ci - c0[a], bins[a]) : ci - c0[a];
                 // image of the row in the frame: the home cell at c0 + h
                 const int kimg = per[a] ? (c0[a] + h - ci) / bins[a] : 0;
-                xf[a] = (float)((xa[a] + (double)kimg * Ls[a]) - (a == 0 ? x0.x : (a == 1 ? x0.y : x0.z)));
+                xf[a] = (float)((xa[a] + (double)kimg * Ls[a]) - xr[a]);
                 sh.rh[a][tid] = (int16_t)h;
                 sh.frel[a][tid] = (float)(xa[a] - S.lo[a]) - (float)ci * cw[a];
                 if (act) {
@@ -787,20 +836,29 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             int u = sh.bpre[q];
             while (word) {
                 const int bit = __ffs(word) - 1;
-                sh.ubit[u++] = (int16_t)(q * 32 + bit);
+                sh.ucell[u++] = q * 32 + bit;
                 word &= word - 1u;
             }
         }
         __syncthreads();
         for (int u = tid; u < nu; u += kFastThreads) {
-            const int b = sh.ubit[u];
-            const int f0 = b % X[0] + blo[0], f1 = (b / X[0]) % X[1] + blo[1], f2 = b / (X[0] * X[1]) + blo[2];
-            int p0 = c0[0] + f0, p1 = c0[1] + f1, p2 = c0[2] + f2;
-            p0 -= p0 >= bins[0] ? bins[0] : (p0 < 0 ? -bins[0] : 0);
-            p1 -= p1 >= bins[1] ? bins[1] : (p1 < 0 ? -bins[1] : 0);
-            p2 -= p2 >= bins[2] ? bins[2] : (p2 < 0 ? -bins[2] : 0);
-            const int m = cell_size[cell0 + ((int64_t)p2 * bins[1] + p1) * bins[0] + p0];
+            const int b = sh.ucell[u];
+            const int f[3] = {b % X[0] + blo[0], (b / X[0]) % X[1] + blo[1], b / (X[0] * X[1]) + blo[2]};
+            int pc[3];
+            float off[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                pc[a] = c0[a] + f[a];
+                const int ki = pc[a] >= bins[a] ? 1 : (pc[a] < 0 ? -1 : 0);
+                pc[a] -= ki * bins[a];
+                // the cell's lower corner in the frame, relative to the reference
+                off[a] = (float)((S.lo[a] + (double)pc[a] * (Ls[a] / bins[a]) + (double)ki * Ls[a]) - xr[a]);
+            }
+            const int32_t cell = (int32_t)(cell0 + ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0]);
+            const int m = cell_size[cell];
             sh.ustart[u] = m < cell_cap ? m : cell_cap;
+            sh.ucell[u] = cell;
+            sh.uoff[u] = make_float4(off[0], off[1], off[2], 0.f);
         }
         __syncthreads();
         const int nslot = block_scan_w<kFastThreads>(sh.ustart, nu, sh.scan);
@@ -853,47 +911,16 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
         // ---- 5. stage members a chunk at a time, scan every row's lines -------------
         const float lo_f = (float)rl2 * (1.0f - kBand), hi_f = (float)rl2 * (1.0f + kBand);
-        const double xr[3] = {x0.x, x0.y, x0.z};
         for (int q0 = 0; q0 < nslot; q0 += kFastChunk) {
             const int q1 = q0 + kFastChunk < nslot ? q0 + kFastChunk : nslot;
             __syncthreads();
-            // staging, kStageBatch members per thread with their loads in flight together
-            for (int qb = q0 + tid; qb < q1; qb += kFastThreads * kStageBatch) {
-                int32_t jj[kStageBatch];
-                int8_t kk[kStageBatch][3];
-#pragma unroll
-                for (int v = 0; v < kStageBatch; ++v) {
-                    const int q = qb + v * kFastThreads;
-                    jj[v] = -1;
-                    if (q < q1) {
-                        const int u = upper_idx(sh.ustart, nu, q);
-                        const int bb = sh.ubit[u];
-                        const int f[3] = {bb % X[0] + blo[0], (bb / X[0]) % X[1] + blo[1],
-                                          bb / (X[0] * X[1]) + blo[2]};
-                        int pc[3];
-#pragma unroll
-                        for (int ax = 0; ax < 3; ++ax) {
-                            pc[ax] = c0[ax] + f[ax];
-                            const int ki = pc[ax] >= bins[ax] ? 1 : (pc[ax] < 0 ? -1 : 0);
-                            pc[ax] -= ki * bins[ax];
-                            kk[v][ax] = (int8_t)ki;
-                        }
-                        const int64_t key = ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0];
-                        jj[v] = cell_idx[(cell0 + key) * cell_cap + (q - sh.ustart[u])];
-                    }
-                }
-                double4 xj[kStageBatch];
-#pragma unroll
-                for (int v = 0; v < kStageBatch; ++v) xj[v] = pos[jj[v] >= 0 ? jj[v] : row0 + r0];
-#pragma unroll
-                for (int v = 0; v < kStageBatch; ++v) {
-                    const int q = qb + v * kFastThreads;
-                    if (jj[v] >= 0)
-                        sh.cp[q - q0] = make_float4((float)((xj[v].x + (double)kk[v][0] * Ls[0]) - xr[0]),
-                                                    (float)((xj[v].y + (double)kk[v][1] * Ls[1]) - xr[1]),
-                                                    (float)((xj[v].z + (double)kk[v][2] * Ls[2]) - xr[2]),
-                                                    __int_as_float(jj[v]));
-                }
+            // staging: one coalesced read per member (cell-relative FP32
+            // position and row), moved into the frame by its cell's corner
+            for (int q = q0 + tid; q < q1; q += kFastThreads) {
+                const int u = upper_idx(sh.ustart, nu, q);
+                const float4 c = cell_xf[(int64_t)sh.ucell[u] * cell_cap + (q - sh.ustart[u])];
+                const float4 o = sh.uoff[u];
+                sh.cp[q - q0] = make_float4(c.x + o.x, c.y + o.y, c.z + o.z, c.w);
             }
             __syncthreads();
             for (int t = wv; t < kTile; t += kFastWaves) {
@@ -1027,20 +1054,17 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                     j = __float_as_int(sh.cp[q].w);
                 } else {
                     const int u = upper_idx(sh.ustart, nu, q);
-                    const int b = sh.ubit[u];
-                    int pc[3] = {c0[0] + b % X[0] + blo[0], c0[1] + (b / X[0]) % X[1] + blo[1],
-                                 c0[2] + b / (X[0] * X[1]) + blo[2]};
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) pc[a] -= pc[a] >= bins[a] ? bins[a] : (pc[a] < 0 ? -bins[a] : 0);
-                    const int64_t key = ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0];
-                    j = cell_idx[(cell0 + key) * cell_cap + (q - sh.ustart[u])];
+                    j = cell_idx[(int64_t)sh.ucell[u] * cell_cap + (q - sh.ustart[u])];
                 }
                 hl[h] = j;
             }
         }
         const int kmax = sh.info[2];
-        if (tid == 0)
+        if (tid == 0) {
             halo_n[tile] = (int32_t)((uint32_t)nhalo | ((uint32_t)kmax << 16) | (sh.info[1] ? 0x80000000u : 0u));
+            // per-pair images or a halo beyond the force pass's LDS staging
+            if (sh.info[1] || nhalo > halo_lds) rare_list[atomicAdd(rare_n, 1)] = tile;
+        }
         uint16_t *out = nlist + nl0 + (int64_t)(r0 >> 6) * cap * kTile;
         for (int e = tid; e < kmax * kTile; e += kFastThreads) {
             const int k = e >> 6, t = e & 63;
@@ -1074,19 +1098,19 @@ void launch_bin(const LaunchCtx &L, const double4 *pos)
     const int blocks = capped(((int64_t)L.tiles_all * kWave + 255) / 256);
     hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.tprefix_all, L.n_sys,
                        L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.status,
-                       L.step_counter, L.slow_n);
+                       L.step_counter, L.slow_n, L.rare_n);
 }
 
-void launch_cell_sort(const LaunchCtx &L)
+void launch_cell_sort(const LaunchCtx &L, const double4 *pos)
 {
     if (L.n_cells == 0) return;
     const int blocks = capped((L.n_cells * kWave + 255) / 256);
     if (L.cell_cap <= 64)
-        hipLaunchKernelGGL(k_cell_sort<1>, dim3(blocks), dim3(256), 0, L.stream, L.n_cells, L.cell_count,
-                           L.cell_size, L.cell_idx, L.cell_cap, L.flag);
+        hipLaunchKernelGGL(k_cell_sort<1>, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.n_sys, pos,
+                           L.n_cells, L.cell_count, L.cell_size, L.cell_idx, L.cell_xf, L.cell_cap, L.flag);
     else
-        hipLaunchKernelGGL(k_cell_sort<2>, dim3(blocks), dim3(256), 0, L.stream, L.n_cells, L.cell_count,
-                           L.cell_size, L.cell_idx, L.cell_cap, L.flag);
+        hipLaunchKernelGGL(k_cell_sort<2>, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.n_sys, pos,
+                           L.n_cells, L.cell_count, L.cell_size, L.cell_idx, L.cell_xf, L.cell_cap, L.flag);
 }
 
 int nlist_row_stride(int cap)
@@ -1122,21 +1146,25 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
     if (L.has_bonds) {
         hipLaunchKernelGGL(k_build_fast<true>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
-                           L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
-                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.flag, L.build_count, L.status);
+                           L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
+                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
+                           L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<true>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.flag, nullptr, L.status);
+                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
+                           nullptr, L.status);
     } else {
         hipLaunchKernelGGL(k_build_fast<false>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
-                           L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
-                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.flag, L.build_count, L.status);
+                           L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
+                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
+                           L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<false>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.flag, nullptr, L.status);
+                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
+                           nullptr, L.status);
     }
 }
 

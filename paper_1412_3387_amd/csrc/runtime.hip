@@ -33,8 +33,8 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
     // byte offsets into the workspace
     size_t sysdev, tpl, tpa, status, flags, thermo, thermo_log, partials;
-    size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, halo, halo_n;
-    size_t rtag, partners, slow_list, sort_ws, ghost_ws, total;
+    size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, cell_xf, halo, halo_n;
+    size_t rtag, partners, slow_list, rare_list, sort_ws, ghost_ws, total;
     // sizes
     int64_t rows, tiles_local, tiles_all, n_cells, nlist_entries;
     int cell_cap, nlist_cap, bond_cap, halo_cap, halo_lds;
@@ -238,9 +238,11 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.cell_count = take(sizeof(int32_t) * (size_t)cell);
     Lo.cell_size = take(sizeof(int32_t) * (size_t)cell);
     Lo.cell_idx = take(sizeof(int32_t) * (size_t)cell * Lo.cell_cap);
+    Lo.cell_xf = take(sizeof(float4) * (size_t)cell * Lo.cell_cap);
     Lo.rtag = take(sizeof(int32_t) * rows);
     Lo.partners = take(sizeof(int32_t) * rows * std::max(Lo.bond_cap, 1));
     Lo.slow_list = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
+    Lo.rare_list = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
     Lo.sort_ws = take(sort_workspace_bytes((int64_t)rows));
     Lo.ghost_ws = take(ghost_workspace_bytes((int64_t)rows, n_sys));
     Lo.total = off;
@@ -326,7 +328,8 @@ size_t mark(hoomd_ctx *c)
 
 // Device flags: 0 and 1 rebuild flags of the two buffer parities, 2 the flag
 // of explicit builds, 4 build counter, 5 step counter of replayed steps, 6
-// tiles passed from the framed build to the general one.
+// tiles passed from the framed build to the general one, 7 tiles the force
+// pass handles in its second launch.
 int32_t *flag_ptr(hoomd_ctx *c, int k) { return ws_ptr<int32_t>(c, c->lay.flags) + k; }
 
 // Queue the rebuild sequence: bin -> per-cell sort -> neighbour rows.  Every
@@ -335,7 +338,7 @@ void queue_rebuild(hoomd_ctx *c, const double4 *pos, const int32_t *tag, int32_t
 {
     c->L.flag = flag;
     launch_bin(c->L, pos);
-    launch_cell_sort(c->L);
+    launch_cell_sort(c->L, pos);
     launch_nlist(c->L, pos, tag, c->tpp_nlist, c->block_nlist);
 }
 
@@ -458,6 +461,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.cell_count = ws_ptr<int32_t>(c, lay.cell_count);
     L.cell_size = ws_ptr<int32_t>(c, lay.cell_size);
     L.cell_idx = ws_ptr<int32_t>(c, lay.cell_idx);
+    L.cell_xf = ws_ptr<float4>(c, lay.cell_xf);
     L.nlist = ws_ptr<uint16_t>(c, lay.nlist);
     L.halo = ws_ptr<int32_t>(c, lay.halo);
     L.halo_n = ws_ptr<int32_t>(c, lay.halo_n);
@@ -473,6 +477,8 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.build_count = flag_ptr(c, 4);
     L.slow_list = ws_ptr<int32_t>(c, lay.slow_list);
     L.slow_n = flag_ptr(c, 6);
+    L.rare_list = ws_ptr<int32_t>(c, lay.rare_list);
+    L.rare_n = flag_ptr(c, 7);
     L.status = ws_ptr<Status>(c, lay.status);
     L.partials = ws_ptr<double>(c, lay.partials);
     L.thermo = ws_ptr<double>(c, lay.thermo);

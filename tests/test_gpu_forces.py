@@ -128,3 +128,24 @@ def test_nan_is_reported(B):
     ctx = B.Context([B.ModelParams(precision=0)], [dict(pos=pos, vel=s.vel, L=s.L)])
     ctx.compute_forces(0, 0)
     assert ctx.sync_status()[0] == 9
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lj_forces_rare_tiles(orc, B, prec):
+    """Rows in random order (no sorting) make tiles whose halos exceed the
+    LDS staging area, and a 4,000-particle box makes tiles wider than half
+    the box: both go to the second launch of the force pass, which must
+    agree with the oracle like the main one."""
+    rng = np.random.default_rng(5)
+    big = inputs.lj_fluid(8000, 11, 12)
+    perm = rng.permutation(big.n)
+    shuffled = inputs.System(pos=big.pos[perm], vel=big.vel[perm], L=big.L, tag=perm.astype(np.int32))
+    for s, ref_pos in ((shuffled, big.pos), (inputs.lj_small(), None)):
+        p = B.ModelParams(precision=prec, sort_period=0, tpp_force=4)
+        f, th, ctx = _forces(B, s, p)
+        ctx.check()
+        hn = ctx._ws_view(ctx.layout().halo_n, (s.n + 63) // 64).cpu().numpy()
+        F, u, wv, nc = orc.pair_forces("lj", s.pos if ref_pos is None else ref_pos, s.L, LJ)
+        assert frel(f[:, :3], F) <= TOL[prec], s.n
+        if ref_pos is not None:
+            assert (hn & 0xFFFF).max() > 1344  # beyond the staging area
