@@ -690,6 +690,7 @@ struct FastShared {
     int32_t rown[kTile];                 // hits of each row so far
     int32_t scan[kFastThreads];
     double xref[3];                      // first row's position: the frame reference
+    double xd[3][kTile];                 // row positions (FP64), for the build position
     int32_t ext[6];
     int32_t info[4];                     // pass-on flag, per-pair image flag, longest row
 };
@@ -733,34 +734,36 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
 
         __syncthreads();  // LDS of the previous tile no longer read
         // ---- 1. rows: home cell in the frame, frame position ------------------
-        // one round trip: the first row's position (the frame reference) is
-        // shared through LDS
+        // Wave 1 does this tile's global reads of rows and cell sizes and no
+        // global writes: a wave's wait for a read also waits for all of its
+        // earlier writes, and the other waves still have the previous
+        // tile's rows in flight.  The first row's position (the frame
+        // reference) is shared through LDS.
+        const bool loader = wv == 1;
+        const int tr = tid - kWave;  // row slot of a loader lane
         double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        int64_t i = row0 + r0;
         bool act = false;
-        if (tid < kTile) {
-            const int r = r0 + tid;
+        if (loader) {
+            const int r = r0 + tr;
             act = r < n_local;
-            i = row0 + (act ? r : r0);
-            xi = pos[i];
-            if (tid == 0) {
+            xi = pos[row0 + (act ? r : r0)];
+            sh.xd[0][tr] = xi.x;
+            sh.xd[1][tr] = xi.y;
+            sh.xd[2][tr] = xi.z;
+            if (tr == 0) {
                 sh.xref[0] = xi.x;
                 sh.xref[1] = xi.y;
                 sh.xref[2] = xi.z;
             }
-        } else if (tid < kTile + 3) {
-            sh.ext[tid - kTile] = INT32_MAX;
-            sh.ext[3 + tid - kTile] = INT32_MIN;
-        } else if (tid == kTile + 3) {
+        } else if (tid == 0) {
             sh.info[0] = 0;
-            sh.info[2] = 0;
         }
         __syncthreads();
         const double xr[3] = {sh.xref[0], sh.xref[1], sh.xref[2]};
         int c0[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) c0[a] = cell_coord(xr[a], S.lo[a], S.scale[a], bins[a]);
-        if (tid < kTile) {
+        if (loader) {
             const double xa[3] = {xi.x, xi.y, xi.z};
             float xf[3];
 #pragma unroll
@@ -770,15 +773,24 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 // image of the row in the frame: the home cell at c0 + h
                 const int kimg = per[a] ? (c0[a] + h - ci) / bins[a] : 0;
                 xf[a] = (float)((xa[a] + (double)kimg * Ls[a]) - xr[a]);
-                sh.rh[a][tid] = (int16_t)h;
-                sh.frel[a][tid] = (float)(xa[a] - S.lo[a]) - (float)ci * cw[a];
-                if (act) {
-                    atomicMin(&sh.ext[a], h);
-                    atomicMax(&sh.ext[3 + a], h);
+                sh.rh[a][tr] = (int16_t)h;
+                sh.frel[a][tr] = (float)(xa[a] - S.lo[a]) - (float)ci * cw[a];
+                // extent of the home cells: wave reductions (lane 0 of the
+                // tile is always a row)
+                int mn = act ? h : INT32_MAX, mx = act ? h : INT32_MIN;
+#pragma unroll
+                for (int m = 1; m < kWave; m <<= 1) {
+                    const int omn = __shfl_xor(mn, m, kWave), omx = __shfl_xor(mx, m, kWave);
+                    mn = omn < mn ? omn : mn;
+                    mx = omx > mx ? omx : mx;
+                }
+                if (tr == 0) {
+                    sh.ext[a] = mn;
+                    sh.ext[3 + a] = mx;
                 }
             }
-            sh.xrow[tid] = make_float4(xf[0], xf[1], xf[2], 0.f);
-            sh.rown[tid] = act ? 0 : -1;
+            sh.xrow[tr] = make_float4(xf[0], xf[1], xf[2], 0.f);
+            sh.rown[tr] = act ? 0 : -1;
         }
         __syncthreads();
         // ---- 2. frame box and the stencil-cell bitmap ---------------------------
@@ -841,7 +853,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             }
         }
         __syncthreads();
-        for (int u = tid; u < nu; u += kFastThreads) {
+        for (int u = loader ? tr : nu; u < nu; u += kWave) {
             const int b = sh.ucell[u];
             const int f[3] = {b % X[0] + blo[0], (b / X[0]) % X[1] + blo[1], b / (X[0] * X[1]) + blo[2]};
             int pc[3];
@@ -1029,9 +1041,21 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
         __syncthreads();
         // ---- 6. halo numbering, rows out ------------------------------------------
-        if (tid < kTile && act) {
-            const int n = sh.rown[tid];
-            atomicMax(&sh.info[2], n < cap ? n : cap);
+        // writers: every wave but the loader
+        const int wid = wv == 0 ? tid : tid - kWave;
+        constexpr int kWriters = kFastThreads - kWave;
+        const bool act0 = tid < kTile && r0 + tid < n_local;
+        const int64_t i0 = row0 + r0 + tid;
+        if (wv == 0) {
+            // longest row of the tile: a wave reduction
+            int n = act0 ? sh.rown[tid] : 0;
+            n = n < cap ? n : cap;
+#pragma unroll
+            for (int m = 1; m < kWave; m <<= 1) {
+                const int o = __shfl_xor(n, m, kWave);
+                n = o > n ? o : n;
+            }
+            if (tid == 0) sh.info[2] = n;
         }
         const int nwords = (nslot + 31) / 32;
         for (int q = tid; q < nwords; q += kFastThreads) sh.wpre[q] = __popc(sh.used[q]);
@@ -1039,13 +1063,13 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         const int nhalo = block_scan_w<kFastThreads>(sh.wpre, nwords, sh.scan);
         if (nhalo > halo_cap) {
             if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nhalo);
-            if (tid < kTile && act) nn[i] = 0;
+            if (act0) nn[i0] = 0;
             if (tid == 0) halo_n[tile] = 0;
             continue;
         }
         int32_t *hl = halo + (int64_t)tile * halo_cap;
         const bool one_chunk = nslot <= kFastChunk;
-        for (int q = tid; q < nslot; q += kFastThreads) {
+        for (int q = loader ? nslot : wid; q < nslot; q += kWriters) {
             const uint32_t word = sh.used[q >> 5];
             if (word & (1u << (q & 31))) {
                 const int h = sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u));
@@ -1066,7 +1090,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             if (sh.info[1] || nhalo > halo_lds) rare_list[atomicAdd(rare_n, 1)] = tile;
         }
         uint16_t *out = nlist + nl0 + (int64_t)(r0 >> 6) * cap * kTile;
-        for (int e = tid; e < kmax * kTile; e += kFastThreads) {
+        for (int e = loader ? kmax * kTile : wid; e < kmax * kTile; e += kWriters) {
             const int k = e >> 6, t = e & 63;
             uint16_t v = 0;
             const int n = sh.rown[t];
@@ -1077,10 +1101,10 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             }
             out[e] = v;
         }
-        if (tid < kTile && act) {
+        if (act0) {
             const int n = sh.rown[tid];
-            nn[i] = n < cap ? n : cap;
-            xbuild[i] = xi;
+            nn[i0] = n < cap ? n : cap;
+            xbuild[i0] = make_double4(sh.xd[0][tid], sh.xd[1][tid], sh.xd[2][tid], 0.0);
             if (n > cap) latch(st, 5 /*NLIST_OVERFLOW*/, n);
         }
     }
