@@ -14,7 +14,7 @@
 //      distinct ones (bitonic sort in LDS), so any tile shape works,
 //   2. stages the members of those cells (positions and row numbers) in LDS,
 //      a chunk at a time,
-//   3. lets W = 4 lanes per particle stride over the members of the
+//   3. lets W = 8 lanes per particle stride over the members of the
 //      particle's own 27 stencil cells and test |x_j - x_i|^2 < r_list^2 in
 //      FP64 (minimum image written as the stencil's image shift, which for
 //      every pair inside r_list is bitwise the shift the exact quotient
@@ -34,12 +34,15 @@
 
 namespace md {
 
-constexpr int kBuildThreads = 256;   // 64 rows x 4 lanes
-constexpr int kBuildW = 4;
-constexpr int kChunk = 512;          // members staged at once
+constexpr int kBuildThreads = 512;   // 64 rows x 8 lanes
+constexpr int kBuildW = 8;
+constexpr int kChunk = 2048;         // members staged at once
 constexpr int kSlotMax = 16384;      // members of a tile's stencil cells
 constexpr int kRebuildGrid = 2048;   // blocks of the grid-stride rebuild kernels
 constexpr int kKeys = 2048;          // 64 rows x 27 stencil cells, padded
+constexpr int kKpt = kKeys / kBuildThreads;  // stencil keys per thread
+static_assert(kKeys % kBuildThreads == 0 && kKeys <= 8 * kBuildThreads, "key split");
+static_assert(kBuildThreads == kTile * kBuildW, "one row per lane group");
 constexpr int kStencil = 27;
 
 // ---------------------------------------------------------------------------
@@ -422,21 +425,22 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
                 __syncthreads();
             }
         }
-        // distinct keys: flag first occurrences, scan, compact
-        int flags8[8];
-        int32_t kv[8];
+        // distinct keys: flag first occurrences, scan, compact (kKpt keys
+        // per thread)
+        int flg[kKpt];
+        int32_t kv[kKpt];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int q = 8 * tid + k;
+        for (int k = 0; k < kKpt; ++k) {
+            const int q = kKpt * tid + k;
             kv[k] = sh.keys[q];
-            flags8[k] = (kv[k] != INT32_MAX && (q == 0 || kv[k] != sh.keys[q - 1])) ? 1 : 0;
-            sh.ucount[q] = flags8[k];
+            flg[k] = (kv[k] != INT32_MAX && (q == 0 || kv[k] != sh.keys[q - 1])) ? 1 : 0;
+            sh.ucount[q] = flg[k];
         }
         __syncthreads();
         const int nu = block_scan8(sh.ucount, kKeys, sh.scan);
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (flags8[k]) sh.keys[sh.ucount[8 * tid + k]] = kv[k];
+        for (int k = 0; k < kKpt; ++k)
+            if (flg[k]) sh.keys[sh.ucount[kKpt * tid + k]] = kv[k];
         if (tid == 0) {
             int pp = 0;
             const double Ls[3] = {Lx, Ly, Lz};
@@ -667,7 +671,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 constexpr int kFastThreads = 512;
 constexpr int kFastWaves = kFastThreads / kWave;
 constexpr int kFastChunk = 2560;     // members staged at once (float4 each)
-constexpr int kBoxMax = 4096;        // cells of the frame box
+constexpr int kBoxMax = 8192;        // cells of the frame box
 constexpr int kBoxWords = kBoxMax / 32;
 constexpr int kUMax = 256;           // distinct cells of a framed tile
 constexpr int kFastSlotMax = 8192;   // members of a framed tile's stencil cells
@@ -769,24 +773,37 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int ci = cell_coord(xa[a], S.lo[a], S.scale[a], bins[a]);
-                const int h = per[a] ? wrap_rel(ci - c0[a], bins[a]) : ci - c0[a];
+                // home cell relative to the first row's, unwrapped with the cut
+                // either opposite the first row or through it, whichever gives
+                // the tile the shorter extent (a tile whose rows straddle the
+                // cell opposite the first row's is compact only with the cut
+                // through the first row); extents by wave reductions (lane 0
+                // of the tile is always a row)
+                const int d = ci - c0[a];
+                const int sft = bins[a] / 2;
+                int hc[2] = {per[a] ? wrap_rel(d, bins[a]) : d, per[a] ? sft + wrap_rel(d - sft, bins[a]) : d};
+                int mn[2], mx[2];
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    mn[v] = act ? hc[v] : INT32_MAX;
+                    mx[v] = act ? hc[v] : INT32_MIN;
+#pragma unroll
+                    for (int m = 1; m < kWave; m <<= 1) {
+                        const int omn = __shfl_xor(mn[v], m, kWave), omx = __shfl_xor(mx[v], m, kWave);
+                        mn[v] = omn < mn[v] ? omn : mn[v];
+                        mx[v] = omx > mx[v] ? omx : mx[v];
+                    }
+                }
+                const int pick = mx[1] - mn[1] < mx[0] - mn[0] ? 1 : 0;
+                const int h = hc[pick];
                 // image of the row in the frame: the home cell at c0 + h
                 const int kimg = per[a] ? (c0[a] + h - ci) / bins[a] : 0;
                 xf[a] = (float)((xa[a] + (double)kimg * Ls[a]) - xr[a]);
                 sh.rh[a][tr] = (int16_t)h;
                 sh.frel[a][tr] = (float)(xa[a] - S.lo[a]) - (float)ci * cw[a];
-                // extent of the home cells: wave reductions (lane 0 of the
-                // tile is always a row)
-                int mn = act ? h : INT32_MAX, mx = act ? h : INT32_MIN;
-#pragma unroll
-                for (int m = 1; m < kWave; m <<= 1) {
-                    const int omn = __shfl_xor(mn, m, kWave), omx = __shfl_xor(mx, m, kWave);
-                    mn = omn < mn ? omn : mn;
-                    mx = omx > mx ? omx : mx;
-                }
                 if (tr == 0) {
-                    sh.ext[a] = mn;
-                    sh.ext[3 + a] = mx;
+                    sh.ext[a] = mn[pick];
+                    sh.ext[3 + a] = mx[pick];
                 }
             }
             sh.xrow[tr] = make_float4(xf[0], xf[1], xf[2], 0.f);
