@@ -172,14 +172,17 @@ def reduce_pmc(fetch_csv, write_csv, out_path, n):
     for label, path in (("fetch", fetch_csv), ("write", write_csv)):
         per = _counter_rows(path)
         copy = [v for (d, k), v in per.items() if "neg" in k]
-        force = [v for (d, k), v in per.items() if "k_force" in k]
-        if not copy or not force:
-            raise SystemExit(f"{path}: no copy ({len(copy)}) or force ({len(force)}) dispatches")
+        # one fused step = the main force launch plus the launch over rare tiles
+        main = [v for (d, k), v in per.items() if "k_force<" in k]
+        rare = [v for (d, k), v in per.items() if "k_force_rare<" in k]
+        if not copy or not main:
+            raise SystemExit(f"{path}: no copy ({len(copy)}) or force ({len(main)}) dispatches")
         copy_kib = sorted(copy)[len(copy) // 2]
         scale = (COPY_BYTES / 1024.0) / copy_kib
-        force_kib = sum(force) / len(force)
+        force_kib = sum(main) / len(main) + (sum(rare) / len(rare) if rare else 0.0)
         res[label] = {"copy_kib_per_dispatch": copy_kib, "scale": scale,
-                      "force_kib_per_dispatch": force_kib, "force_dispatches": len(force),
+                      "force_kib_per_step": force_kib, "main_dispatches": len(main),
+                      "rare_dispatches": len(rare),
                       "bytes_per_launch": force_kib * 1024.0 * scale}
     res["bytes_per_launch"] = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
     with open(out_path, "w") as f:
