@@ -321,7 +321,7 @@ def main():
                             "rebuilds": mixed["prof_builds"],
                             "force_ms_per_step": pr.force_ms / PS,
                             "rebuild_ms_per_step": pr.rebuild_ms / PS,
-                            "rebuild_ms_each": pr.rebuild_ms / max(pr.rebuild_launches, 1)},
+                            "rebuild_ms_per_build": pr.rebuild_ms / max(mixed["prof_builds"], 1)},
         "step_alg_bytes_per_particle": step_bytes,
         "step_frac_of_hbm": step_bytes * s.n * K / (mixed["ms"] / 1e3) / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "kernel": "k_force (fused force + velocity Verlet)",
