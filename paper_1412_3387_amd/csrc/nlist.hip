@@ -4,9 +4,10 @@
 // Cell list: fixed-capacity bins.  A binning pass assigns every row to the
 // cell floor((x - lo) * bins / L); lanes of a wave that hit the same cell
 // claim their slots with one integer atomic per distinct cell.  A per-cell
-// pass then sorts the members of each cell by row index (rank sort inside
-// one wave), so the list is deterministic although the slots were claimed
-// in arbitrary order.  It also resets the counters for the next build.
+// pass then sorts the members of each cell by x coordinate, ties by row
+// index (rank sort inside one wave), so the list is deterministic although
+// the slots were claimed in arbitrary order, and a line of x-adjacent cells
+// is ordered by x.  It also resets the counters for the next build.
 //
 // Neighbour list: one workgroup per tile of 64 consecutive rows (Morton
 // ordered rows make a tile one or a few compact clusters).  The workgroup
@@ -113,7 +114,9 @@ __device__ __forceinline__ int find_sys_cell(const SysDev *__restrict__ sys, int
     return lo;
 }
 
-// One wave per cell: members ranked by row index, sizes published, counters
+// One wave per cell: members ranked by their FP32 x coordinate relative to
+// the cell's corner, ties by row index (a total order on (bits, row), so the
+// ranks are a permutation whatever the values), sizes published, counters
 // cleared.  Next to each member's row the list keeps its position relative
 // to the cell's lower corner in FP32 (row bits in w), so that the framed
 // build stages a cell with one coalesced read.  cell_cap <= 64 * CPL.
@@ -131,11 +134,28 @@ __global__ __launch_bounds__(256) void k_cell_sort(const SysDev *__restrict__ sy
     for (int64_t c = (int64_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); c < n_cells; c += waves) {
         int m = cell_count[c];
         m = m < cell_cap ? m : cell_cap;
+        const SysDev &S = sys[find_sys_cell(sys, n_sys, c)];
+        const int64_t key = c - S.cell0;
+        const int cx = (int)(key % S.bins[0]), cy = (int)((key / S.bins[0]) % S.bins[1]),
+                  cz = (int)(key / ((int64_t)S.bins[0] * S.bins[1]));
+        const double ox = S.lo[0] + (double)cx * (S.L[0] / S.bins[0]);
+        const double oy = S.lo[1] + (double)cy * (S.L[1] / S.bins[1]);
+        const double oz = S.lo[2] + (double)cz * (S.L[2] / S.bins[2]);
         int32_t v[CPL];
+        float4 f[CPL];
+        int64_t ord[CPL];  // (x bits made order-preserving as a signed integer, row)
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const int k = q * kWave + lane;
             v[q] = k < m ? cell_idx[c * cell_cap + k] : INT32_MAX;
+            f[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            ord[q] = INT64_MAX;
+            if (k < m) {
+                const double4 x = pos[v[q]];
+                f[q] = make_float4((float)(x.x - ox), (float)(x.y - oy), (float)(x.z - oz), __int_as_float(v[q]));
+                const int32_t b = __float_as_int(f[q].x);
+                ord[q] = ((int64_t)(b ^ ((b >> 31) & 0x7FFFFFFF)) << 32) | (uint32_t)v[q];
+            }
         }
         int rank[CPL];
 #pragma unroll
@@ -144,26 +164,17 @@ __global__ __launch_bounds__(256) void k_cell_sort(const SysDev *__restrict__ sy
         for (int q2 = 0; q2 < CPL; ++q2) {
             const int tmax = m - q2 * kWave < kWave ? m - q2 * kWave : kWave;
             for (int t = 0; t < tmax; ++t) {
-                const int32_t other = __shfl(v[q2], t, kWave);
+                const int64_t other = __shfl(ord[q2], t, kWave);
 #pragma unroll
-                for (int q = 0; q < CPL; ++q) rank[q] += other < v[q] ? 1 : 0;
+                for (int q = 0; q < CPL; ++q) rank[q] += other < ord[q] ? 1 : 0;
             }
         }
-        const SysDev &S = sys[find_sys_cell(sys, n_sys, c)];
-        const int64_t key = c - S.cell0;
-        const int cx = (int)(key % S.bins[0]), cy = (int)((key / S.bins[0]) % S.bins[1]),
-                  cz = (int)(key / ((int64_t)S.bins[0] * S.bins[1]));
-        const double ox = S.lo[0] + (double)cx * (S.L[0] / S.bins[0]);
-        const double oy = S.lo[1] + (double)cy * (S.L[1] / S.bins[1]);
-        const double oz = S.lo[2] + (double)cz * (S.L[2] / S.bins[2]);
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const int k = q * kWave + lane;
             if (k < m) {
                 cell_idx[c * cell_cap + rank[q]] = v[q];
-                const double4 x = pos[v[q]];
-                cell_xf[c * cell_cap + rank[q]] =
-                    make_float4((float)(x.x - ox), (float)(x.y - oy), (float)(x.z - oz), __int_as_float(v[q]));
+                cell_xf[c * cell_cap + rank[q]] = f[q];
             }
         }
         if (lane == 0) {
@@ -677,6 +688,48 @@ constexpr int kUMax = 256;           // distinct cells of a framed tile
 constexpr int kFastSlotMax = 8192;   // members of a framed tile's stencil cells
 constexpr int kRuns = 9;
 constexpr float kBand = 1.0f / 1024.0f;
+static_assert(kUMax <= 256, "slot map holds distinct cells as bytes");
+
+// DPP lane move within rows of 16 lanes (every lane of the wave active).
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+
+// Minimum / maximum over the 64 lanes of a fully active wave: swaps within
+// quads, half rows and rows, then the four row results.
+__device__ __forceinline__ int wave_min_full(int v)
+{
+    v = min(v, dpp_mov<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = min(v, dpp_mov<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = min(v, dpp_mov<0x141>(v));  // row_half_mirror
+    v = min(v, dpp_mov<0x140>(v));  // row_mirror
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// Values that are the same in every lane (read from LDS or computed from
+// such values), moved to scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ double uni(double v)
+{
+    const int64_t b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ int wave_max_full(int v)
+{
+    v = max(v, dpp_mov<0xB1>(v));
+    v = max(v, dpp_mov<0x4E>(v));
+    v = max(v, dpp_mov<0x141>(v));
+    v = max(v, dpp_mov<0x140>(v));
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
 
 struct FastShared {
     float4 cp[kFastChunk];               // member position in the frame (FP32), row in w
@@ -692,7 +745,8 @@ struct FastShared {
     float frel[3][kTile];                // row offset inside its home cell
     int16_t rh[3][kTile];                // row home cell in the frame
     int32_t rown[kTile];                 // hits of each row so far
-    int32_t scan[kFastThreads];
+    int32_t scan[kFastWaves];            // per-wave totals of the block scans
+    uint8_t smap[kFastChunk];            // distinct cell of each slot of the chunk
     double xref[3];                      // first row's position: the frame reference
     double xd[3][kTile];                 // row positions (FP64), for the build position
     int32_t ext[6];
@@ -763,10 +817,10 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             sh.info[0] = 0;
         }
         __syncthreads();
-        const double xr[3] = {sh.xref[0], sh.xref[1], sh.xref[2]};
+        const double xr[3] = {uni(sh.xref[0]), uni(sh.xref[1]), uni(sh.xref[2])};
         int c0[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) c0[a] = cell_coord(xr[a], S.lo[a], S.scale[a], bins[a]);
+        for (int a = 0; a < 3; ++a) c0[a] = uni(cell_coord(xr[a], S.lo[a], S.scale[a], bins[a]));
         if (loader) {
             const double xa[3] = {xi.x, xi.y, xi.z};
             float xf[3];
@@ -785,14 +839,8 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 int mn[2], mx[2];
 #pragma unroll
                 for (int v = 0; v < 2; ++v) {
-                    mn[v] = act ? hc[v] : INT32_MAX;
-                    mx[v] = act ? hc[v] : INT32_MIN;
-#pragma unroll
-                    for (int m = 1; m < kWave; m <<= 1) {
-                        const int omn = __shfl_xor(mn[v], m, kWave), omx = __shfl_xor(mx[v], m, kWave);
-                        mn[v] = omn < mn[v] ? omn : mn[v];
-                        mx[v] = omx > mx[v] ? omx : mx[v];
-                    }
+                    mn[v] = wave_min_full(act ? hc[v] : INT32_MAX);
+                    mx[v] = wave_max_full(act ? hc[v] : INT32_MIN);
                 }
                 const int pick = mx[1] - mn[1] < mx[0] - mn[0] ? 1 : 0;
                 const int h = hc[pick];
@@ -815,7 +863,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         bool pass = false;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            int lo_ = sh.ext[a] - 1, hi_ = sh.ext[3 + a] + 1;
+            int lo_ = uni(sh.ext[a]) - 1, hi_ = uni(sh.ext[3 + a]) + 1;
             if (!per[a]) {
                 lo_ = lo_ > -c0[a] ? lo_ : -c0[a];
                 hi_ = hi_ < bins[a] - 1 - c0[a] ? hi_ : bins[a] - 1 - c0[a];
@@ -854,7 +902,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         // ---- 3. distinct cells (box order) and their members ----------------------
         for (int q = tid; q < nbw; q += kFastThreads) sh.bpre[q] = __popc(sh.box[q]);
         __syncthreads();
-        const int nu = block_scan_w<kFastThreads>(sh.bpre, nbw, sh.scan);
+        const int nu = uni(block_scan_w<kFastThreads>(sh.bpre, nbw, sh.scan));
         if (tid == 0) sh.bpre[nbw] = nu;
         if (nu > kUMax) {
             if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
@@ -890,7 +938,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             sh.uoff[u] = make_float4(off[0], off[1], off[2], 0.f);
         }
         __syncthreads();
-        const int nslot = block_scan_w<kFastThreads>(sh.ustart, nu, sh.scan);
+        const int nslot = uni(block_scan_w<kFastThreads>(sh.ustart, nu, sh.scan));
         if (tid == 0) {
             sh.ustart[nu] = nslot;
             int pp = 0;
@@ -906,6 +954,20 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         __syncthreads();
         // ---- 4. the nine lines of every row, cut to cells within r_list -------------
         const float rl2f = (float)rl2 * 1.0001f + 1e-3f;
+        // squared distance in y and z from row t to the cells of its line rr
+        // (a lower bound for every member of the line)
+        auto line_gap2 = [&](int t, int dy, int dz) -> float {
+            float gyz = 0.f;
+            if (dy != 0) {
+                const float gg = dy < 0 ? sh.frel[1][t] : cw[1] - sh.frel[1][t];
+                gyz += gg > 0.f ? gg * gg : 0.f;
+            }
+            if (dz != 0) {
+                const float gg = dz < 0 ? sh.frel[2][t] : cw[2] - sh.frel[2][t];
+                gyz += gg > 0.f ? gg * gg : 0.f;
+            }
+            return gyz;
+        };
         for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
             const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
             uint32_t v = 0u;
@@ -914,15 +976,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 const int hx = sh.rh[0][t], hy = sh.rh[1][t] + dy, hz = sh.rh[2][t] + dz;
                 bool in = (per[1] || (c0[1] + hy >= 0 && c0[1] + hy < bins[1])) &&
                           (per[2] || (c0[2] + hz >= 0 && c0[2] + hz < bins[2]));
-                float gyz = 0.f;
-                if (dy != 0) {
-                    const float gg = dy < 0 ? sh.frel[1][t] : cw[1] - sh.frel[1][t];
-                    gyz += gg > 0.f ? gg * gg : 0.f;
-                }
-                if (dz != 0) {
-                    const float gg = dz < 0 ? sh.frel[2][t] : cw[2] - sh.frel[2][t];
-                    gyz += gg > 0.f ? gg * gg : 0.f;
-                }
+                const float gyz = line_gap2(t, dy, dz);
                 in = in && gyz <= rl2f;
                 if (in) {
                     const float fx = sh.frel[0][t];
@@ -939,21 +993,82 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             sh.run[t][rr] = v;
         }
         // ---- 5. stage members a chunk at a time, scan every row's lines -------------
+        const bool one_chunk = nslot <= kFastChunk;
+        float fext = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fext = fmaxf(fext, (float)X[a] * cw[a]);
+        // bound on the FP32 error of a frame x difference, with room to spare
+        const float xmargin = 1e-3f + fext * 0x1p-18f;
         const float lo_f = (float)rl2 * (1.0f - kBand), hi_f = (float)rl2 * (1.0f + kBand);
         for (int q0 = 0; q0 < nslot; q0 += kFastChunk) {
             const int q1 = q0 + kFastChunk < nslot ? q0 + kFastChunk : nslot;
             __syncthreads();
-            // staging: one coalesced read per member (cell-relative FP32
-            // position and row), moved into the frame by its cell's corner
-            for (int q = q0 + tid; q < q1; q += kFastThreads) {
-                const int u = upper_idx(sh.ustart, nu, q);
-                const float4 c = cell_xf[(int64_t)sh.ucell[u] * cell_cap + (q - sh.ustart[u])];
-                const float4 o = sh.uoff[u];
-                sh.cp[q - q0] = make_float4(c.x + o.x, c.y + o.y, c.z + o.z, c.w);
+            // slot -> distinct cell of the chunk: each cell writes its index
+            // over its own slots
+            for (int u = tid; u < nu; u += kFastThreads) {
+                int qa = sh.ustart[u], qb = sh.ustart[u + 1];
+                qa = qa > q0 ? qa : q0;
+                qb = qb < q1 ? qb : q1;
+                for (int q = qa; q < qb; ++q) sh.smap[q - q0] = (uint8_t)u;
             }
             __syncthreads();
+            // staging: one coalesced read per member (cell-relative FP32
+            // position and row), moved into the frame by its cell's corner;
+            // two reads of a thread in flight at once
+            {
+                constexpr int kB = 2;
+                for (int qb = q0 + tid; qb < q1; qb += kB * kFastThreads) {
+                    int us[kB];
+                    float4 cs[kB];
+#pragma unroll
+                    for (int k = 0; k < kB; ++k) {
+                        const int q = qb + k * kFastThreads;
+                        us[k] = q < q1 ? (int)sh.smap[q - q0] : 0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < kB; ++k) {
+                        const int q = qb + k * kFastThreads;
+                        if (q < q1) cs[k] = cell_xf[(int64_t)sh.ucell[us[k]] * cell_cap + (q - sh.ustart[us[k]])];
+                    }
+#pragma unroll
+                    for (int k = 0; k < kB; ++k) {
+                        const int q = qb + k * kFastThreads;
+                        if (q < q1) {
+                            const float4 o = sh.uoff[us[k]];
+                            sh.cp[q - q0] = make_float4(cs[k].x + o.x, cs[k].y + o.y, cs[k].z + o.z, cs[k].w);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (one_chunk) {
+                // members of a line are ordered by x (cells in x order, each
+                // sorted by x): cut every line to the slots within the half
+                // width that its y-z distance leaves, |dx|^2 <= r_list^2 -
+                // gap^2, widened by a margin for the FP32 frame coordinates
+                for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
+                    const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
+                    const uint32_t v = sh.run[t][rr];
+                    const int a = (int)(v & 0xffffu), b = (int)(v >> 16);
+                    if (b <= a) continue;
+                    const float gyz = line_gap2(t, rr % 3 - 1, rr / 3 - 1);
+                    const float hw = sqrtf(fmaxf(rl2f - gyz, 0.f)) + xmargin;
+                    const float xc = sh.xrow[t].x;
+                    const float tlo = xc - hw, thi = xc + hw;
+                    // first slot with x >= tlo, first slot with x > thi
+                    int pa = a, pb = a;
+                    int step = 1;
+                    while (2 * step <= b - a) step *= 2;
+                    for (; step > 0; step >>= 1) {
+                        if (pa + step <= b && sh.cp[pa + step - 1].x < tlo) pa += step;
+                        if (pb + step <= b && sh.cp[pb + step - 1].x <= thi) pb += step;
+                    }
+                    sh.run[t][rr] = (uint32_t)pa | ((uint32_t)(pb > pa ? pb : pa) << 16);
+                }
+                __syncthreads();
+            }
             for (int t = wv; t < kTile; t += kFastWaves) {
-                int ntot = sh.rown[t];
+                int ntot = uni(sh.rown[t]);
                 if (ntot < 0) continue;  // inactive row
                 // the row's nine lines cut to this chunk; lane r < 9 holds line r
                 int len = 0, ra0 = 0;
@@ -992,7 +1107,8 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                     b0 = b1;
                     pre = pn;
                 }
-                const float4 xt = sh.xrow[t];
+                const float4 xt0 = sh.xrow[t];
+                const float4 xt = make_float4(uni(xt0.x), uni(xt0.y), uni(xt0.z), 0.f);
                 const int32_t it = (int32_t)(row0 + r0 + t);
                 int32_t part[kMaxBondCap];
                 if constexpr (EXCL) {
@@ -1002,56 +1118,73 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                         part[bnd] = bnd < S.bond_cap ? partners[prow + bnd] : -1;
                 }
                 uint16_t *myrow = srows + t * rstride;
-                // candidate test: FP32 in the frame, the exact FP64 test near r_list
-                auto near = [&](const float4 c, bool on) -> bool {
-                    const float dx = c.x - xt.x, dy = c.y - xt.y, dz = c.z - xt.z;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
+                // exact FP64 decision of a candidate whose FP32 distance is
+                // within the band around r_list
+                auto exact = [&](const float4 c) -> bool {
                     const int32_t j = __float_as_int(c.w);
-                    bool hit = on && r2 < lo_f && j != it;
-                    if (on && r2 >= lo_f && r2 <= hi_f) {
-                        const double4 xa = pos[it], xb = pos[j];
-                        const double cj[3] = {(double)c.x, (double)c.y, (double)c.z};
-                        const double xt3[3] = {(double)xt.x, (double)xt.y, (double)xt.z};
-                        const double pa[3] = {xa.x, xa.y, xa.z}, pb[3] = {xb.x, xb.y, xb.z};
-                        double d[3];
+                    const double4 xa = pos[it], xb = pos[j];
+                    const double cj[3] = {(double)c.x, (double)c.y, (double)c.z};
+                    const double xt3[3] = {(double)xt.x, (double)xt.y, (double)xt.z};
+                    const double pa[3] = {xa.x, xa.y, xa.z}, pb[3] = {xb.x, xb.y, xb.z};
+                    double d[3];
 #pragma unroll
-                        for (int ax = 0; ax < 3; ++ax) {
-                            // frame images of both: k = round((frame - stored) / L)
-                            const double kj = rint((cj[ax] + xr[ax] - pb[ax]) * iL[ax]);
-                            const double ki = rint((xt3[ax] + xr[ax] - pa[ax]) * iL[ax]);
-                            d[ax] = pb[ax] - pa[ax];
-                            if (kj != ki) d[ax] = d[ax] + (kj - ki) * Ls[ax];
-                        }
-                        hit = norm2_exact(d[0], d[1], d[2]) < rl2 && j != it;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        // frame images of both: k = round((frame - stored) / L)
+                        const double kj = rint((cj[ax] + xr[ax] - pb[ax]) * iL[ax]);
+                        const double ki = rint((xt3[ax] + xr[ax] - pa[ax]) * iL[ax]);
+                        d[ax] = pb[ax] - pa[ax];
+                        if (kj != ki) d[ax] = d[ax] + (kj - ki) * Ls[ax];
                     }
+                    return norm2_exact(d[0], d[1], d[2]) < rl2 && j != it;
+                };
+                auto excluded = [&](bool hit, const float4 c) -> bool {
                     if constexpr (EXCL) {
                         if (hit) {
-                            const int32_t tj = tag[j];
+                            const int32_t tj = tag[__float_as_int(c.w)];
 #pragma unroll
                             for (int bnd = 0; bnd < kMaxBondCap; ++bnd) hit = hit && part[bnd] != tj;
                         }
                     }
                     return hit;
                 };
-                auto append = [&](bool hit, int q) {
-                    const uint64_t mask = __ballot(hit);
-                    const int p = ntot + __popcll(mask & below);
+                // a hit goes to the row's next entry (entries past the
+                // capacity land on the row's spare slot) and marks its slot
+                auto append = [&](bool hit, uint64_t mask, int q) {
                     if (hit) {
-                        if (p < cap) myrow[p] = (uint16_t)q;
+                        const int p = ntot + (int)__builtin_amdgcn_mbcnt_hi(
+                                                 (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                        myrow[p < cap ? p : cap] = (uint16_t)q;
                         atomicOr(&sh.used[q >> 5], 1u << (q & 31));
                     }
                     ntot += __popcll(mask);
                 };
+                // every lane reads a slot of the chunk, clamped: lanes past
+                // their line's end take no part
+                const float4 *cq = sh.cp - q0;
+                const int qlast = q1 - 1;
                 for (int qa = base;; qa += 2 * gsz) {
                     const int qb = qa + gsz;
                     const bool ona = qa < end, onb = qb < end;
                     if (__ballot(ona) == 0ull) break;
-                    const float4 ca = sh.cp[(ona ? qa : q0) - q0];
-                    const float4 cb = sh.cp[(onb ? qb : q0) - q0];
-                    const bool ha = near(ca, ona);
-                    const bool hb = near(cb, onb);
-                    append(ha, qa);
-                    append(hb, qb);
+                    const float4 ca = cq[qa < qlast ? qa : qlast];
+                    const float4 cb = cq[qb < qlast ? qb : qlast];
+                    const float dxa = ca.x - xt.x, dya = ca.y - xt.y, dza = ca.z - xt.z;
+                    const float dxb = cb.x - xt.x, dyb = cb.y - xt.y, dzb = cb.z - xt.z;
+                    const float r2a = dxa * dxa + dya * dya + dza * dza;
+                    const float r2b = dxb * dxb + dyb * dyb + dzb * dzb;
+                    bool ha = ona && r2a < lo_f && __float_as_int(ca.w) != it;
+                    bool hb = onb && r2b < lo_f && __float_as_int(cb.w) != it;
+                    const bool ba = ona && r2a >= lo_f && r2a <= hi_f;
+                    const bool bb = onb && r2b >= lo_f && r2b <= hi_f;
+                    if (__builtin_expect(__ballot(ba || bb) != 0ull, 0)) {
+                        if (ba) ha = exact(ca);
+                        if (bb) hb = exact(cb);
+                    }
+                    ha = excluded(ha, ca);
+                    hb = excluded(hb, cb);
+                    const uint64_t ma = __ballot(ha), mb = __ballot(hb);
+                    append(ha, ma, qa);
+                    append(hb, mb, qb);
                 }
                 if (lane == 0) sh.rown[t] = ntot;
             }
@@ -1066,18 +1199,13 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         if (wv == 0) {
             // longest row of the tile: a wave reduction
             int n = act0 ? sh.rown[tid] : 0;
-            n = n < cap ? n : cap;
-#pragma unroll
-            for (int m = 1; m < kWave; m <<= 1) {
-                const int o = __shfl_xor(n, m, kWave);
-                n = o > n ? o : n;
-            }
+            n = wave_max_full(n < cap ? n : cap);
             if (tid == 0) sh.info[2] = n;
         }
         const int nwords = (nslot + 31) / 32;
         for (int q = tid; q < nwords; q += kFastThreads) sh.wpre[q] = __popc(sh.used[q]);
         __syncthreads();
-        const int nhalo = block_scan_w<kFastThreads>(sh.wpre, nwords, sh.scan);
+        const int nhalo = uni(block_scan_w<kFastThreads>(sh.wpre, nwords, sh.scan));
         if (nhalo > halo_cap) {
             if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nhalo);
             if (act0) nn[i0] = 0;
@@ -1085,7 +1213,6 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             continue;
         }
         int32_t *hl = halo + (int64_t)tile * halo_cap;
-        const bool one_chunk = nslot <= kFastChunk;
         for (int q = loader ? nslot : wid; q < nslot; q += kWriters) {
             const uint32_t word = sh.used[q >> 5];
             if (word & (1u << (q & 31))) {
@@ -1100,7 +1227,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 hl[h] = j;
             }
         }
-        const int kmax = sh.info[2];
+        const int kmax = uni(sh.info[2]);
         if (tid == 0) {
             halo_n[tile] = (int32_t)((uint32_t)nhalo | ((uint32_t)kmax << 16) | (sh.info[1] ? 0x80000000u : 0u));
             // per-pair images or a halo beyond the force pass's LDS staging
@@ -1158,7 +1285,8 @@ int nlist_row_stride(int cap)
 {
     // uint16 entries per staged row; an odd number of words keeps the
     // transposed read-out free of bank conflicts
-    int r = cap + (cap & 1);
+    // one spare entry past the capacity takes the writes of an overflowing row
+    int r = cap + 1 + ((cap + 1) & 1);
     if (((r / 2) & 1) == 0) r += 2;
     return r;
 }

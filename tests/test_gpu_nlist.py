@@ -21,7 +21,11 @@ def _ctx(B, pos, vel, L, **kw):
     return B.Context([p], [dict(pos=pos, vel=vel, L=L)])
 
 
-def test_cell_list_matches_stable_counting_sort(orc, B):
+def test_cell_list_matches_counting_sort_ordered_by_x(orc, B):
+    """Cell membership equals the oracle's counting sort; inside a cell the
+    members are ordered by their FP32 x offset from the cell's lower corner,
+    ties by row (any order within a cell is a valid cell list; this one makes
+    a line of x-adjacent cells x-ordered)."""
     s = inputs.lj_small()
     ctx = _ctx(B, s.pos, s.vel, s.L, precision=B.FP64)
     ctx.build_nlist(True)
@@ -31,8 +35,15 @@ def test_cell_list_matches_stable_counting_sort(orc, B):
     assert np.array_equal(bins, rb)
     cell_of, start, idx = orc.cell_list(s.pos, s.L, rb)
     assert np.array_equal(size, np.diff(start))
+    x, _, _, _ = ctx.host_state()  # rows as the device holds them (unsorted here)
+    w = s.L[0] / rb[0]
     for c in range(len(size)):
-        assert np.array_equal(members[c], idx[start[c]:start[c + 1]]), c
+        m = np.asarray(members[c])
+        assert np.array_equal(np.sort(m), np.sort(idx[start[c]:start[c + 1]])), c
+        cx = c % rb[0]
+        xr = (x[m, 0] - (0.0 + cx * w)).astype(np.float32)
+        key = list(zip(xr.tolist(), m.tolist()))
+        assert key == sorted(key), c
 
 
 @pytest.mark.parametrize("sort_period,halo_cap", [(0, 0), (1, 0), (0, 2048), (1, 1024)])
