@@ -14,9 +14,10 @@
 // read in the launch sees the old ones; DPD double-buffers the velocities
 // too, because the pair force reads neighbour velocities.
 //
-// Precision: every separation, the cut-off test and the integrator are
-// FP64.  With MIXED the pair and bond arithmetic after the cut-off test and
-// the force accumulation are FP32; energies and virials are summed in FP64.
+// Precision: every separation, the cut-off test, the force sums and the
+// integrator are FP64.  With MIXED the pair and bond arithmetic after the
+// cut-off test is FP32 (each pair's F/r is widened before it is summed);
+// energies and virials are summed in FP64.
 #include <type_traits>
 
 #include "device.h"
@@ -37,7 +38,10 @@ template <> __device__ __forceinline__ float tlog<float>(float x) { return __log
 template <> __device__ __forceinline__ double tlog<double>(double x) { return log(x); }
 
 // LJ-family pair term for one neighbour inside the cut-off.  Returns the
-// force divided by r (F_i = ff * (x_i - x_j)); adds energy and virial.
+// force divided by r (F_i = ff * (x_i - x_j)), 24 eps s6 (2 s6 - 1) / r^2 with
+// s6 = (sigma^2 / r^2)^3 written as s6 (48 eps s6 - 24 eps) / r^2; adds energy
+// and virial.  Finite for every r2 > 0; a caller that masks the result with a
+// select may pass any r2.
 template <typename T, bool LOG>
 __device__ __forceinline__ T lj_pair(double r2, T eps, T sig2, double shift, double &e, double &vir,
                                     bool in = true)
@@ -45,7 +49,7 @@ __device__ __forceinline__ T lj_pair(double r2, T eps, T sig2, double shift, dou
     const T r2inv = recip<T>((T)r2);
     const T s2 = sig2 * r2inv;
     const T s6 = s2 * s2 * s2;
-    const T ff = (T)24 * eps * s6 * ((T)2 * s6 - (T)1) * r2inv;
+    const T ff = s6 * ((T)48 * eps * s6 - (T)24 * eps) * r2inv;
     if constexpr (LOG) {
         if (in) {
             e += (double)((T)4 * eps * s6 * (s6 - (T)1)) - shift;
@@ -181,7 +185,7 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
     uint32_t step_key = a.timestep;
     if constexpr (POT == PAIR_DPD)
         if (a.timestep_ptr) step_key = *a.timestep_ptr;
-    T fx = 0, fy = 0, fz = 0;
+    double fx = 0, fy = 0, fz = 0;
     double e = 0.0, vir = 0.0;
 
     // four neighbours per pass: all LDS reads of a pass issue before any use.
@@ -226,15 +230,18 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double r2 = norm2_exact(dx[u], dy[u], dz[u]);
+                // FP64 in both precisions; the FP64 path keeps the unfused,
+                // fixed-order sum of the reference, the mixed path fuses it
+                const double r2 = MIXED ? __fma_rn(dx[u], dx[u], __fma_rn(dy[u], dy[u], dz[u] * dz[u]))
+                                        : norm2_exact(dx[u], dy[u], dz[u]);
                 if constexpr (POT == PAIR_LJ || POT == PAIR_WCA) {
                     // branch-free: lanes outside the cut-off add zero
                     const bool in = ok[u] && r2 < rc2;
-                    T ff = lj_pair<T, LOG>(in ? r2 : 1.0, eps, sig2, shift, e, vir, in);
+                    T ff = lj_pair<T, LOG>(r2, eps, sig2, shift, e, vir, in);
                     ff = in ? ff : (T)0;
-                    fx += ff * (T)dx[u];
-                    fy += ff * (T)dy[u];
-                    fz += ff * (T)dz[u];
+                    fx = __fma_rn((double)ff, dx[u], fx);
+                    fy = __fma_rn((double)ff, dy[u], fy);
+                    fz = __fma_rn((double)ff, dz[u], fz);
                     continue;
                 }
                 if (ok[u] && r2 < rc2) {
@@ -274,9 +281,9 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
                             vir += (double)(ff * tr2);
                         }
                     }
-                    fx += ff * (T)dx[u];
-                    fy += ff * (T)dy[u];
-                    fz += ff * (T)dz[u];
+                    fx = __fma_rn((double)ff, dx[u], fx);
+                    fy = __fma_rn((double)ff, dy[u], fy);
+                    fz = __fma_rn((double)ff, dz[u], fz);
                 }
             }
         }

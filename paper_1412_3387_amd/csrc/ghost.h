@@ -14,6 +14,7 @@ constexpr int kGhostPerRow = 8;      // stored list entries per local row (7 nee
 struct GhostBuffers {
     uint32_t *mask;       // direction bits per row
     int32_t *blk_counts;  // [26][blocks] entries per direction per block, scanned in place
+    int32_t *blk_sums;    // block sums of that scan
     int32_t *list;        // kGhostPerRow slots per row: system s owns [8 row0_s, 8 (row0_s + n_cap_s))
     int32_t *totals;      // entries of the stored list of each system
     int64_t rows;

@@ -22,6 +22,7 @@ size_t ghost_workspace_bytes(int64_t rows, int n_sys)
 {
     const int64_t blocks = (rows + kGhostBlock - 1) / kGhostBlock;
     return a256(sizeof(uint32_t) * rows) + a256(sizeof(int32_t) * 26 * (size_t)blocks) +
+           a256(sizeof(int32_t) * scan_sums_len(26 * blocks)) +
            a256(sizeof(int32_t) * kGhostPerRow * (size_t)rows) + a256(sizeof(int32_t) * n_sys) + 256;
 }
 
@@ -33,6 +34,7 @@ GhostBuffers make_ghost_buffers(char *base, int64_t rows, int n_sys)
     size_t off = 0;
     B.mask = reinterpret_cast<uint32_t *>(base + off); off += a256(sizeof(uint32_t) * rows);
     B.blk_counts = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * 26 * (size_t)blocks);
+    B.blk_sums = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * scan_sums_len(26 * blocks));
     B.list = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * kGhostPerRow * (size_t)rows);
     B.totals = reinterpret_cast<int32_t *>(base + off);
     B.rows = rows;
@@ -197,7 +199,7 @@ int queue_ghost_select(hipStream_t stream, const GhostBuffers &B, const GhostArg
     const int nblocks = (g.n_local + kGhostBlock - 1) / kGhostBlock;
     const int nb = nblocks > 0 ? nblocks : 1;
     hipLaunchKernelGGL(k_ghost_mask, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb);
-    launch_scan_single(stream, B.blk_counts, B.blk_counts, 26 * (int64_t)nb, g.total);
+    launch_scan(stream, B.blk_counts, B.blk_counts, 26 * (int64_t)nb, g.total, B.blk_sums);
     hipLaunchKernelGGL(k_ghost_totals, dim3(1), dim3(64), 0, stream, B.blk_counts, g.total, nb, g.counts,
                        g.offsets, g.send_cap, g.list_cap, g.status);
     hipLaunchKernelGGL(k_ghost_scatter, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb);

@@ -1234,16 +1234,29 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             if (sh.info[1] || nhalo > halo_lds) rare_list[atomicAdd(rare_n, 1)] = tile;
         }
         uint16_t *out = nlist + nl0 + (int64_t)(r0 >> 6) * cap * kTile;
-        for (int e = loader ? kmax * kTile : wid; e < kmax * kTile; e += kWriters) {
-            const int k = e >> 6, t = e & 63;
-            uint16_t v = 0;
-            const int n = sh.rown[t];
-            if (k < n && k < cap) {
-                const int q = srows[t * rstride + k];
-                const uint32_t word = sh.used[q >> 5];
-                v = (uint16_t)(sh.wpre[q >> 5] + __popc(word & ((1u << (q & 31)) - 1u)));
+        // four entries of a thread at a time, their LDS reads issued together
+        constexpr int kOut = 4;
+        for (int e0 = loader ? kmax * kTile : wid; e0 < kmax * kTile; e0 += kOut * kWriters) {
+            int q[kOut];
+#pragma unroll
+            for (int b = 0; b < kOut; ++b) {
+                const int e = e0 + b * kWriters;
+                const int k = e >> 6, t = e & 63;
+                const int n = sh.rown[t];
+                q[b] = e < kmax * kTile && k < n && k < cap ? (int)srows[t * rstride + k] : -1;
             }
-            out[e] = v;
+#pragma unroll
+            for (int b = 0; b < kOut; ++b) {
+                const int e = e0 + b * kWriters;
+                if (e < kmax * kTile) {
+                    uint16_t v = 0;
+                    if (q[b] >= 0) {
+                        const uint32_t word = sh.used[q[b] >> 5];
+                        v = (uint16_t)(sh.wpre[q[b] >> 5] + __popc(word & ((1u << (q[b] & 31)) - 1u)));
+                    }
+                    out[e] = v;
+                }
+            }
         }
         if (act0) {
             const int n = sh.rown[tid];

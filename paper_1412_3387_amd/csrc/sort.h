@@ -13,6 +13,7 @@ struct SortBuffers {
     uint64_t *keys[2];
     int32_t *vals[2];
     int32_t *hist;      // 256 digit counts per tile
+    int32_t *hist_sums; // block sums of the histogram scan
     int32_t *tag_tmp;
     int64_t rows;
     int64_t tiles;      // radix tiles of kRadixTile rows
@@ -33,9 +34,13 @@ int queue_morton_sort(const LaunchCtx &L, const SortBuffers &B, double4 *pos, do
 // Keys only (for inspection): keys[row] = (system << 30) | morton.
 void launch_morton_keys(const LaunchCtx &L, const double4 *pos, uint64_t *keys, int32_t *vals);
 
-// Exclusive scan of n int32 values in one workgroup; out may alias in.
-// If total != nullptr the sum is written there.
-void launch_scan_single(hipStream_t stream, const int32_t *in, int32_t *out, int64_t n,
-                        int32_t *total);
+// Exclusive scan of n int32 values; out may alias in.  If total != nullptr
+// the sum is written there.  Two levels: the sums of blocks of kScanTile
+// values (in sums, scan_sums_len(n) entries), their scan in one workgroup,
+// then every block's scan offset by its prefix.
+constexpr int kScanTile = 4096;
+inline int64_t scan_sums_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+void launch_scan(hipStream_t stream, const int32_t *in, int32_t *out, int64_t n, int32_t *total,
+                 int32_t *sums);
 
 }  // namespace md

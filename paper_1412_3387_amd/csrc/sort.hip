@@ -15,7 +15,8 @@ size_t sort_workspace_bytes(int64_t rows)
 {
     const int64_t tiles = (rows + kRadixTile - 1) / kRadixTile;
     return 2 * a256(sizeof(uint64_t) * rows) + 2 * a256(sizeof(int32_t) * rows) +
-           a256(sizeof(int32_t) * 256 * (size_t)tiles) + a256(sizeof(int32_t) * rows) + 256;
+           a256(sizeof(int32_t) * 256 * (size_t)tiles) + a256(sizeof(int32_t) * scan_sums_len(256 * tiles)) +
+           a256(sizeof(int32_t) * rows) + 256;
 }
 
 SortBuffers make_sort_buffers(char *base, int64_t rows)
@@ -29,6 +30,8 @@ SortBuffers make_sort_buffers(char *base, int64_t rows)
     B.vals[0] = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * rows);
     B.vals[1] = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * rows);
     B.hist = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * 256 * (size_t)B.tiles);
+    B.hist_sums = reinterpret_cast<int32_t *>(base + off);
+    off += a256(sizeof(int32_t) * scan_sums_len(256 * B.tiles));
     B.tag_tmp = reinterpret_cast<int32_t *>(base + off);
     return B;
 }
@@ -181,9 +184,66 @@ __global__ __launch_bounds__(1024) void k_scan_single(const int32_t *in, int32_t
     }
 }
 
-void launch_scan_single(hipStream_t stream, const int32_t *in, int32_t *out, int64_t n, int32_t *total)
+// Sum of each block of kScanTile values (coalesced reads, fixed-order
+// integer reduction).
+__global__ __launch_bounds__(256) void k_scan_block_sums(const int32_t *__restrict__ in, int64_t n,
+                                                         int32_t *__restrict__ sums)
 {
-    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, stream, in, out, n, total);
+    __shared__ int32_t ws[4];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanTile / 256; ++k) {
+        const int64_t i = b0 + k * 256 + threadIdx.x;
+        s += i < n ? in[i] : 0;
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// Exclusive scan of each block, offset by the block's scanned sum: every
+// thread reads its 16 consecutive values before writing them (in-place safe).
+__global__ __launch_bounds__(256) void k_scan_block_apply(const int32_t *in, int32_t *out, int64_t n,
+                                                          const int32_t *__restrict__ sums)
+{
+    constexpr int kPer = kScanTile / 256;
+    __shared__ int32_t ws[4];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)kPer * threadIdx.x;
+    int32_t v[kPer];
+    int32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        v[k] = b0 + k < n ? in[b0 + k] : 0;
+        tot += v[k];
+    }
+    const int lane = lane_id();
+    int32_t inc = tot;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+    }
+    if (lane == kWave - 1) ws[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    int32_t run = sums[blockIdx.x] + inc - tot;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) run += ws[w];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (b0 + k < n) out[b0 + k] = run;
+        run += v[k];
+    }
+}
+
+void launch_scan(hipStream_t stream, const int32_t *in, int32_t *out, int64_t n, int32_t *total,
+                 int32_t *sums)
+{
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb > 0) hipLaunchKernelGGL(k_scan_block_sums, dim3((unsigned)nb), dim3(256), 0, stream, in, n, sums);
+    // the block sums, scanned in place by one workgroup (also writes the total)
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, stream, sums, sums, nb, total);
+    if (nb > 0) hipLaunchKernelGGL(k_scan_block_apply, dim3((unsigned)nb), dim3(256), 0, stream, in, out, n, sums);
 }
 
 void launch_morton_keys(const LaunchCtx &L, const double4 *pos, uint64_t *keys, int32_t *vals)
@@ -208,7 +268,7 @@ int queue_morton_sort(const LaunchCtx &L, const SortBuffers &B, double4 *pos, do
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)B.tiles), dim3(256), 0, L.stream, B.keys[cur],
                            B.rows, shift, B.tiles, B.hist);
-        launch_scan_single(L.stream, B.hist, B.hist, 256 * B.tiles, nullptr);
+        launch_scan(L.stream, B.hist, B.hist, 256 * B.tiles, nullptr, B.hist_sums);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)B.tiles), dim3(256), 0, L.stream, B.keys[cur],
                            B.vals[cur], B.keys[cur ^ 1], B.vals[cur ^ 1], B.rows, shift, B.tiles, B.hist);
         cur ^= 1;
