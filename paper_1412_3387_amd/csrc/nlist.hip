@@ -883,20 +883,23 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         const int nbw = (vol + 31) >> 5;
         for (int q = tid; q < nbw; q += kFastThreads) sh.box[q] = 0u;
         __syncthreads();
-        for (int e = tid; e < kTile * 27; e += kFastThreads) {
-            const int t = e / 27, k = e - 27 * (e / 27);
+        // a row's stencil as nine x-lines of (up to) three adjacent cells:
+        // consecutive bits of one box row
+        for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
+            const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
             if (r0 + t >= n_local) continue;
-            const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
-            int f[3];
-            bool in = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                f[a] = sh.rh[a][t] + o[a];
-                if (!per[a]) in = in && c0[a] + f[a] >= 0 && c0[a] + f[a] < bins[a];
+            const int fy = sh.rh[1][t] + rr % 3 - 1, fz = sh.rh[2][t] + rr / 3 - 1;
+            if (!per[1] && (c0[1] + fy < 0 || c0[1] + fy >= bins[1])) continue;
+            if (!per[2] && (c0[2] + fz < 0 || c0[2] + fz >= bins[2])) continue;
+            int xa = sh.rh[0][t] - 1, xb = sh.rh[0][t] + 1;
+            if (!per[0]) {
+                xa = c0[0] + xa >= 0 ? xa : -c0[0];
+                xb = c0[0] + xb < bins[0] ? xb : bins[0] - 1 - c0[0];
             }
-            if (!in) continue;
-            const int b = ((f[2] - blo[2]) * X[1] + (f[1] - blo[1])) * X[0] + (f[0] - blo[0]);
-            atomicOr(&sh.box[b >> 5], 1u << (b & 31));
+            const int b = ((fz - blo[2]) * X[1] + (fy - blo[1])) * X[0] + (xa - blo[0]);
+            const uint64_t bits = ((1ull << (xb - xa + 1)) - 1ull) << (b & 31);
+            atomicOr(&sh.box[b >> 5], (uint32_t)bits);
+            if (bits >> 32) atomicOr(&sh.box[(b >> 5) + 1], (uint32_t)(bits >> 32));
         }
         __syncthreads();
         // ---- 3. distinct cells (box order) and their members ----------------------
@@ -908,16 +911,14 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
             continue;
         }
-        for (int q = tid; q < nbw; q += kFastThreads) {
-            uint32_t word = sh.box[q];
-            int u = sh.bpre[q];
-            while (word) {
-                const int bit = __ffs(word) - 1;
-                sh.ucell[u++] = q * 32 + bit;
-                word &= word - 1u;
-            }
+        for (int b = tid; b < vol; b += kFastThreads) {
+            const uint32_t word = sh.box[b >> 5];
+            if ((word >> (b & 31)) & 1u) sh.ucell[sh.bpre[b >> 5] + __popc(word & ((1u << (b & 31)) - 1u))] = b;
         }
         __syncthreads();
+        // the cell sizes are read by the loader wave, which has no stores of
+        // the previous tile in flight (a wave's wait for a read also waits for
+        // its own earlier stores)
         for (int u = loader ? tr : nu; u < nu; u += kWave) {
             const int b = sh.ucell[u];
             const int f[3] = {b % X[0] + blo[0], (b / X[0]) % X[1] + blo[1], b / (X[0] * X[1]) + blo[2]};
@@ -1018,18 +1019,17 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             {
                 constexpr int kB = 2;
                 for (int qb = q0 + tid; qb < q1; qb += kB * kFastThreads) {
-                    int us[kB];
+                    int us[kB], qs[kB];
                     float4 cs[kB];
 #pragma unroll
                     for (int k = 0; k < kB; ++k) {
                         const int q = qb + k * kFastThreads;
+                        qs[k] = q;
                         us[k] = q < q1 ? (int)sh.smap[q - q0] : 0;
                     }
 #pragma unroll
-                    for (int k = 0; k < kB; ++k) {
-                        const int q = qb + k * kFastThreads;
-                        if (q < q1) cs[k] = cell_xf[(int64_t)sh.ucell[us[k]] * cell_cap + (q - sh.ustart[us[k]])];
-                    }
+                    for (int k = 0; k < kB; ++k)
+                        if (qs[k] < q1) cs[k] = cell_xf[(int64_t)sh.ucell[us[k]] * cell_cap + (qs[k] - sh.ustart[us[k]])];
 #pragma unroll
                     for (int k = 0; k < kB; ++k) {
                         const int q = qb + k * kFastThreads;
