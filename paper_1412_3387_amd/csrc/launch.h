@@ -42,6 +42,7 @@ struct LaunchCtx {
     int32_t *rtag;                 // row of each tag (per system offset row0)
     bool has_bonds;
     int32_t *slow_list;            // tiles the framed build passes on to the general one
+    char *plan;                    // per-tile plans of the framed build (build_plan_bytes)
     int32_t *slow_n;               // their number (cleared by the binning launch)
     int32_t *rare_list;            // tiles the force pass handles in its second launch
     int32_t *rare_n;               // their number (cleared by the binning launch)
@@ -84,6 +85,7 @@ size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
 int force_row_over_read();
 int force_halo_entry_bytes(int pair);
 size_t fast_build_lds_bytes(int nlist_cap);
+size_t build_plan_bytes(int64_t tiles);
 hipError_t prepare_nlist(int nlist_cap);
 
 }  // namespace md

@@ -40,6 +40,7 @@ constexpr int kBuildW = 8;
 constexpr int kChunk = 2048;         // members staged at once
 constexpr int kSlotMax = 16384;      // members of a tile's stencil cells
 constexpr int kRebuildGrid = 2048;   // blocks of the grid-stride rebuild kernels
+constexpr int kPlanGrid = 8192;      // one-wave workgroups of the plan kernel
 constexpr int kKeys = 2048;          // 64 rows x 27 stencil cells, padded
 constexpr int kKpt = kKeys / kBuildThreads;  // stencil keys per thread
 static_assert(kKeys % kBuildThreads == 0 && kKeys <= 8 * kBuildThreads, "key split");
@@ -733,25 +734,318 @@ __device__ __forceinline__ int wave_max_full(int v)
 
 struct FastShared {
     float4 cp[kFastChunk];               // member position in the frame (FP32), row in w
-    uint32_t box[kBoxWords];             // stencil cells in the frame box
-    int32_t bpre[kBoxWords + 1];         // set bits before each box word
-    int32_t ucell[kUMax];                // box bit, then cell index, of each distinct cell
+    int32_t ucell[kUMax];                // cell index of each distinct cell
     float4 uoff[kUMax];                  // frame position of each distinct cell's corner (FP32)
     int32_t ustart[kUMax + 1];           // first slot of each distinct cell
     uint32_t used[kFastSlotMax / 32];
     int32_t wpre[kFastSlotMax / 32 + 1];
     uint32_t run[kTile][kRuns];          // slot range of each row line: lo | hi << 16
+    float hw[kTile][kRuns];              // half width in x of each row line
     float4 xrow[kTile];                  // row position in the frame (FP32)
-    float frel[3][kTile];                // row offset inside its home cell
-    int16_t rh[3][kTile];                // row home cell in the frame
     int32_t rown[kTile];                 // hits of each row so far
+    uint64_t lmask[kTile];               // per row: bit of the last lane of each line but the last
+    uint8_t lb[kTile][kRuns + 1];        // per row: first lane of each line, then 64
     int32_t scan[kFastWaves];            // per-wave totals of the block scans
     uint8_t smap[kFastChunk];            // distinct cell of each slot of the chunk
     double xref[3];                      // first row's position: the frame reference
-    double xd[3][kTile];                 // row positions (FP64), for the build position
-    int32_t ext[6];
-    int32_t info[4];                     // pass-on flag, per-pair image flag, longest row
+    int32_t info[4];                     // distinct cells, per-pair image flag, longest row, slots
 };
+
+// Per-tile plan of the framed build, written by k_build_plan and read by
+// k_build_fast: a header {distinct cells (-1: passed on), slots, per-pair
+// image flag, 0}, then per distinct cell {cell, first slot} and its corner
+// in the frame, per row its frame position, and per row line its slot range
+// and the half width in x that its y-z distance leaves.
+struct PlanPtrs {
+    int4 *hdr;
+    int2 *cell;
+    float4 *off;
+    float4 *xrow;
+    uint32_t *run;
+    float *hw;
+};
+
+__host__ __device__ inline PlanPtrs plan_ptrs(char *base, int64_t tiles)
+{
+    PlanPtrs P;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        char *p = base + off;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    P.hdr = reinterpret_cast<int4 *>(carve(sizeof(int4) * tiles));
+    P.cell = reinterpret_cast<int2 *>(carve(sizeof(int2) * tiles * kUMax));
+    P.off = reinterpret_cast<float4 *>(carve(sizeof(float4) * tiles * kUMax));
+    P.xrow = reinterpret_cast<float4 *>(carve(sizeof(float4) * tiles * kTile));
+    P.run = reinterpret_cast<uint32_t *>(carve(sizeof(uint32_t) * tiles * kTile * kRuns));
+    P.hw = reinterpret_cast<float *>(carve(sizeof(float) * tiles * kTile * kRuns));
+    return P;
+}
+
+// Exclusive scan in place of a[0..n), n <= 4 * 64, by one fully active
+// wave; returns the total.
+__device__ __forceinline__ int wave_scan_excl(int32_t *a, int n)
+{
+    const int lane = lane_id();
+    int v[4];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = lane * 4 + k;
+        v[k] = i < n ? a[i] : 0;
+        sum += v[k];
+    }
+    int inc = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+    }
+    const int total = __shfl(inc, kWave - 1, kWave);
+    int run = inc - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = lane * 4 + k;
+        if (i < n) a[i] = run;
+        run += v[k];
+    }
+    return total;
+}
+static_assert(kBoxWords <= 4 * kWave && kUMax <= 4 * kWave, "one-wave scans of the plan");
+
+// The plan of one tile per wave (workgroups of one wave: no block barriers
+// wait on other waves, so many tiles are in flight per CU).  Lane t takes
+// row t: its home cell in the frame (cell coordinates relative to the first
+// row's cell, unwrapped across periodic faces with the cut opposite the first
+// row or through it, whichever gives the shorter extent), its nine x-lines of
+// three cells marked in a bitmap over the frame's box, the distinct cells in
+// box order with their sizes and first slots, and every line cut to the cells
+// within r_list.  The rows' build positions are written here.  Tiles that do
+// not fit (a frame wider than a periodic box, fewer than three cells on a
+// periodic axis, too many distinct cells or members) go to the general build.
+__global__ __launch_bounds__(kWave) void k_build_plan(
+    const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
+    const double4 *__restrict__ pos, const int32_t *__restrict__ cell_size, int cell_cap,
+    double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n,
+    PlanPtrs plan, const int32_t *__restrict__ flag)
+{
+    if (*flag == 0) return;
+    __shared__ uint32_t box[kBoxWords];
+    __shared__ int32_t bpre[kBoxWords + 1];
+    __shared__ int32_t ucell[kUMax];
+    __shared__ int32_t ustart[kUMax + 1];
+    const int lane = lane_id();
+    int64_t tfirst, tend;
+    int tstep;
+    die_range(blockIdx.x, gridDim.x, tiles, tfirst, tend, tstep);
+    for (int tile = (int)tfirst; tile < tend; tile += tstep) {
+        const int s = find_sys(tprefix, n_sys, tile);
+        const SysDev &S = sys[s];
+        const double Ls[3] = {S.L[0], S.L[1], S.L[2]};
+        const int bins[3] = {S.bins[0], S.bins[1], S.bins[2]};
+        const int per[3] = {S.per[0], S.per[1], S.per[2]};
+        const int64_t row0 = S.row0, cell0 = S.cell0;
+        const int n_local = S.n_local;
+        const double rl2 = S.rl2;
+        const int r0 = (tile - S.tile0) * kTile;
+        const float cw[3] = {(float)(Ls[0] / bins[0]), (float)(Ls[1] / bins[1]), (float)(Ls[2] / bins[2])};
+        auto pass_on = [&]() {
+            if (lane == 0) {
+                slow_list[atomicAdd(slow_n, 1)] = tile;
+                plan.hdr[tile] = make_int4(-1, 0, 0, 0);
+            }
+        };
+
+        // ---- rows: home cell in the frame, frame position, build position ----
+        const int r = r0 + lane;
+        const bool act = r < n_local;
+        const double4 xi = pos[row0 + (act ? r : r0)];
+        if (act) xbuild[row0 + r] = make_double4(xi.x, xi.y, xi.z, 0.0);
+        const double xr[3] = {uni(xi.x), uni(xi.y), uni(xi.z)};  // row 0 of the tile
+        const double xa[3] = {xi.x, xi.y, xi.z};
+        int c0[3], h[3], elo[3], ehi[3];
+        float xf[3], frel[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            c0[a] = uni(cell_coord(xr[a], S.lo[a], S.scale[a], bins[a]));
+            const int ci = cell_coord(xa[a], S.lo[a], S.scale[a], bins[a]);
+            const int d = ci - c0[a];
+            const int sft = bins[a] / 2;
+            const int hc[2] = {per[a] ? wrap_rel(d, bins[a]) : d, per[a] ? sft + wrap_rel(d - sft, bins[a]) : d};
+            int mn[2], mx[2];
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                mn[v] = wave_min_full(act ? hc[v] : INT32_MAX);
+                mx[v] = wave_max_full(act ? hc[v] : INT32_MIN);
+            }
+            const int pick = mx[1] - mn[1] < mx[0] - mn[0] ? 1 : 0;
+            h[a] = hc[pick];
+            elo[a] = pick ? mn[1] : mn[0];
+            ehi[a] = pick ? mx[1] : mx[0];
+            // image of the row in the frame: the home cell at c0 + h
+            const int kimg = per[a] ? (c0[a] + h[a] - ci) / bins[a] : 0;
+            xf[a] = (float)((xa[a] + (double)kimg * Ls[a]) - xr[a]);
+            frel[a] = (float)(xa[a] - S.lo[a]) - (float)ci * cw[a];
+        }
+        plan.xrow[(int64_t)tile * kTile + lane] = make_float4(xf[0], xf[1], xf[2], 0.f);
+
+        // ---- frame box and the stencil-cell bitmap ----------------------------
+        int blo[3], X[3];
+        bool pass = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int lo_ = elo[a] - 1, hi_ = ehi[a] + 1;
+            if (!per[a]) {
+                lo_ = lo_ > -c0[a] ? lo_ : -c0[a];
+                hi_ = hi_ < bins[a] - 1 - c0[a] ? hi_ : bins[a] - 1 - c0[a];
+            } else if (bins[a] < 3 || hi_ - lo_ + 1 > bins[a]) {
+                pass = true;
+            }
+            blo[a] = lo_;
+            X[a] = hi_ - lo_ + 1;
+            if ((double)X[a] * (double)cw[a] > 512.0 * sqrt(rl2)) pass = true;
+        }
+        const int vol = X[0] * X[1] * X[2];
+        if (pass || vol > kBoxMax) {
+            pass_on();
+            continue;
+        }
+        const int nbw = (vol + 31) >> 5;
+        __syncthreads();  // LDS of the previous tile no longer read
+        for (int q = lane; q < nbw; q += kWave) box[q] = 0u;
+        __syncthreads();
+        // a row's stencil as nine x-lines of (up to) three adjacent cells:
+        // consecutive bits of one box row
+        if (act) {
+            for (int rr = 0; rr < kRuns; ++rr) {
+                const int fy = h[1] + rr % 3 - 1, fz = h[2] + rr / 3 - 1;
+                if (!per[1] && (c0[1] + fy < 0 || c0[1] + fy >= bins[1])) continue;
+                if (!per[2] && (c0[2] + fz < 0 || c0[2] + fz >= bins[2])) continue;
+                int xa_ = h[0] - 1, xb_ = h[0] + 1;
+                if (!per[0]) {
+                    xa_ = c0[0] + xa_ >= 0 ? xa_ : -c0[0];
+                    xb_ = c0[0] + xb_ < bins[0] ? xb_ : bins[0] - 1 - c0[0];
+                }
+                const int b = ((fz - blo[2]) * X[1] + (fy - blo[1])) * X[0] + (xa_ - blo[0]);
+                const uint64_t bits = ((1ull << (xb_ - xa_ + 1)) - 1ull) << (b & 31);
+                atomicOr(&box[b >> 5], (uint32_t)bits);
+                if (bits >> 32) atomicOr(&box[(b >> 5) + 1], (uint32_t)(bits >> 32));
+            }
+        }
+        __syncthreads();
+
+        // ---- distinct cells (box order), sizes, first slots ----------------------
+        for (int q = lane; q < nbw; q += kWave) bpre[q] = __popc(box[q]);
+        __syncthreads();
+        const int nu = uni(wave_scan_excl(bpre, nbw));
+        __syncthreads();
+        if (nu > kUMax || nu < 1) {
+            pass_on();
+            continue;
+        }
+        for (int b = lane; b < vol; b += kWave) {
+            const uint32_t word = box[b >> 5];
+            if ((word >> (b & 31)) & 1u) ucell[bpre[b >> 5] + __popc(word & ((1u << (b & 31)) - 1u))] = b;
+        }
+        __syncthreads();
+        // four distinct cells per lane; every lane reads a valid cell (the
+        // last one again past the end) so that the reads are in flight together
+        int cells[4];
+        float4 offs[4];
+        int sizes[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int u = lane + k * kWave;
+            const int b = ucell[u < nu ? u : nu - 1];
+            const int f[3] = {b % X[0] + blo[0], (b / X[0]) % X[1] + blo[1], b / (X[0] * X[1]) + blo[2]};
+            int pc[3];
+            float off[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                pc[a] = c0[a] + f[a];
+                const int ki = pc[a] >= bins[a] ? 1 : (pc[a] < 0 ? -1 : 0);
+                pc[a] -= ki * bins[a];
+                // the cell's lower corner in the frame, relative to the reference
+                off[a] = (float)((S.lo[a] + (double)pc[a] * (Ls[a] / bins[a]) + (double)ki * Ls[a]) - xr[a]);
+            }
+            cells[k] = (int32_t)(cell0 + ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0]);
+            offs[k] = make_float4(off[0], off[1], off[2], 0.f);
+            sizes[k] = cell_size[cells[k]];
+        }
+        __syncthreads();  // ucell no longer read
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int u = lane + k * kWave;
+            if (u < nu) ustart[u] = sizes[k] < cell_cap ? sizes[k] : cell_cap;
+        }
+        __syncthreads();
+        const int nslot = uni(wave_scan_excl(ustart, nu));
+        if (lane == 0) ustart[nu] = nslot;
+        __syncthreads();
+        if (nslot > kFastSlotMax) {
+            pass_on();
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int u = lane + k * kWave;
+            if (u < nu) {
+                plan.cell[(int64_t)tile * kUMax + u] = make_int2(cells[k], ustart[u]);
+                plan.off[(int64_t)tile * kUMax + u] = offs[k];
+            }
+        }
+
+        // ---- every row line cut to the cells within r_list; x half widths -----
+        const float rl2f = (float)rl2 * 1.0001f + 1e-3f;
+        float fext = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fext = fmaxf(fext, (float)X[a] * cw[a]);
+        // bound on the FP32 error of a frame x difference, with room to spare
+        const float xmargin = 1e-3f + fext * 0x1p-18f;
+        const int64_t pr = ((int64_t)tile * kTile + lane) * kRuns;
+        for (int rr = 0; rr < kRuns; ++rr) {
+            uint32_t v = 0u;
+            float hwv = 0.f;
+            if (act) {
+                const int dy = rr % 3 - 1, dz = rr / 3 - 1;
+                const int hx = h[0], hy = h[1] + dy, hz = h[2] + dz;
+                bool in = (per[1] || (c0[1] + hy >= 0 && c0[1] + hy < bins[1])) &&
+                          (per[2] || (c0[2] + hz >= 0 && c0[2] + hz < bins[2]));
+                // squared distance in y and z from the row to the line's cells
+                // (a lower bound for every member of the line)
+                float gyz = 0.f;
+                if (dy != 0) {
+                    const float gg = dy < 0 ? frel[1] : cw[1] - frel[1];
+                    gyz += gg > 0.f ? gg * gg : 0.f;
+                }
+                if (dz != 0) {
+                    const float gg = dz < 0 ? frel[2] : cw[2] - frel[2];
+                    gyz += gg > 0.f ? gg * gg : 0.f;
+                }
+                in = in && gyz <= rl2f;
+                if (in) {
+                    const float fx = frel[0];
+                    const float gl = fx > 0.f ? fx : 0.f, gr = cw[0] - fx > 0.f ? cw[0] - fx : 0.f;
+                    const bool left = (per[0] || c0[0] + hx - 1 >= 0) && gl * gl + gyz <= rl2f;
+                    const bool right = (per[0] || c0[0] + hx + 1 < bins[0]) && gr * gr + gyz <= rl2f;
+                    const int xa_ = hx + (left ? -1 : 0), xb_ = hx + (right ? 1 : 0);
+                    const int b = ((hz - blo[2]) * X[1] + (hy - blo[1])) * X[0] + (xa_ - blo[0]);
+                    const int u0 = bpre[b >> 5] + __popc(box[b >> 5] & ((1u << (b & 31)) - 1u));
+                    const int u1 = u0 + (xb_ - xa_);
+                    v = (uint32_t)ustart[u0] | ((uint32_t)ustart[u1 + 1] << 16);
+                    hwv = sqrtf(fmaxf(rl2f - gyz, 0.f)) + xmargin;
+                }
+            }
+            plan.run[pr + rr] = v;
+            plan.hw[pr + rr] = hwv;
+        }
+        int pp = 0;
+        for (int a = 0; a < 3; ++a)
+            if (per[a] && (double)(ehi[a] - elo[a] + 3) * (Ls[a] / bins[a]) >= 0.5 * Ls[a]) pp = 1;
+        if (lane == 0) plan.hdr[tile] = make_int4(nu, nslot, pp, 0);
+    }
+}
 
 template <bool EXCL>
 __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_build_fast(
@@ -760,8 +1054,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
     const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx,
     const float4 *__restrict__ cell_xf, int cell_cap,
     uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int rstride,
-    int32_t *__restrict__ halo, int32_t *__restrict__ halo_n, int halo_cap,
-    double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n,
+    int32_t *__restrict__ halo, int32_t *__restrict__ halo_n, int halo_cap, PlanPtrs plan,
     int halo_lds, int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n,
     const int32_t *__restrict__ flag, int32_t *build_count, Status *st)
 {
@@ -784,222 +1077,81 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         const double iL[3] = {S.invL[0], S.invL[1], S.invL[2]};
         const int bins[3] = {S.bins[0], S.bins[1], S.bins[2]};
         const int per[3] = {S.per[0], S.per[1], S.per[2]};
-        const int64_t row0 = S.row0, cell0 = S.cell0, nl0 = S.nl0;
+        const int64_t row0 = S.row0, nl0 = S.nl0;
         const int n_local = S.n_local;
         const double rl2 = S.rl2;
         const int r0 = (tile - S.tile0) * kTile;
-        const float cw[3] = {(float)(Ls[0] / bins[0]), (float)(Ls[1] / bins[1]), (float)(Ls[2] / bins[2])};
 
         __syncthreads();  // LDS of the previous tile no longer read
-        // ---- 1. rows: home cell in the frame, frame position ------------------
-        // Wave 1 does this tile's global reads of rows and cell sizes and no
-        // global writes: a wave's wait for a read also waits for all of its
-        // earlier writes, and the other waves still have the previous
-        // tile's rows in flight.  The first row's position (the frame
-        // reference) is shared through LDS.
+        // ---- 1. the tile's plan ------------------------------------------------
+        // Wave 1 does this tile's global reads and no global writes: a wave's
+        // wait for a read also waits for all of its earlier writes, and the
+        // other waves still have the previous tile's rows in flight.
         const bool loader = wv == 1;
-        const int tr = tid - kWave;  // row slot of a loader lane
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        bool act = false;
+        const int tr = tid - kWave;  // lane of the loader wave
         if (loader) {
-            const int r = r0 + tr;
-            act = r < n_local;
-            xi = pos[row0 + (act ? r : r0)];
-            sh.xd[0][tr] = xi.x;
-            sh.xd[1][tr] = xi.y;
-            sh.xd[2][tr] = xi.z;
+            const int4 hd = plan.hdr[tile];
             if (tr == 0) {
-                sh.xref[0] = xi.x;
-                sh.xref[1] = xi.y;
-                sh.xref[2] = xi.z;
+                sh.info[0] = hd.x;
+                sh.info[1] = hd.z;
+                sh.info[3] = hd.y;
             }
-        } else if (tid == 0) {
-            sh.info[0] = 0;
-        }
-        __syncthreads();
-        const double xr[3] = {uni(sh.xref[0]), uni(sh.xref[1]), uni(sh.xref[2])};
-        int c0[3];
+            if (hd.x > 0) {
+                const int nu_ = hd.x < kUMax ? hd.x : kUMax;
+                const int64_t pu = (int64_t)tile * kUMax, pr = (int64_t)tile * kTile * kRuns;
+                // every read issued before the first is used: cells past the
+                // end read the last one again
+                int2 cs[kUMax / kWave];
+                float4 os[kUMax / kWave];
+                uint32_t rv[kRuns];
+                float hv[kRuns];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) c0[a] = uni(cell_coord(xr[a], S.lo[a], S.scale[a], bins[a]));
-        if (loader) {
-            const double xa[3] = {xi.x, xi.y, xi.z};
-            float xf[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int ci = cell_coord(xa[a], S.lo[a], S.scale[a], bins[a]);
-                // home cell relative to the first row's, unwrapped with the cut
-                // either opposite the first row or through it, whichever gives
-                // the tile the shorter extent (a tile whose rows straddle the
-                // cell opposite the first row's is compact only with the cut
-                // through the first row); extents by wave reductions (lane 0
-                // of the tile is always a row)
-                const int d = ci - c0[a];
-                const int sft = bins[a] / 2;
-                int hc[2] = {per[a] ? wrap_rel(d, bins[a]) : d, per[a] ? sft + wrap_rel(d - sft, bins[a]) : d};
-                int mn[2], mx[2];
-#pragma unroll
-                for (int v = 0; v < 2; ++v) {
-                    mn[v] = wave_min_full(act ? hc[v] : INT32_MAX);
-                    mx[v] = wave_max_full(act ? hc[v] : INT32_MIN);
+                for (int k = 0; k < kUMax / kWave; ++k) {
+                    const int u = tr + k * kWave;
+                    cs[k] = plan.cell[pu + (u < nu_ ? u : nu_ - 1)];
+                    os[k] = plan.off[pu + (u < nu_ ? u : nu_ - 1)];
                 }
-                const int pick = mx[1] - mn[1] < mx[0] - mn[0] ? 1 : 0;
-                const int h = hc[pick];
-                // image of the row in the frame: the home cell at c0 + h
-                const int kimg = per[a] ? (c0[a] + h - ci) / bins[a] : 0;
-                xf[a] = (float)((xa[a] + (double)kimg * Ls[a]) - xr[a]);
-                sh.rh[a][tr] = (int16_t)h;
-                sh.frel[a][tr] = (float)(xa[a] - S.lo[a]) - (float)ci * cw[a];
+#pragma unroll
+                for (int k = 0; k < kRuns; ++k) {
+                    rv[k] = plan.run[pr + tr + k * kWave];
+                    hv[k] = plan.hw[pr + tr + k * kWave];
+                }
+                const float4 xw = plan.xrow[(int64_t)tile * kTile + tr];
+                const double4 x0 = pos[row0 + r0];
+#pragma unroll
+                for (int k = 0; k < kUMax / kWave; ++k) {
+                    const int u = tr + k * kWave;
+                    if (u < nu_) {
+                        sh.ucell[u] = cs[k].x;
+                        sh.ustart[u] = cs[k].y;
+                        sh.uoff[u] = os[k];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kRuns; ++k) {
+                    const int e = tr + k * kWave;
+                    sh.run[e / kRuns][e % kRuns] = rv[k];
+                    sh.hw[e / kRuns][e % kRuns] = hv[k];
+                }
+                sh.xrow[tr] = xw;
                 if (tr == 0) {
-                    sh.ext[a] = mn[pick];
-                    sh.ext[3 + a] = mx[pick];
+                    sh.ustart[nu_] = hd.y;
+                    sh.xref[0] = x0.x;
+                    sh.xref[1] = x0.y;
+                    sh.xref[2] = x0.z;
                 }
             }
-            sh.xrow[tr] = make_float4(xf[0], xf[1], xf[2], 0.f);
-            sh.rown[tr] = act ? 0 : -1;
+        } else if (wv == 0) {
+            sh.rown[tid] = r0 + tid < n_local ? 0 : -1;
         }
         __syncthreads();
-        // ---- 2. frame box and the stencil-cell bitmap ---------------------------
-        int blo[3], X[3];
-        bool pass = false;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            int lo_ = uni(sh.ext[a]) - 1, hi_ = uni(sh.ext[3 + a]) + 1;
-            if (!per[a]) {
-                lo_ = lo_ > -c0[a] ? lo_ : -c0[a];
-                hi_ = hi_ < bins[a] - 1 - c0[a] ? hi_ : bins[a] - 1 - c0[a];
-            } else if (bins[a] < 3 || hi_ - lo_ + 1 > bins[a]) {
-                pass = true;
-            }
-            blo[a] = lo_;
-            X[a] = hi_ - lo_ + 1;
-            if ((double)X[a] * (double)cw[a] > 512.0 * sqrt(rl2)) pass = true;
-        }
-        const int vol = X[0] * X[1] * X[2];
-        if (vol > kBoxMax) pass = true;
-        if (pass) {
-            if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
-            continue;
-        }
-        const int nbw = (vol + 31) >> 5;
-        for (int q = tid; q < nbw; q += kFastThreads) sh.box[q] = 0u;
-        __syncthreads();
-        // a row's stencil as nine x-lines of (up to) three adjacent cells:
-        // consecutive bits of one box row
-        for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
-            const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
-            if (r0 + t >= n_local) continue;
-            const int fy = sh.rh[1][t] + rr % 3 - 1, fz = sh.rh[2][t] + rr / 3 - 1;
-            if (!per[1] && (c0[1] + fy < 0 || c0[1] + fy >= bins[1])) continue;
-            if (!per[2] && (c0[2] + fz < 0 || c0[2] + fz >= bins[2])) continue;
-            int xa = sh.rh[0][t] - 1, xb = sh.rh[0][t] + 1;
-            if (!per[0]) {
-                xa = c0[0] + xa >= 0 ? xa : -c0[0];
-                xb = c0[0] + xb < bins[0] ? xb : bins[0] - 1 - c0[0];
-            }
-            const int b = ((fz - blo[2]) * X[1] + (fy - blo[1])) * X[0] + (xa - blo[0]);
-            const uint64_t bits = ((1ull << (xb - xa + 1)) - 1ull) << (b & 31);
-            atomicOr(&sh.box[b >> 5], (uint32_t)bits);
-            if (bits >> 32) atomicOr(&sh.box[(b >> 5) + 1], (uint32_t)(bits >> 32));
-        }
-        __syncthreads();
-        // ---- 3. distinct cells (box order) and their members ----------------------
-        for (int q = tid; q < nbw; q += kFastThreads) sh.bpre[q] = __popc(sh.box[q]);
-        __syncthreads();
-        const int nu = uni(block_scan_w<kFastThreads>(sh.bpre, nbw, sh.scan));
-        if (tid == 0) sh.bpre[nbw] = nu;
-        if (nu > kUMax) {
-            if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
-            continue;
-        }
-        for (int b = tid; b < vol; b += kFastThreads) {
-            const uint32_t word = sh.box[b >> 5];
-            if ((word >> (b & 31)) & 1u) sh.ucell[sh.bpre[b >> 5] + __popc(word & ((1u << (b & 31)) - 1u))] = b;
-        }
-        __syncthreads();
-        // the cell sizes are read by the loader wave, which has no stores of
-        // the previous tile in flight (a wave's wait for a read also waits for
-        // its own earlier stores)
-        for (int u = loader ? tr : nu; u < nu; u += kWave) {
-            const int b = sh.ucell[u];
-            const int f[3] = {b % X[0] + blo[0], (b / X[0]) % X[1] + blo[1], b / (X[0] * X[1]) + blo[2]};
-            int pc[3];
-            float off[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                pc[a] = c0[a] + f[a];
-                const int ki = pc[a] >= bins[a] ? 1 : (pc[a] < 0 ? -1 : 0);
-                pc[a] -= ki * bins[a];
-                // the cell's lower corner in the frame, relative to the reference
-                off[a] = (float)((S.lo[a] + (double)pc[a] * (Ls[a] / bins[a]) + (double)ki * Ls[a]) - xr[a]);
-            }
-            const int32_t cell = (int32_t)(cell0 + ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0]);
-            const int m = cell_size[cell];
-            sh.ustart[u] = m < cell_cap ? m : cell_cap;
-            sh.ucell[u] = cell;
-            sh.uoff[u] = make_float4(off[0], off[1], off[2], 0.f);
-        }
-        __syncthreads();
-        const int nslot = uni(block_scan_w<kFastThreads>(sh.ustart, nu, sh.scan));
-        if (tid == 0) {
-            sh.ustart[nu] = nslot;
-            int pp = 0;
-            for (int a = 0; a < 3; ++a)
-                if (per[a] && (double)(sh.ext[3 + a] - sh.ext[a] + 3) * (Ls[a] / bins[a]) >= 0.5 * Ls[a]) pp = 1;
-            sh.info[1] = pp;
-        }
-        if (nslot > kFastSlotMax) {
-            if (tid == 0) slow_list[atomicAdd(slow_n, 1)] = tile;
-            continue;
-        }
+        const int nu = uni(sh.info[0]);
+        const int nslot = uni(sh.info[3]);
+        if (nu <= 0 || nu > kUMax || nslot > kFastSlotMax) continue;  // built by the general kernel
+        const double xr[3] = {uni(sh.xref[0]), uni(sh.xref[1]), uni(sh.xref[2])};
         for (int q = tid; q < (nslot + 31) / 32; q += kFastThreads) sh.used[q] = 0u;
-        __syncthreads();
-        // ---- 4. the nine lines of every row, cut to cells within r_list -------------
-        const float rl2f = (float)rl2 * 1.0001f + 1e-3f;
-        // squared distance in y and z from row t to the cells of its line rr
-        // (a lower bound for every member of the line)
-        auto line_gap2 = [&](int t, int dy, int dz) -> float {
-            float gyz = 0.f;
-            if (dy != 0) {
-                const float gg = dy < 0 ? sh.frel[1][t] : cw[1] - sh.frel[1][t];
-                gyz += gg > 0.f ? gg * gg : 0.f;
-            }
-            if (dz != 0) {
-                const float gg = dz < 0 ? sh.frel[2][t] : cw[2] - sh.frel[2][t];
-                gyz += gg > 0.f ? gg * gg : 0.f;
-            }
-            return gyz;
-        };
-        for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
-            const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
-            uint32_t v = 0u;
-            if (r0 + t < n_local) {
-                const int dy = rr % 3 - 1, dz = rr / 3 - 1;
-                const int hx = sh.rh[0][t], hy = sh.rh[1][t] + dy, hz = sh.rh[2][t] + dz;
-                bool in = (per[1] || (c0[1] + hy >= 0 && c0[1] + hy < bins[1])) &&
-                          (per[2] || (c0[2] + hz >= 0 && c0[2] + hz < bins[2]));
-                const float gyz = line_gap2(t, dy, dz);
-                in = in && gyz <= rl2f;
-                if (in) {
-                    const float fx = sh.frel[0][t];
-                    const float gl = fx > 0.f ? fx : 0.f, gr = cw[0] - fx > 0.f ? cw[0] - fx : 0.f;
-                    const bool left = (per[0] || c0[0] + hx - 1 >= 0) && gl * gl + gyz <= rl2f;
-                    const bool right = (per[0] || c0[0] + hx + 1 < bins[0]) && gr * gr + gyz <= rl2f;
-                    const int xa = hx + (left ? -1 : 0), xb = hx + (right ? 1 : 0);
-                    const int b = ((hz - blo[2]) * X[1] + (hy - blo[1])) * X[0] + (xa - blo[0]);
-                    const int u0 = sh.bpre[b >> 5] + __popc(sh.box[b >> 5] & ((1u << (b & 31)) - 1u));
-                    const int u1 = u0 + (xb - xa);
-                    v = (uint32_t)sh.ustart[u0] | ((uint32_t)sh.ustart[u1 + 1] << 16);
-                }
-            }
-            sh.run[t][rr] = v;
-        }
         // ---- 5. stage members a chunk at a time, scan every row's lines -------------
         const bool one_chunk = nslot <= kFastChunk;
-        float fext = 0.f;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) fext = fmaxf(fext, (float)X[a] * cw[a]);
-        // bound on the FP32 error of a frame x difference, with room to spare
-        const float xmargin = 1e-3f + fext * 0x1p-18f;
         const float lo_f = (float)rl2 * (1.0f - kBand), hi_f = (float)rl2 * (1.0f + kBand);
         for (int q0 = 0; q0 < nslot; q0 += kFastChunk) {
             const int q1 = q0 + kFastChunk < nslot ? q0 + kFastChunk : nslot;
@@ -1044,15 +1196,14 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             if (one_chunk) {
                 // members of a line are ordered by x (cells in x order, each
                 // sorted by x): cut every line to the slots within the half
-                // width that its y-z distance leaves, |dx|^2 <= r_list^2 -
-                // gap^2, widened by a margin for the FP32 frame coordinates
+                // width that its y-z distance leaves (|dx|^2 <= r_list^2 -
+                // gap^2, widened by a margin for the FP32 frame coordinates)
                 for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
                     const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
                     const uint32_t v = sh.run[t][rr];
                     const int a = (int)(v & 0xffffu), b = (int)(v >> 16);
                     if (b <= a) continue;
-                    const float gyz = line_gap2(t, rr % 3 - 1, rr / 3 - 1);
-                    const float hw = sqrtf(fmaxf(rl2f - gyz, 0.f)) + xmargin;
+                    const float hw = sh.hw[t][rr];
                     const float xc = sh.xrow[t].x;
                     const float tlo = xc - hw, thi = xc + hw;
                     // first slot with x >= tlo, first slot with x > thi
@@ -1067,46 +1218,58 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 }
                 __syncthreads();
             }
-            for (int t = wv; t < kTile; t += kFastWaves) {
-                int ntot = uni(sh.rown[t]);
-                if (ntot < 0) continue;  // inactive row
-                // the row's nine lines cut to this chunk; lane r < 9 holds line r
-                int len = 0, ra0 = 0;
-                if (lane < kRuns) {
-                    const uint32_t rv = sh.run[t][lane];
-                    int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
-                    x0_ = x0_ > q0 ? x0_ : q0;
-                    x1_ = x1_ < q1 ? x1_ : q1;
-                    ra0 = x0_;
-                    len = x1_ > x0_ ? x1_ - x0_ : 0;
-                }
-                // lanes to lines: line r takes lanes [B_r, B_r+1) with B_r = r + about
-                // 55 P_r / T (P_r the members before line r, T all of them): every
-                // line keeps at least one lane and longer lines get more.  The line
-                // data are wave-uniform: read lane by lane into scalars.
-                int lens[kRuns], a0s[kRuns];
+            // lanes to lines, one thread per row: line r takes lanes [B_r, B_r+1)
+            // with B_r = r + about 55 P_r / T (P_r the members of the row's lines
+            // before line r in this chunk, T all of them), so every line keeps at
+            // least one lane and longer lines get more.  Kept as the first lanes
+            // and a mask with the last lane of every line but the last.
+            if (tid < kTile) {
+                int lens[kRuns];
                 int tot = 0;
 #pragma unroll
                 for (int r = 0; r < kRuns; ++r) {
-                    lens[r] = __builtin_amdgcn_readlane(len, r);
-                    a0s[r] = __builtin_amdgcn_readlane(ra0, r);
+                    const uint32_t rv = sh.run[tid][r];
+                    int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
+                    x0_ = x0_ > q0 ? x0_ : q0;
+                    x1_ = x1_ < q1 ? x1_ : q1;
+                    lens[r] = x1_ > x0_ ? x1_ - x0_ : 0;
                     tot += lens[r];
                 }
-                if (tot == 0) continue;
-                const uint32_t inv = 65536u / (uint32_t)tot;  // floor(2^16 / T)
-                int base = 0, end = 0, gsz = 1, pre = 0, b0 = 0;
+                const uint32_t inv = tot > 0 ? 65536u / (uint32_t)tot : 0u;  // floor(2^16 / T)
+                uint64_t mask = 0;
+                int pre = 0, b0 = 0;
 #pragma unroll
                 for (int r = 0; r < kRuns; ++r) {
                     const int pn = pre + lens[r];
                     const int b1 = r == kRuns - 1 ? kWave : r + 1 + (int)((55u * (uint32_t)pn * inv) >> 16);
-                    if (lane >= b0 && lane < b1) {
-                        base = a0s[r] + (lane - b0);
-                        end = a0s[r] + lens[r];
-                        gsz = b1 - b0;
-                    }
+                    sh.lb[tid][r] = (uint8_t)b0;
+                    if (r < kRuns - 1) mask |= 1ull << (b1 - 1);
                     b0 = b1;
                     pre = pn;
                 }
+                sh.lb[tid][kRuns] = (uint8_t)kWave;
+                sh.lmask[tid] = tot > 0 ? mask : 0ull;
+                if (tot == 0 && sh.rown[tid] >= 0) sh.lb[tid][0] = 0xFF;  // nothing to scan in this chunk
+            }
+            __syncthreads();
+            for (int t = wv; t < kTile; t += kFastWaves) {
+                int ntot = uni(sh.rown[t]);
+                if (ntot < 0) continue;  // inactive row
+                if (uni((int)sh.lb[t][0]) == 0xFF) continue;  // no members in this chunk
+                // this lane's line: the lines that end before it; its lanes,
+                // members (cut to the chunk) and stride
+                const uint64_t lm = sh.lmask[t];
+                int myline = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(lm >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u));
+                myline = myline < kRuns - 1 ? myline : kRuns - 1;
+                const int blo_ = sh.lb[t][myline], bhi_ = sh.lb[t][myline + 1];
+                const uint32_t rv = sh.run[t][myline];
+                int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
+                x0_ = x0_ > q0 ? x0_ : q0;
+                x1_ = x1_ < q1 ? x1_ : q1;
+                const int gsz = bhi_ - blo_ > 1 ? bhi_ - blo_ : 1;
+                const int base = x0_ + (lane - blo_);
+                const int end = x1_;
                 const float4 xt0 = sh.xrow[t];
                 const float4 xt = make_float4(uni(xt0.x), uni(xt0.y), uni(xt0.z), 0.f);
                 const int32_t it = (int32_t)(row0 + r0 + t);
@@ -1261,7 +1424,6 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         if (act0) {
             const int n = sh.rown[tid];
             nn[i0] = n < cap ? n : cap;
-            xbuild[i0] = make_double4(sh.xd[0][tid], sh.xd[1][tid], sh.xd[2][tid], 0.0);
             if (n > cap) latch(st, 5 /*NLIST_OVERFLOW*/, n);
         }
     }
@@ -1306,6 +1468,16 @@ int nlist_row_stride(int cap)
 
 size_t fast_build_lds_bytes(int cap) { return sizeof(FastShared) + (size_t)kTile * nlist_row_stride(cap) * 2; }
 
+size_t build_plan_bytes(int64_t tiles)
+{
+    // the carving of plan_ptrs, with every part rounded to 256 bytes
+    auto r = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t t = (size_t)(tiles > 0 ? tiles : 1);
+    return r(sizeof(int4) * t) + r(sizeof(int2) * t * kUMax) + r(sizeof(float4) * t * kUMax) +
+           r(sizeof(float4) * t * kTile) + r(sizeof(uint32_t) * t * kTile * kRuns) +
+           r(sizeof(float) * t * kTile * kRuns);
+}
+
 hipError_t prepare_nlist(int cap)
 {
     const int dyn = kTile * nlist_row_stride(cap) * 2;
@@ -1325,12 +1497,15 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
     const int blocks = capped(L.tiles_local);
     const int rs = nlist_row_stride(L.nlist_cap);
     const size_t dyn = (size_t)kTile * rs * 2;
+    const PlanPtrs plan = plan_ptrs(L.plan, L.tiles_local);
+    hipLaunchKernelGGL(k_build_plan, dim3(L.tiles_local < kPlanGrid ? L.tiles_local : kPlanGrid), dim3(kWave), 0,
+                       L.stream, L.sys, L.tprefix_local, L.n_sys, L.tiles_local, pos, L.cell_size, L.cell_cap,
+                       L.xbuild, L.slow_list, L.slow_n, plan, L.flag);
     if (L.has_bonds) {
         hipLaunchKernelGGL(k_build_fast<true>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
-                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
-                           L.build_count, L.status);
+                           L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.flag, L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<true>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
@@ -1340,8 +1515,7 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
         hipLaunchKernelGGL(k_build_fast<false>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
-                           L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
-                           L.build_count, L.status);
+                           L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.flag, L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<false>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,

@@ -34,7 +34,7 @@ struct Layout {
     // byte offsets into the workspace
     size_t sysdev, tpl, tpa, status, flags, thermo, thermo_log, partials;
     size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, cell_xf, halo, halo_n;
-    size_t rtag, partners, slow_list, rare_list, sort_ws, ghost_ws, total;
+    size_t rtag, partners, slow_list, rare_list, plan, sort_ws, ghost_ws, total;
     // sizes
     int64_t rows, tiles_local, tiles_all, n_cells, nlist_entries;
     int cell_cap, nlist_cap, bond_cap, halo_cap, halo_lds;
@@ -243,6 +243,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.partners = take(sizeof(int32_t) * rows * std::max(Lo.bond_cap, 1));
     Lo.slow_list = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
     Lo.rare_list = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
+    Lo.plan = take(build_plan_bytes(tile));
     Lo.sort_ws = take(sort_workspace_bytes((int64_t)rows));
     Lo.ghost_ws = take(ghost_workspace_bytes((int64_t)rows, n_sys));
     Lo.total = off;
@@ -478,6 +479,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.slow_list = ws_ptr<int32_t>(c, lay.slow_list);
     L.slow_n = flag_ptr(c, 6);
     L.rare_list = ws_ptr<int32_t>(c, lay.rare_list);
+    L.plan = ws_ptr<char>(c, lay.plan);
     L.rare_n = flag_ptr(c, 7);
     L.status = ws_ptr<Status>(c, lay.status);
     L.partials = ws_ptr<double>(c, lay.partials);
