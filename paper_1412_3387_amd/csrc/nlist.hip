@@ -115,24 +115,23 @@ __device__ __forceinline__ int find_sys_cell(const SysDev *__restrict__ sys, int
     return lo;
 }
 
-// One wave per cell: members ranked by their FP32 x coordinate relative to
-// the cell's corner, ties by row index (a total order on (bits, row), so the
-// ranks are a permutation whatever the values), sizes published, counters
-// cleared.  Next to each member's row the list keeps its position relative
-// to the cell's lower corner in FP32 (row bits in w), so that the framed
-// build stages a cell with one coalesced read.  cell_cap <= 64 * CPL.
+// One wave per cell (wave w of W takes cells w, w + W, ...): members ranked
+// by their FP32 x coordinate relative to the cell's corner, ties by row index
+// (a total order on (bits, row), so the ranks are a permutation whatever the
+// values), sizes published.  Next to each member's row the list keeps its
+// position relative to the cell's lower corner in FP32 (row bits in w), so
+// that the framed build stages a cell with one coalesced read.  The counts
+// are left for the plan of the framed build, which runs beside this, and
+// cleared by the framed scan.  cell_cap <= 64 * CPL.
 template <int CPL>
-__global__ __launch_bounds__(256) void k_cell_sort(const SysDev *__restrict__ sys, int n_sys,
-                                                   const double4 *__restrict__ pos, int64_t n_cells,
-                                                   int32_t *__restrict__ cell_count,
-                                                   int32_t *__restrict__ cell_size,
-                                                   int32_t *__restrict__ cell_idx, float4 *__restrict__ cell_xf,
-                                                   int cell_cap, const int32_t *__restrict__ flag)
+__device__ __forceinline__ void cell_sort_waves(int64_t wfirst, int64_t wstep, const SysDev *__restrict__ sys,
+                                                int n_sys, const double4 *__restrict__ pos, int64_t n_cells,
+                                                const int32_t *__restrict__ cell_count,
+                                                int32_t *__restrict__ cell_size, int32_t *__restrict__ cell_idx,
+                                                float4 *__restrict__ cell_xf, int cell_cap)
 {
-    if (*flag == 0) return;
     const int lane = lane_id();
-    const int64_t waves = (int64_t)(gridDim.x * blockDim.x) >> 6;
-    for (int64_t c = (int64_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); c < n_cells; c += waves) {
+    for (int64_t c = wfirst; c < n_cells; c += wstep) {
         int m = cell_count[c];
         m = m < cell_cap ? m : cell_cap;
         const SysDev &S = sys[find_sys_cell(sys, n_sys, c)];
@@ -178,10 +177,7 @@ __global__ __launch_bounds__(256) void k_cell_sort(const SysDev *__restrict__ sy
                 cell_xf[c * cell_cap + rank[q]] = f[q];
             }
         }
-        if (lane == 0) {
-            cell_size[c] = m;
-            cell_count[c] = 0;
-        }
+        if (lane == 0) cell_size[c] = m;
     }
 }
 
@@ -751,7 +747,7 @@ struct FastShared {
     int32_t info[4];                     // distinct cells, per-pair image flag, longest row, slots
 };
 
-// Per-tile plan of the framed build, written by k_build_plan and read by
+// Per-tile plan of the framed build, written by k_cells_and_plan and read by
 // k_build_fast: a header {distinct cells (-1: passed on), slots, per-pair
 // image flag, 0}, then per distinct cell {cell, first slot} and its corner
 // in the frame, per row its frame position, and per row line its slot range
@@ -824,21 +820,26 @@ static_assert(kBoxWords <= 4 * kWave && kUMax <= 4 * kWave, "one-wave scans of t
 // within r_list.  The rows' build positions are written here.  Tiles that do
 // not fit (a frame wider than a periodic box, fewer than three cells on a
 // periodic axis, too many distinct cells or members) go to the general build.
-__global__ __launch_bounds__(kWave) void k_build_plan(
-    const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
-    const double4 *__restrict__ pos, const int32_t *__restrict__ cell_size, int cell_cap,
-    double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n,
-    PlanPtrs plan, const int32_t *__restrict__ flag)
+struct PlanShared {
+    uint32_t box[kBoxWords];
+    int32_t bpre[kBoxWords + 1];
+    int32_t ucell[kUMax];
+    int32_t ustart[kUMax + 1];
+};
+
+__device__ __forceinline__ void plan_tiles(
+    PlanShared &ps, int pb, int npb, const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
+    int n_sys, int tiles, const double4 *__restrict__ pos, const int32_t *__restrict__ cell_count, int cell_cap,
+    double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan)
 {
-    if (*flag == 0) return;
-    __shared__ uint32_t box[kBoxWords];
-    __shared__ int32_t bpre[kBoxWords + 1];
-    __shared__ int32_t ucell[kUMax];
-    __shared__ int32_t ustart[kUMax + 1];
+    uint32_t *box = ps.box;
+    int32_t *bpre = ps.bpre;
+    int32_t *ucell = ps.ucell;
+    int32_t *ustart = ps.ustart;
     const int lane = lane_id();
     int64_t tfirst, tend;
     int tstep;
-    die_range(blockIdx.x, gridDim.x, tiles, tfirst, tend, tstep);
+    die_range(pb, npb, tiles, tfirst, tend, tstep);
     for (int tile = (int)tfirst; tile < tend; tile += tstep) {
         const int s = find_sys(tprefix, n_sys, tile);
         const SysDev &S = sys[s];
@@ -971,7 +972,7 @@ __global__ __launch_bounds__(kWave) void k_build_plan(
             }
             cells[k] = (int32_t)(cell0 + ((int64_t)pc[2] * bins[1] + pc[1]) * bins[0] + pc[0]);
             offs[k] = make_float4(off[0], off[1], off[2], 0.f);
-            sizes[k] = cell_size[cells[k]];
+            sizes[k] = cell_count[cells[k]];
         }
         __syncthreads();  // ucell no longer read
 #pragma unroll
@@ -1047,6 +1048,37 @@ __global__ __launch_bounds__(kWave) void k_build_plan(
     }
 }
 
+// The cell sort and the plans of the framed build in one launch of one-wave
+// workgroups: both read only the binning results, so the first n_sort
+// workgroups sort cells while the others plan tiles.
+template <int CPL>
+__global__ __launch_bounds__(kWave) void k_cells_and_plan(
+    int n_sort, const SysDev *__restrict__ sys, int n_sys, const int32_t *__restrict__ tprefix, int tiles,
+    const double4 *__restrict__ pos, int64_t n_cells, const int32_t *__restrict__ cell_count,
+    int32_t *__restrict__ cell_size, int32_t *__restrict__ cell_idx, float4 *__restrict__ cell_xf, int cell_cap,
+    double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan,
+    const int32_t *__restrict__ flag)
+{
+    if (*flag == 0) return;
+    if ((int)blockIdx.x < n_sort) {
+        cell_sort_waves<CPL>(blockIdx.x, n_sort, sys, n_sys, pos, n_cells, cell_count, cell_size, cell_idx, cell_xf,
+                             cell_cap);
+    } else {
+        __shared__ PlanShared ps;
+        plan_tiles(ps, (int)blockIdx.x - n_sort, (int)gridDim.x - n_sort, sys, tprefix, n_sys, tiles, pos,
+                   cell_count, cell_cap, xbuild, slow_list, slow_n, plan);
+    }
+}
+
+// Counts back to zero for the next binning (systems without local tiles,
+// whose builds have no framed scan).
+__global__ void k_zero_counts(int32_t *__restrict__ cell_count, int64_t n_cells, const int32_t *__restrict__ flag)
+{
+    if (*flag == 0) return;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells; c += (int64_t)gridDim.x * blockDim.x)
+        cell_count[c] = 0;
+}
+
 template <bool EXCL>
 __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_build_fast(
     const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
@@ -1056,9 +1088,14 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
     uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int rstride,
     int32_t *__restrict__ halo, int32_t *__restrict__ halo_n, int halo_cap, PlanPtrs plan,
     int halo_lds, int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n,
+    int32_t *__restrict__ cell_count, int64_t n_cells,
     const int32_t *__restrict__ flag, int32_t *build_count, Status *st)
 {
     if (*flag == 0) return;
+    // the binning counts, read by the cell sort and the plans, back to zero
+    // for the next build
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells; c += (int64_t)gridDim.x * blockDim.x)
+        cell_count[c] = 0;
     __shared__ FastShared sh;
     extern __shared__ uint16_t srows[];  // [kTile][rstride]: staged slot of each hit
     const int tid = threadIdx.x;
@@ -1070,6 +1107,9 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
     int64_t tfirst, tend;
     int tstep;
     die_range(blockIdx.x, gridDim.x, tiles, tfirst, tend, tstep);
+    // the loader wave reads each tile's plan header one tile ahead
+    int4 hd_next = make_int4(-1, 0, 0, 0);
+    if (wv == 1 && tfirst < tend) hd_next = plan.hdr[tfirst];
     for (int tile = (int)tfirst; tile < tend; tile += tstep) {
         const int s = find_sys(tprefix, n_sys, tile);
         const SysDev &S = sys[s];
@@ -1090,7 +1130,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         const bool loader = wv == 1;
         const int tr = tid - kWave;  // lane of the loader wave
         if (loader) {
-            const int4 hd = plan.hdr[tile];
+            const int4 hd = hd_next;
             if (tr == 0) {
                 sh.info[0] = hd.x;
                 sh.info[1] = hd.z;
@@ -1145,6 +1185,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             sh.rown[tid] = r0 + tid < n_local ? 0 : -1;
         }
         __syncthreads();
+        if (loader && tile + tstep < tend) hd_next = plan.hdr[tile + tstep];
         const int nu = uni(sh.info[0]);
         const int nslot = uni(sh.info[3]);
         if (nu <= 0 || nu > kUMax || nslot > kFastSlotMax) continue;  // built by the general kernel
@@ -1447,13 +1488,21 @@ void launch_bin(const LaunchCtx &L, const double4 *pos)
 void launch_cell_sort(const LaunchCtx &L, const double4 *pos)
 {
     if (L.n_cells == 0) return;
-    const int blocks = capped((L.n_cells * kWave + 255) / 256);
+    // one-wave workgroups: the cell sort (a multiple of the die count, so
+    // that the plan workgroups keep their die mapping), then the plans
+    int64_t n_sort = L.n_cells < 8192 ? L.n_cells : 8192;
+    n_sort = (n_sort + kDies - 1) / kDies * kDies;
+    const int n_plan = L.tiles_local < kPlanGrid ? L.tiles_local : kPlanGrid;
+    const PlanPtrs plan = plan_ptrs(L.plan, L.tiles_local);
+    const dim3 grid((unsigned)(n_sort + n_plan));
     if (L.cell_cap <= 64)
-        hipLaunchKernelGGL(k_cell_sort<1>, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.n_sys, pos,
-                           L.n_cells, L.cell_count, L.cell_size, L.cell_idx, L.cell_xf, L.cell_cap, L.flag);
+        hipLaunchKernelGGL(k_cells_and_plan<1>, grid, dim3(kWave), 0, L.stream, (int)n_sort, L.sys, L.n_sys,
+                           L.tprefix_local, L.tiles_local, pos, L.n_cells, L.cell_count, L.cell_size, L.cell_idx,
+                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag);
     else
-        hipLaunchKernelGGL(k_cell_sort<2>, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.n_sys, pos,
-                           L.n_cells, L.cell_count, L.cell_size, L.cell_idx, L.cell_xf, L.cell_cap, L.flag);
+        hipLaunchKernelGGL(k_cells_and_plan<2>, grid, dim3(kWave), 0, L.stream, (int)n_sort, L.sys, L.n_sys,
+                           L.tprefix_local, L.tiles_local, pos, L.n_cells, L.cell_count, L.cell_size, L.cell_idx,
+                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag);
 }
 
 int nlist_row_stride(int cap)
@@ -1493,19 +1542,22 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
 {
     (void)w;
     (void)block;
-    if (L.tiles_local == 0) return;
+    if (L.tiles_local == 0) {
+        // no framed scan to clear the cell counts
+        if (L.n_cells > 0)
+            hipLaunchKernelGGL(k_zero_counts, dim3(256), dim3(256), 0, L.stream, L.cell_count, L.n_cells, L.flag);
+        return;
+    }
     const int blocks = capped(L.tiles_local);
     const int rs = nlist_row_stride(L.nlist_cap);
     const size_t dyn = (size_t)kTile * rs * 2;
     const PlanPtrs plan = plan_ptrs(L.plan, L.tiles_local);
-    hipLaunchKernelGGL(k_build_plan, dim3(L.tiles_local < kPlanGrid ? L.tiles_local : kPlanGrid), dim3(kWave), 0,
-                       L.stream, L.sys, L.tprefix_local, L.n_sys, L.tiles_local, pos, L.cell_size, L.cell_cap,
-                       L.xbuild, L.slow_list, L.slow_n, plan, L.flag);
     if (L.has_bonds) {
         hipLaunchKernelGGL(k_build_fast<true>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
-                           L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.flag, L.build_count, L.status);
+                           L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.cell_count, L.n_cells, L.flag,
+                           L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<true>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
@@ -1515,7 +1567,8 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
         hipLaunchKernelGGL(k_build_fast<false>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
-                           L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.flag, L.build_count, L.status);
+                           L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.cell_count, L.n_cells, L.flag,
+                           L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<false>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
