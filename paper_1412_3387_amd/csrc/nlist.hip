@@ -736,6 +736,7 @@ struct FastShared {
     uint32_t used[kFastSlotMax / 32];
     int32_t wpre[kFastSlotMax / 32 + 1];
     uint32_t run[kTile][kRuns];          // slot range of each row line: lo | hi << 16
+    uint32_t runc[kTile][kRuns];         // the same cut to the chunk and to the line's x-window
     float hw[kTile][kRuns];              // half width in x of each row line
     float4 xrow[kTile];                  // row position in the frame (FP32)
     int32_t rown[kTile];                 // hits of each row so far
@@ -1234,31 +1235,34 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 }
             }
             __syncthreads();
-            if (one_chunk) {
-                // members of a line are ordered by x (cells in x order, each
-                // sorted by x): cut every line to the slots within the half
-                // width that its y-z distance leaves (|dx|^2 <= r_list^2 -
-                // gap^2, widened by a margin for the FP32 frame coordinates)
-                for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
-                    const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
-                    const uint32_t v = sh.run[t][rr];
-                    const int a = (int)(v & 0xffffu), b = (int)(v >> 16);
-                    if (b <= a) continue;
-                    const float hw = sh.hw[t][rr];
-                    const float xc = sh.xrow[t].x;
-                    const float tlo = xc - hw, thi = xc + hw;
-                    // first slot with x >= tlo, first slot with x > thi
-                    int pa = a, pb = a;
-                    int step = 1;
-                    while (2 * step <= b - a) step *= 2;
-                    for (; step > 0; step >>= 1) {
-                        if (pa + step <= b && sh.cp[pa + step - 1].x < tlo) pa += step;
-                        if (pb + step <= b && sh.cp[pb + step - 1].x <= thi) pb += step;
-                    }
-                    sh.run[t][rr] = (uint32_t)pa | ((uint32_t)(pb > pa ? pb : pa) << 16);
+            // members of a line are ordered by x (cells in x order, each sorted
+            // by x): cut every line, within this chunk, to the slots within the
+            // half width that its y-z distance leaves (|dx|^2 <= r_list^2 - gap^2,
+            // widened by a margin for the FP32 frame coordinates)
+            for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
+                const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
+                const uint32_t v = sh.run[t][rr];
+                int a = (int)(v & 0xffffu), b = (int)(v >> 16);
+                a = a > q0 ? a : q0;
+                b = b < q1 ? b : q1;
+                if (b <= a) {
+                    sh.runc[t][rr] = 0u;
+                    continue;
                 }
-                __syncthreads();
+                const float hw = sh.hw[t][rr];
+                const float xc = sh.xrow[t].x;
+                const float tlo = xc - hw, thi = xc + hw;
+                // first slot with x >= tlo, first slot with x > thi
+                int pa = a, pb = a;
+                int step = 1;
+                while (2 * step <= b - a) step *= 2;
+                for (; step > 0; step >>= 1) {
+                    if (pa + step <= b && sh.cp[pa + step - 1 - q0].x < tlo) pa += step;
+                    if (pb + step <= b && sh.cp[pb + step - 1 - q0].x <= thi) pb += step;
+                }
+                sh.runc[t][rr] = (uint32_t)pa | ((uint32_t)(pb > pa ? pb : pa) << 16);
             }
+            __syncthreads();
             // lanes to lines, one thread per row: line r takes lanes [B_r, B_r+1)
             // with B_r = r + about 55 P_r / T (P_r the members of the row's lines
             // before line r in this chunk, T all of them), so every line keeps at
@@ -1269,10 +1273,8 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 int tot = 0;
 #pragma unroll
                 for (int r = 0; r < kRuns; ++r) {
-                    const uint32_t rv = sh.run[tid][r];
-                    int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
-                    x0_ = x0_ > q0 ? x0_ : q0;
-                    x1_ = x1_ < q1 ? x1_ : q1;
+                    const uint32_t rv = sh.runc[tid][r];
+                    const int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
                     lens[r] = x1_ > x0_ ? x1_ - x0_ : 0;
                     tot += lens[r];
                 }
@@ -1304,10 +1306,8 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u));
                 myline = myline < kRuns - 1 ? myline : kRuns - 1;
                 const int blo_ = sh.lb[t][myline], bhi_ = sh.lb[t][myline + 1];
-                const uint32_t rv = sh.run[t][myline];
-                int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
-                x0_ = x0_ > q0 ? x0_ : q0;
-                x1_ = x1_ < q1 ? x1_ : q1;
+                const uint32_t rv = sh.runc[t][myline];
+                const int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
                 const int gsz = bhi_ - blo_ > 1 ? bhi_ - blo_ : 1;
                 const int base = x0_ + (lane - blo_);
                 const int end = x1_;
