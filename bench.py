@@ -205,9 +205,11 @@ def cpu_baseline(s, seconds):
         t0 = time.perf_counter()
         oracle.pair_forces("lj", s.pos, s.L, lj, which=which)
         t = time.perf_counter() - t0
-        if t > 0.25 * seconds or m >= s.n:
+        # the last, timed sample aims at `seconds` of CPU work (stops past
+        # two thirds of it)
+        if t > 0.66 * seconds or m >= s.n:
             break
-        m = min(s.n, int(m * max(2.0, min(16.0, 0.5 * seconds / max(t, 1e-3)))))
+        m = min(s.n, int(m * max(2.0, min(16.0, seconds / max(t, 1e-3)))))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": m / t, "unit": "particle-timesteps/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 brute-force forces of {m} random particles against all {s.n} "
@@ -224,7 +226,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tuning-out", default=None,
                     help="write the lanes/block sizes chosen per precision to this JSON file")
     ap.add_argument("--tuning-from", default=None,
