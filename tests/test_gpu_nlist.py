@@ -150,6 +150,23 @@ def test_bulk_sampled_rows(orc, B):
     assert neighbor_sets_equal(orc, ctx, s.pos, s.L, 2.5, 0.4, which=which) == []
 
 
+@pytest.mark.parametrize("density", [1.2, 3.4])
+def test_dense_builds_agree_with_oracle(orc, B, density):
+    """Dense liquids, Morton-ordered: the tiles are framed but have more
+    candidate members than one staging chunk holds (two chunks at 1.2, about
+    three at 3.4), so the x-window cut and the lane split run per chunk."""
+    s = inputs.lj_fluid(12000, 43, 44, density=density)
+    ctx = _ctx(B, s.pos, s.vel, s.L, sort_period=1)
+    ctx.build_nlist(True)
+    ctx.check()
+    tiles = (s.n + 63) // 64
+    assert ctx.general_tiles() < tiles // 4
+    assert neighbor_sets_equal(orc, ctx, s.pos, s.L, 2.5, 0.4) == []
+    nn, rows = ctx.neighbor_rows()
+    for r in rows:
+        assert len(np.unique(r)) == len(r)
+
+
 @pytest.mark.parametrize("n,sort_period", [(4000, 0), (4000, 1), (30000, 1), (30000, 0)])
 def test_framed_and_general_builds_agree_with_oracle(orc, B, n, sort_period):
     """Tiles built in one unwrapped frame (FP32 filter, FP64 decision near
