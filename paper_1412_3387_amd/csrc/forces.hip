@@ -40,13 +40,14 @@ template <> __device__ __forceinline__ double tlog<double>(double x) { return lo
 // LJ-family pair term for one neighbour inside the cut-off.  Returns the
 // force divided by r (F_i = ff * (x_i - x_j)), 24 eps s6 (2 s6 - 1) / r^2 with
 // s6 = (sigma^2 / r^2)^3 written as s6 (48 eps s6 - 24 eps) / r^2; adds energy
-// and virial.  Finite for every r2 > 0; a caller that masks the result with a
-// select may pass any r2.
+// and virial.  Zero where in is false, whatever r2 holds (masked lanes pass
+// the separations of stale entries).
 template <typename T, bool LOG>
 __device__ __forceinline__ T lj_pair(double r2, T eps, T sig2, double shift, double &e, double &vir,
                                     bool in = true)
 {
-    const T r2inv = recip<T>((T)r2);
+    // a pair outside (in == false) gets 1/r^2 = 0, hence a zero force
+    const T r2inv = in ? recip<T>((T)r2) : (T)0;
     const T s2 = sig2 * r2inv;
     const T s6 = s2 * s2 * s2;
     const T ff = s6 * ((T)48 * eps * s6 - (T)24 * eps) * r2inv;
@@ -66,6 +67,7 @@ __host__ __device__ constexpr int halo_entry_bytes(int pot) { return pot == PAIR
 // widest split): the neighbour list is padded by as many tile columns.
 constexpr int kRowOverRead = 2 * 4 * 16;
 constexpr int kRareGrid = 256;  // workgroups of the launch over the rare tiles
+constexpr size_t kRareLds = 96 * 1024;  // LDS of a workgroup of that launch, at most
 
 // One tile of the fused step.  RARE selects the code for tiles with a
 // per-pair image or a halo larger than the LDS staging area; the main
@@ -209,7 +211,8 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
             for (int u = 0; u < U; ++u) {
                 double px, py, pz;
                 if (!OVF || hh[u] < halo_lds) {
-                    const double *hp = hxyz + 3 * hh[u];
+                    const double *hp = reinterpret_cast<const double *>(
+                        reinterpret_cast<const char *>(hxyz) + (uint32_t)hh[u] * 24u);
                     px = hp[0];
                     py = hp[1];
                     pz = hp[2];
@@ -237,8 +240,7 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
                 if constexpr (POT == PAIR_LJ || POT == PAIR_WCA) {
                     // branch-free: lanes outside the cut-off add zero
                     const bool in = ok[u] && r2 < rc2;
-                    T ff = lj_pair<T, LOG>(r2, eps, sig2, shift, e, vir, in);
-                    ff = in ? ff : (T)0;
+                    const T ff = lj_pair<T, LOG>(r2, eps, sig2, shift, e, vir, in);
                     fx = __fma_rn((double)ff, dx[u], fx);
                     fy = __fma_rn((double)ff, dy[u], fy);
                     fz = __fma_rn((double)ff, dz[u], fz);
@@ -546,11 +548,48 @@ static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
                        L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
                        L.halo_cap, L.halo_lds, L.partners, L.rtag, L.xbuild, L.partials, L.status,
                        L.rare_list, L.rare_n, F);
+    // the launch over rare tiles runs few workgroups: it stages up to the
+    // whole halo list (at most kRareLds bytes), so that oversized halos are
+    // read from LDS too
     const int rb = L.tiles_local < kRareGrid ? L.tiles_local : kRareGrid;
-    hipLaunchKernelGGL((k_force_rare<W, MIXED, POT, LOG>), dim3(rb), dim3(W * kWave), lds, L.stream,
-                       L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                       L.halo_cap, L.halo_lds, L.partners, L.rtag, L.xbuild, L.partials, L.status,
-                       L.rare_list, L.rare_n, F);
+    int rare_lds_entries = (int)(kRareLds / (size_t)halo_entry_bytes(POT));
+    rare_lds_entries = rare_lds_entries < L.halo_cap ? rare_lds_entries : L.halo_cap;
+    rare_lds_entries = rare_lds_entries > L.halo_lds ? rare_lds_entries : L.halo_lds;
+    const size_t rare_lds = force_lds_bytes(POT, rare_lds_entries, L.nlist_cap);
+    hipLaunchKernelGGL((k_force_rare<W, MIXED, POT, LOG>), dim3(rb), dim3(W * kWave), rare_lds, L.stream, L.sys,
+                       L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n, L.halo_cap,
+                       rare_lds_entries, L.partners, L.rtag, L.xbuild, L.partials, L.status, L.rare_list,
+                       L.rare_n, F);
+}
+
+// Lets every instantiation of the rare-tile kernel take kRareLds bytes of
+// dynamic LDS (above the default limit).
+template <int W, bool MIXED, int POT, bool LOG>
+static hipError_t rare_attr()
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force_rare<W, MIXED, POT, LOG>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRareLds);
+}
+
+template <int W>
+static hipError_t rare_attr_w()
+{
+    const hipError_t es[8] = {rare_attr<W, true, PAIR_LJ, true>(),   rare_attr<W, true, PAIR_LJ, false>(),
+                              rare_attr<W, true, PAIR_DPD, true>(),  rare_attr<W, true, PAIR_DPD, false>(),
+                              rare_attr<W, false, PAIR_LJ, true>(),  rare_attr<W, false, PAIR_LJ, false>(),
+                              rare_attr<W, false, PAIR_DPD, true>(), rare_attr<W, false, PAIR_DPD, false>()};
+    for (hipError_t e : es)
+        if (e != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t prepare_force()
+{
+    const hipError_t es[5] = {rare_attr_w<1>(), rare_attr_w<2>(), rare_attr_w<4>(), rare_attr_w<8>(),
+                              rare_attr_w<16>()};
+    for (hipError_t e : es)
+        if (e != hipSuccess) return e;
+    return hipSuccess;
 }
 
 template <int W, bool MIXED, int POT>

@@ -87,5 +87,7 @@ int force_halo_entry_bytes(int pair);
 size_t fast_build_lds_bytes(int nlist_cap);
 size_t build_plan_bytes(int64_t tiles);
 hipError_t prepare_nlist(int nlist_cap);
+// Raises the dynamic-LDS limit of the rare-tile force kernels (init time).
+hipError_t prepare_force();
 
 }  // namespace md

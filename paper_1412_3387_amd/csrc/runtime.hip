@@ -122,6 +122,11 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         }
         hc = std::min(std::max(hc, 64), 65535);
         int hl = p[s].sort_period > 0 ? (int)std::ceil(1.25 * est / 64.0) * 64 : lds_budget;
+        // where the mean halo fits, stay within the share of seven
+        // 256-thread workgroups in a CU's 160 KB of LDS: seven resident tiles
+        // per CU outrun six, though a few more tiles go to the rare launch
+        const int share7 = std::max(163840 / 7 / entry / 64 * 64, 64);
+        if (p[s].sort_period > 0 && est <= share7) hl = std::min(hl, share7);
         hl = std::min(std::max(hl, 64), std::min(lds_budget, hc));
         Lo.halo_cap = std::max(Lo.halo_cap, hc);
         Lo.halo_lds = std::max(Lo.halo_lds, hl);
@@ -495,6 +500,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
 
     // descriptors, prefixes, cleared counters (synchronous: init is not hot)
     hipError_t e = prepare_nlist(lay.nlist_cap);
+    if (e == hipSuccess) e = prepare_force();
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.sysdev, lay.sys.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpl, lay.tpl_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpa, lay.tpa_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
