@@ -155,24 +155,57 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
         hxyz[1] = xref.y;
         hxyz[2] = xref.z;
     }
-    for (int h = tid; h < ns; h += W * kWave) {
-        double px, py, pz;
-        halo_pos(h, px, py, pz);
-        hxyz[3 * h] = px;
-        hxyz[3 * h + 1] = py;
-        hxyz[3 * h + 2] = pz;
+    // the row's own position, read before the staging so that its latency
+    // overlaps it
+    const double4 xi = a.pos[i];
+    // SB entries per thread per batch: every index load of a batch issues
+    // before any gather, and every gather before any use, so a tile waits for
+    // two memory round trips per batch instead of two per entry (indices past
+    // the halo's end are clamped to its last entry and not stored)
+    constexpr int SB = 4;
+    constexpr int NT = W * kWave;
+    for (int h0 = tid; h0 < ns; h0 += SB * NT) {
+        int32_t jb[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+            const int h = h0 + b * NT;
+            jb[b] = hl[h < ns ? h : ns - 1];
+        }
+        double4 xb[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) xb[b] = a.pos[jb[b]];
+        double4 vb[SB];
+        int32_t tb[SB];
         if constexpr (POT == PAIR_DPD) {
-            const int32_t j = hl[h];
-            const double4 v = a.vel[j];
-            hv[3 * h] = v.x;
-            hv[3 * h + 1] = v.y;
-            hv[3 * h + 2] = v.z;
-            htag[h] = a.tag[j];
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                vb[b] = a.vel[jb[b]];
+                tb[b] = a.tag[jb[b]];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+            const int h = h0 + b * NT;
+            if (h >= ns) break;
+            double px = xb[b].x, py = xb[b].y, pz = xb[b].z;
+            if (!per_pair) {
+                px = __fma_rn(-Lx, rint((px - xref.x) * iLx), px);
+                py = __fma_rn(-Ly, rint((py - xref.y) * iLy), py);
+                pz = __fma_rn(-Lz, rint((pz - xref.z) * iLz), pz);
+            }
+            hxyz[3 * h] = px;
+            hxyz[3 * h + 1] = py;
+            hxyz[3 * h + 2] = pz;
+            if constexpr (POT == PAIR_DPD) {
+                hv[3 * h] = vb[b].x;
+                hv[3 * h + 1] = vb[b].y;
+                hv[3 * h + 2] = vb[b].z;
+                htag[h] = tb[b];
+            }
         }
     }
     __syncthreads();
 
-    const double4 xi = a.pos[i];
     // the row's own position, moved to the same frame as the halo images
     double xs = xi.x, ys = xi.y, zs = xi.z;
     if (!per_pair) {
