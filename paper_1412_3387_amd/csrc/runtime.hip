@@ -280,15 +280,17 @@ struct hoomd_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used;
     std::vector<std::pair<size_t, size_t>> ev_force, ev_rebuild;
-    // captured pairs of middle steps, one per buffer parity
+    // captured runs of middle steps, per buffer parity: [p][0] two steps,
+    // [p][1] 2 kLongPairs steps
     hipStream_t cap_stream;
-    hipGraphExec_t graph_exec[2];
-    int graph_tpp[2];
+    hipGraphExec_t graph_exec[2][2];
+    int graph_tpp[2][2];
     ~hoomd_ctx()
     {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (int p = 0; p < 2; ++p)
-            if (graph_exec[p]) (void)hipGraphExecDestroy(graph_exec[p]);
+            for (int k = 0; k < 2; ++k)
+                if (graph_exec[p][k]) (void)hipGraphExecDestroy(graph_exec[p][k]);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 };
@@ -378,12 +380,17 @@ void queue_mid_step(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V, b
     queue_rebuild(c, P[p ^ 1], c->arr.tag, flag_ptr(c, p));
 }
 
-int ensure_step_graph(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V, bool dpd)
+// Pairs of middle steps in the long captured run: one graph launch per 16
+// steps instead of per 2 (each launch leaves a gap of some microseconds).
+constexpr int kLongPairs = 8;
+
+int ensure_step_graph(hoomd_ctx *c, int p, int kind, double4 *const *P, double4 *const *V, bool dpd)
 {
-    if (c->graph_exec[p] && c->graph_tpp[p] == c->tpp_force) return HOOMD_OK;
-    if (c->graph_exec[p]) {
-        (void)hipGraphExecDestroy(c->graph_exec[p]);
-        c->graph_exec[p] = nullptr;
+    hipGraphExec_t &ge = c->graph_exec[p][kind];
+    if (ge && c->graph_tpp[p][kind] == c->tpp_force) return HOOMD_OK;
+    if (ge) {
+        (void)hipGraphExecDestroy(ge);
+        ge = nullptr;
     }
     // capture on a private stream (the caller's may be the null stream, which
     // cannot be captured); the graph is launched on the caller's stream
@@ -394,18 +401,21 @@ int ensure_step_graph(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V,
     hipGraph_t g = nullptr;
     bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-        queue_mid_step(c, p, P, V, dpd);
-        queue_mid_step(c, p ^ 1, P, V, dpd);
+        const int pairs = kind ? kLongPairs : 1;
+        for (int k = 0; k < pairs; ++k) {
+            queue_mid_step(c, p, P, V, dpd);
+            queue_mid_step(c, p ^ 1, P, V, dpd);
+        }
         ok = hipStreamEndCapture(c->cap_stream, &g) == hipSuccess && g;
     }
     c->L.stream = keep;
-    if (ok) ok = hipGraphInstantiate(&c->graph_exec[p], g, nullptr, nullptr, 0) == hipSuccess;
+    if (ok) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
     if (g) (void)hipGraphDestroy(g);
     if (!ok) {
-        c->graph_exec[p] = nullptr;
+        ge = nullptr;
         return HOOMD_E_DEVICE;
     }
-    c->graph_tpp[p] = c->tpp_force;
+    c->graph_tpp[p][kind] = c->tpp_force;
     return HOOMD_OK;
 }
 
@@ -650,19 +660,25 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
     while (s <= n_steps) {
         const uint64_t t = t0 + (uint64_t)s;
         const int p = s & 1;  // parity of the position (and DPD velocity) buffers
-        // two middle steps with nothing eager in between replay as one graph
-        if (graphs && s > 0 && s + 1 < n_steps && !logs_at(s) && !logs_at(s + 1) && !sorts_after(s) &&
-            !sorts_after(s + 1)) {
-            if (ensure_step_graph(c, p, P, V, dpd) != HOOMD_OK) {
-                c->L.step_counter = nullptr;
-                return HOOMD_E_DEVICE;
+        // middle steps with nothing eager in between replay as one graph:
+        // 2 kLongPairs of them where they all qualify, else two
+        if (graphs && s > 0) {
+            int run = 0;
+            while (run < 2 * kLongPairs && s + run < n_steps && !logs_at(s + run) && !sorts_after(s + run))
+                ++run;
+            if (run >= 2) {
+                const int kind = run == 2 * kLongPairs ? 1 : 0;
+                if (ensure_step_graph(c, p, kind, P, V, dpd) != HOOMD_OK) {
+                    c->L.step_counter = nullptr;
+                    return HOOMD_E_DEVICE;
+                }
+                if (hipGraphLaunch(c->graph_exec[p][kind], c->stream) != hipSuccess) {
+                    c->L.step_counter = nullptr;
+                    return HOOMD_E_DEVICE;
+                }
+                s += kind ? 2 * kLongPairs : 2;
+                continue;
             }
-            if (hipGraphLaunch(c->graph_exec[p], c->stream) != hipSuccess) {
-                c->L.step_counter = nullptr;
-                return HOOMD_E_DEVICE;
-            }
-            s += 2;
-            continue;
         }
         ForceLaunch F = base_force(c);
         F.pos = P[p];
