@@ -9,6 +9,9 @@ rebuilds and sorts that fall inside the window).  The reported value is the
 mixed-precision rate (FP32 pair arithmetic, FP64 positions / integration /
 reductions); the all-FP64 rate is measured on the same workload beside it.
 
+Beside it (under "others", context only) the same path's mixed-precision rate
+on the DPD fluid (N = 1,000,000) and on the 256-system batched ensemble.
+
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
 import argparse
@@ -122,6 +125,67 @@ def force_check(B, torch, s):
     return {"max_err_over_Frms": err, "tolerance": 1e-5, "pass": err <= 1e-5, "F_rms": frms}
 
 
+def other_workload(B, torch, label, params, systems, steps, warmup, t0=0):
+    """Mixed-precision throughput of a secondary workload (context beside the
+    headline: the same product path, captured steps replayed): total
+    particles x steps / device time of `steps` steps after `warmup` steps
+    that start at step t0."""
+    ctx = B.Context(params, systems)
+    ctx.build_nlist(True)
+    tuning = ctx.autotune(False)  # the default lanes per row and block sizes
+    ctx.step(t0, warmup)
+    ctx.check()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    b0 = ctx.build_count()
+    e0.record(ctx.stream)
+    ctx.step(t0 + warmup, steps)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = e0.elapsed_time(e1)
+    n = sum(int(sy["pos"].shape[0]) for sy in systems)
+    out = {"workload": label, "value": n * steps / (ms / 1e3), "unit": "particle-timesteps/s",
+           "steps_per_s": steps / (ms / 1e3), "particles": n, "systems": len(systems), "steps": steps,
+           "rebuilds": ctx.build_count() - b0,
+           "precision": "mixed", "tuning": {"tpp_force": tuning.tpp_force, "tpp_nlist": tuning.tpp_nlist}}
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def other_workloads(B, inputs, torch, steps, warmup):
+    """DPD fluid (N = 1,000,000, density 3, r_cut 1, A 25, gamma 4.5, kT 1,
+    dt 0.02) and the batched ensemble (128 LJ liquids of 500..20,000
+    particles and 128 bead-spring melts of 20..400 chains of 50, FENE + WCA),
+    each in one context."""
+    res = {}
+    try:
+        # rows start in random order: the halos of the first build need a
+        # larger list, and starting at step 499 puts the first Morton sort
+        # (every 500 steps) right after the first step
+        d = inputs.dpd_bulk()
+        p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=33,
+                          sort_period=500, halo_cap=4096)
+        res["dpd_1M"] = other_workload(B, torch, "dpd_1M", [p], [dict(pos=d.pos, vel=d.vel, L=d.L)],
+                                       steps, warmup, t0=499)
+    except Exception as e:  # reported, not fatal: the headline line still prints
+        res["dpd_1M"] = {"error": repr(e)}
+    try:
+        batch = inputs.batch_ensemble()
+        params = [B.ModelParams(precision=B.MIXED, pair=B.PAIR_LJ, tpp_force=4, sort_period=500)
+                  if sy.kind == "lj" else
+                  B.ModelParams(precision=B.MIXED, pair=B.PAIR_WCA, bond_cap=2, tpp_force=4, sort_period=500)
+                  for sy in batch]
+        systems = [dict(pos=sy.pos, vel=sy.vel, L=sy.L, bonds=sy.bonds, tag=sy.tag) for sy in batch]
+        res["batch_256"] = other_workload(B, torch, "batch_256", params, systems, steps, warmup)
+    except Exception as e:
+        res["batch_256"] = {"error": repr(e)}
+    return res
+
+
 COPY_BYTES = 1 << 30
 
 
@@ -227,6 +291,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the secondary workloads (DPD 1M, 256-system batch)")
+    ap.add_argument("--other-steps", type=int, default=1000)
     ap.add_argument("--tuning-out", default=None,
                     help="write the lanes/block sizes chosen per precision to this JSON file")
     ap.add_argument("--tuning-from", default=None,
@@ -340,6 +407,9 @@ def main():
                         "force_avg_us": fp64["prof"].force_ms / max(fp64["prof"].force_launches, 1) * 1e3}
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
     line["force_check"] = force_check(B, torch, s)
+    if not args.no_others:
+        print("[bench] other workloads", file=sys.stderr, flush=True)
+        line["others"] = other_workloads(B, inputs, torch, args.other_steps, 100)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
