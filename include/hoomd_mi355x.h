@@ -211,6 +211,27 @@ int pack_ghosts(hoomd_ctx *ctx, int32_t sys, const hoomd_subdomain *subdomain, i
                 uint32_t fields, void *send, int64_t send_cap, int32_t *counts26,
                 int32_t *offsets26);
 
+/* pack_ghosts() in HOOMD_GHOST_SELECT mode without a context or workspace,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc).  Selects and
+ * packs rows [0, n_local) of pos (double[n_local][4]; vel and tag as in the
+ * particle layout, needed only when HOOMD_FIELD_VEL / HOOMD_FIELD_TAG are
+ * asked for) with the same send rule, order and record layout as
+ * pack_ghosts(); counts26 / offsets26 are device int32[26] outputs.  The
+ * per-row masks and scan partials live in a fixed device array of the
+ * library (about 9 MB per GPU, held until the process ends): n_local above
+ * HOOMD_NOALLOC_MAX_ROWS returns HOOMD_E_ARG and queues nothing.  No device
+ * memory is allocated.  No send list is stored (there is no UPDATE mode),
+ * and overflow is not latched: a total (offsets26[25] + counts26[25]) above
+ * send_cap means the records past send_cap were not written.  Every call on
+ * one GPU uses that GPU's one array, so calls that overlap in time on the
+ * same GPU (different streams or threads) race; calls queued on one stream
+ * are safe.  Queued on `stream` (a hipStream_t, NULL = null stream). */
+#define HOOMD_NOALLOC_MAX_ROWS 2097152
+int pack_ghosts_noalloc(const double *pos, const double *vel, const int32_t *tag, int64_t n_local,
+                        const hoomd_subdomain *subdomain, uint32_t fields, void *send, int64_t send_cap,
+                        int32_t *counts26, int32_t *offsets26, void *stream);
+
 /* Append (HOOMD_GHOST_SELECT) or overwrite in place (HOOMD_GHOST_UPDATE)
  * the n_recv ghosts of a receive buffer laid out as pack_ghosts() writes it,
  * after the locals of system `sys`.  Each received position is moved to its

@@ -82,7 +82,7 @@ class Profile(C.Structure):
 EXPORTS = ["hoomd_workspace_bytes", "hoomd_init", "hoomd_destroy", "build_nlist",
            "compute_forces", "step", "pack_ghosts", "unpack_ghosts", "hoomd_thermo",
            "hoomd_thermo_log", "hoomd_sync_status", "hoomd_build_count", "hoomd_get_layout",
-           "hoomd_autotune", "hoomd_profile", "hoomd_strerror"]
+           "hoomd_autotune", "hoomd_profile", "hoomd_strerror", "pack_ghosts_noalloc"]
 
 _lib = None
 
@@ -120,6 +120,8 @@ def lib():
         L.hoomd_get_layout.argtypes = [P, C.c_int32, C.POINTER(Layout)]
         L.hoomd_autotune.argtypes = [P, C.c_int32, C.POINTER(Tuning)]
         L.hoomd_profile.argtypes = [P, C.c_int32, C.POINTER(Profile)]
+        L.pack_ghosts_noalloc.argtypes = [P, P, P, C.c_int64, C.POINTER(Subdomain), C.c_uint32, P,
+                                          C.c_int64, P, P, P]
         L.hoomd_strerror.argtypes = [C.c_int]
         L.hoomd_strerror.restype = C.c_char_p
         _lib = L
@@ -169,6 +171,26 @@ class ModelParams:
             setattr(p, f.name, getattr(self, f.name))
         p.nlist_cap = cap
         return p
+
+
+NOALLOC_MAX_ROWS = 2097152
+
+
+def pack_ghosts_noalloc(pos, vel, tag, n_local: int, lo, hi, width: float, fields: int, send,
+                        send_cap: int, counts, offsets, stream=None):
+    """Context-free ghost selection + packing (C ABI pack_ghosts_noalloc)
+    over device tensors: pos / vel (n, 4) float64, tag (n,) int32."""
+    sd = Subdomain()
+    for a in range(3):
+        sd.lo[a] = float(lo[a])
+        sd.hi[a] = float(hi[a])
+    sd.width = float(width)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(lib().pack_ghosts_noalloc(_ptr(pos), _ptr(vel), _ptr(tag), n_local, C.byref(sd), fields,
+                                     _ptr(send), send_cap, _ptr(counts), _ptr(offsets), stream),
+           "pack_ghosts_noalloc")
 
 
 def _check(code: int, what: str):

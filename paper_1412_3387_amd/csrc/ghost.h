@@ -57,6 +57,12 @@ int queue_ghost_select(hipStream_t stream, const GhostBuffers &B, const GhostArg
 int queue_ghost_update(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g);
 int queue_ghost_unpack(hipStream_t stream, const UnpackArgs &u);
 
+// Selection + packing with the library's fixed device scratch instead of a
+// workspace (no stored list, no status word): rows [0, n_local) of g.pos.
+int queue_ghost_select_static(hipStream_t stream, GhostArgs g);
+int64_t ghost_static_max_rows();
+size_t ghost_static_bytes();
+
 // Bytes of one packed record for a field set.
 __host__ __device__ inline int ghost_record_bytes(uint32_t fields)
 {

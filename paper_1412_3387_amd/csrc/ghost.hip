@@ -14,6 +14,8 @@
 #include "ghost.h"
 #include "sort.h"
 
+#include <mutex>
+
 namespace md {
 
 static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
@@ -136,7 +138,7 @@ __global__ void k_ghost_totals(const int32_t *__restrict__ scanned, const int32_
         offsets[d] = a;
         counts[d] = b - a;
     }
-    if (d == 0 && ((int64_t)*total > send_cap || (int64_t)*total > list_cap))
+    if (st && d == 0 && ((int64_t)*total > send_cap || (int64_t)*total > list_cap))
         latch(st, 7 /*GHOST_OVERFLOW*/, *total);
 }
 
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kGhostBlock) void k_ghost_scatter(GhostArgs g, cons
         if (!sel) continue;
         int64_t p = scanned[(int64_t)d * nblocks + blockIdx.x] + __popcll(b & lt);
         for (int v = 0; v < w; ++v) p += wc[v][d];
-        if (p < g.list_cap) g.list[p] = r;
+        if (g.list && p < g.list_cap) g.list[p] = r;
         if (p < g.send_cap) pack_record(g, p, g.row0 + r);
     }
 }
@@ -200,8 +202,10 @@ int queue_ghost_select(hipStream_t stream, const GhostBuffers &B, const GhostArg
     const int nb = nblocks > 0 ? nblocks : 1;
     hipLaunchKernelGGL(k_ghost_mask, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb);
     launch_scan(stream, B.blk_counts, B.blk_counts, 26 * (int64_t)nb, g.total, B.blk_sums);
+    // without a stored list (list == nullptr) only the send buffer bounds the total
+    const int64_t list_cap = g.list ? g.list_cap : INT64_MAX;
     hipLaunchKernelGGL(k_ghost_totals, dim3(1), dim3(64), 0, stream, B.blk_counts, g.total, nb, g.counts,
-                       g.offsets, g.send_cap, g.list_cap, g.status);
+                       g.offsets, g.send_cap, list_cap, g.status);
     hipLaunchKernelGGL(k_ghost_scatter, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
@@ -219,6 +223,87 @@ int queue_ghost_unpack(hipStream_t stream, const UnpackArgs &u)
     const int blocks = (int)((u.n + 255) / 256);
     hipLaunchKernelGGL(k_ghost_unpack, dim3(blocks), dim3(256), 0, stream, u);
     return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+}  // namespace md
+
+// ---------------------------------------------------------------------------
+// Ghost selection and packing without a caller workspace (for callers that
+// cannot allocate device memory).  The per-row direction masks, the
+// direction-by-block count table, the scan's block sums and the list total
+// live in one file-scope device array of fixed size.  Host code never uses
+// the array's name as an address: at the first call on a device (that device
+// current) its device address is looked up once with hipGetSymbolAddress and
+// kept per device, and only that address is handed to the kernels.
+// ---------------------------------------------------------------------------
+
+namespace md {
+namespace {
+
+constexpr int64_t kStaticRows = (int64_t)1 << 21;  // locals per call at most
+constexpr int64_t kStaticBlocks = kStaticRows / kGhostBlock;
+constexpr size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t kStaticTotalOff = 0;                  // int32 list total
+constexpr size_t kStaticMaskOff = 256;                 // uint32 per row
+constexpr size_t kStaticCountsOff = kStaticMaskOff + up256(sizeof(uint32_t) * kStaticRows);
+constexpr size_t kStaticSumsOff = kStaticCountsOff + up256(sizeof(int32_t) * 26 * kStaticBlocks);
+constexpr size_t kStaticBytes =
+    kStaticSumsOff + up256(sizeof(int32_t) * (size_t)((26 * kStaticBlocks + kScanTile - 1) / kScanTile + 1));
+static_assert(kStaticRows % kGhostBlock == 0, "whole selection blocks");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (nullptr: not looked up)
+
+}  // namespace
+
+}  // namespace md
+
+static __device__ __align__(256) char scratch[md::kStaticBytes];
+
+namespace md {
+
+// Device address of the array on the current device (looked up once).
+static hipError_t static_scratch(char **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+int64_t ghost_static_max_rows() { return kStaticRows; }
+size_t ghost_static_bytes() { return kStaticBytes; }
+
+// Queue selection + packing of rows [0, n_local) on `stream` with the
+// static scratch.  Returns 0, 1 on a launch error, 2 when the scratch
+// address cannot be found.
+int queue_ghost_select_static(hipStream_t stream, GhostArgs g)
+{
+    char *base = nullptr;
+    if (static_scratch(&base) != hipSuccess) return 2;
+    GhostBuffers B{};
+    B.mask = reinterpret_cast<uint32_t *>(base + kStaticMaskOff);
+    B.blk_counts = reinterpret_cast<int32_t *>(base + kStaticCountsOff);
+    B.blk_sums = reinterpret_cast<int32_t *>(base + kStaticSumsOff);
+    B.list = nullptr;
+    B.totals = reinterpret_cast<int32_t *>(base + kStaticTotalOff);
+    B.rows = kStaticRows;
+    g.mask = B.mask;
+    g.list = nullptr;
+    g.list_cap = 0;
+    g.total = B.totals;
+    g.status = nullptr;
+    return queue_ghost_select(stream, B, g);
 }
 
 }  // namespace md

@@ -764,6 +764,34 @@ int pack_ghosts(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, int32_t mo
     return rc ? HOOMD_E_DEVICE : HOOMD_OK;
 }
 
+int pack_ghosts_noalloc(const double *pos, const double *vel, const int32_t *tag, int64_t n_local,
+                        const hoomd_subdomain *sd, uint32_t fields, void *send, int64_t send_cap,
+                        int32_t *counts26, int32_t *offsets26, void *stream)
+{
+    if (!sd || !counts26 || !offsets26 || n_local < 0 || n_local > ghost_static_max_rows()) return HOOMD_E_ARG;
+    if ((fields & ~7u) || send_cap < 0 || (send_cap > 0 && !send)) return HOOMD_E_ARG;
+    if ((n_local > 0 && !pos) || ((fields & HOOMD_FIELD_VEL) && !vel) || ((fields & HOOMD_FIELD_TAG) && !tag))
+        return HOOMD_E_ARG;
+    if (!(sd->width >= 0)) return HOOMD_E_ARG;
+    GhostArgs g{};
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = sd->lo[a];
+        g.hi[a] = sd->hi[a];
+    }
+    g.width = sd->width;
+    g.row0 = 0;
+    g.n_local = (int32_t)n_local;
+    g.fields = fields;
+    g.send = send;
+    g.send_cap = send_cap;
+    g.counts = counts26;
+    g.offsets = offsets26;
+    g.pos = reinterpret_cast<const double4 *>(pos);
+    g.vel = reinterpret_cast<const double4 *>(vel);
+    g.tag = tag;
+    return queue_ghost_select_static((hipStream_t)stream, g) ? HOOMD_E_DEVICE : HOOMD_OK;
+}
+
 int unpack_ghosts(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, uint32_t fields,
                   int32_t mode, const double *box_L)
 {
