@@ -111,11 +111,23 @@ typedef struct {
                               LDS and reads any further entries from global
                               memory, so this bounds memory, not speed      */
     int32_t sort_period;   /* Morton sort every this many steps (0 = never)  */
-    int32_t check_period;  /* displacement check every k steps (>= 1)        */
-    int32_t tpp_nlist;     /* lanes per particle, neighbour list (0 = tuned) */
-    int32_t tpp_force;     /* lanes per particle, forces (0 = tuned)         */
-    int32_t block_nlist;   /* threads per block (0 = tuned)                  */
-    int32_t block_force;
+    int32_t check_period;  /* step() checks displacements on every k-th step
+                              counted from the last build (0 or 1 = every
+                              step; equal in all systems).  With k > 1 a
+                              rebuild found at the first check after a build
+                              latches HOOMD_E_DANGEROUS_BUILD: a particle may
+                              have passed r_buff/2 before it was seen
+                              (Sec. 4.2, Sec. 6.1)                          */
+    int32_t tpp_nlist;     /* lanes per particle of the neighbour-list build:
+                              0 or the fixed value hoomd_autotune() reports
+                              (anything else is HOOMD_E_ARG)               */
+    int32_t tpp_force;     /* lanes per particle, forces: 1, 2, 4, 8 or 16
+                              (0 = chosen from the system size; hoomd_autotune
+                              times the candidates) (Sec. 5.1, 5.2)         */
+    int32_t block_nlist;   /* threads per workgroup of the build: 0 or the
+                              value hoomd_autotune() reports                */
+    int32_t block_force;   /* threads per workgroup of the force pass: 0 or
+                              64 * tpp_force (one 64-row tile each)         */
     int32_t use_graph;     /* 1: step() replays captured pairs of middle steps
                               (HIP graph, captured once per context)          */
 } hoomd_params;
@@ -167,22 +179,27 @@ void hoomd_destroy(hoomd_ctx *ctx);
  * current positions (Sec. 5.1, Fig. 4): particle j != i is listed in row i
  * when |x_j - x_i|^2 < (r_cut + r_buff)^2 in FP64, minimum image along
  * periodic axes, excluding bonded partners.  force_rebuild = 0 builds only
- * if some particle moved more than r_buff/2 since the last build.  Rows are
- * ordered by stencil cell (z, y, x offsets from -1 to 1) then by ascending
- * index inside the cell.  Overflow of a row or a cell latches a status. */
+ * if some particle moved more than r_buff/2 since the last build (Sec. 4.2).
+ * A row holds 16-bit indices into the halo of its 64-row tile (the tile's
+ * distinct neighbours, see hoomd_get_layout); the order of the entries in a
+ * row is unspecified (it follows the build's staging order), the set is
+ * exact.  With sort_period > 0 the rows are first put in Morton order.
+ * Overflow of a row, a cell or a halo latches a status. */
 int build_nlist(hoomd_ctx *ctx, int32_t force_rebuild);
 
 /* Flags of compute_forces() and step(). */
 enum { HOOMD_ENERGY = 1u, HOOMD_VIRIAL = 2u };
 
-/* Forces on the local particles at the current state, keyed (for DPD) on
- * `timestep`.  Builds the neighbour list first if needed.  Writes `force`
+/* Forces on the local particles at the current state (Sec. 3: LJ, DPD;
+ * Sec. 4.3.4: FENE + WCA bonds; Sec. 5.1: w lanes per particle), keyed (for
+ * DPD) on `timestep`.  Builds the neighbour list first if needed.  Writes `force`
  * (energy in the w component when HOOMD_ENERGY is set) and, with flags, the
  * per-system thermo sums read by hoomd_thermo(). */
 int compute_forces(hoomd_ctx *ctx, uint64_t timestep, uint32_t flags);
 
-/* Advance every system n_steps velocity-Verlet steps, the state before the
- * call being that of timestep first_timestep: per step v += dt/2 F; x += dt
+/* Advance every system n_steps velocity-Verlet (NVE, Sec. 3) steps with
+ * rebuilds decided on the device (Sec. 4.2), the state before the call being
+ * that of timestep first_timestep: per step v += dt/2 F; x += dt
  * v (folded); rebuild when needed; F <- F(x, v, t+1); v += dt/2 F.  With
  * log_every > 0 the thermo sums are recorded every log_every steps (and at
  * the last step) in a device ring read by hoomd_thermo_log().  Morton sorts
@@ -232,7 +249,9 @@ int pack_ghosts_noalloc(const double *pos, const double *vel, const int32_t *tag
                         const hoomd_subdomain *subdomain, uint32_t fields, void *send, int64_t send_cap,
                         int32_t *counts26, int32_t *offsets26, void *stream);
 
-/* Append (HOOMD_GHOST_SELECT) or overwrite in place (HOOMD_GHOST_UPDATE)
+/* Ghost unpacking (Sec. 4.3.2: ghosts are appended after the local
+ * particles; Sec. 9: DPD ghosts carry velocities and IDs).  Append
+ * (HOOMD_GHOST_SELECT) or overwrite in place (HOOMD_GHOST_UPDATE)
  * the n_recv ghosts of a receive buffer laid out as pack_ghosts() writes it,
  * after the locals of system `sys`.  Each received position is moved to its
  * periodic image nearest the centre of the frame [lo, lo + L) of the
@@ -241,8 +260,8 @@ int pack_ghosts_noalloc(const double *pos, const double *vel, const int32_t *tag
 int unpack_ghosts(hoomd_ctx *ctx, int32_t sys, const void *recv, int64_t n_recv,
                   uint32_t fields, int32_t mode, const double *box_L);
 
-/* Per-system thermo {KE, PE, W, T} of the last evaluation that asked for
- * energies (compute_forces with flags, or a logged step), FP64, summed in a
+/* Per-system thermo {KE, PE, W, T} (Sec. 4.3.3: energies and virial summed
+ * once per evaluation) of the last evaluation that asked for energies (compute_forces with flags, or a logged step), FP64, summed in a
  * fixed order.  out holds 4 * n_sys doubles.  Synchronises. */
 int hoomd_thermo(hoomd_ctx *ctx, double *out);
 
@@ -251,7 +270,8 @@ int hoomd_thermo(hoomd_ctx *ctx, double *out);
  * the number of rows via *rows. */
 int hoomd_thermo_log(hoomd_ctx *ctx, double *out, int32_t max_rows, int32_t *rows);
 
-/* Read and clear the device status word.  Returns the first latched
+/* Read and clear the device status word (overflow of a row, cell, halo or
+ * ghost list; bond stretch; NaN; dangerous build, Sec. 4.2 and Sec. 6.1).  Returns the first latched
  * condition (HOOMD_OK if none); *required (may be NULL) receives the
  * capacity that would have avoided an overflow (row entries, cell members or
  * ghost entries).  Synchronises. */
@@ -274,7 +294,10 @@ int hoomd_build_count(hoomd_ctx *ctx, int64_t *builds);
  *   bins per axis.  Row i of system s is row row_offset + i of the arrays,
  *   tile t of the system is tile tile_offset + t of halo and halo_n.
  *   general_tiles: int32 count, over all systems, of the tiles that the
- *   last build handed from the framed build to the general one. */
+ *   last build handed from the framed build to the general one;
+ *   rare_tiles: int32 count, over all systems, of the tiles that the force
+ *   pass handles in its second launch (per-pair images, or a halo above
+ *   halo_lds, the entries the first launch stages in LDS). */
 typedef struct {
     const uint16_t *nlist;
     const int32_t *nn;
@@ -290,6 +313,9 @@ typedef struct {
     int64_t cell_offset;
     int64_t tile_offset;
     const int32_t *general_tiles;
+    const int32_t *rare_tiles;
+    int32_t halo_lds;
+    int32_t pad_;
 } hoomd_layout;
 int hoomd_get_layout(hoomd_ctx *ctx, int32_t sys, hoomd_layout *out);
 

@@ -66,7 +66,8 @@ class Layout(C.Structure):
                 ("halo_n", C.c_void_p), ("cell_idx", C.c_void_p), ("cell_size", C.c_void_p),
                 ("nlist_cap", C.c_int32), ("cell_cap", C.c_int32), ("halo_cap", C.c_int32),
                 ("bins", C.c_int32 * 3), ("row_offset", C.c_int64), ("cell_offset", C.c_int64),
-                ("tile_offset", C.c_int64), ("general_tiles", C.c_void_p)]
+                ("tile_offset", C.c_int64), ("general_tiles", C.c_void_p),
+                ("rare_tiles", C.c_void_p), ("halo_lds", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -385,6 +386,19 @@ class Context:
         """Tiles of the last build that went to the general (unframed) build."""
         lay = self.layout(0)
         return int(self._ws_view(lay.general_tiles, 1).cpu().item())
+
+    def rare_tiles(self) -> int:
+        """Tiles of the last build that the force pass handles in its second
+        launch (per-pair images or a halo beyond its LDS stage)."""
+        lay = self.layout(0)
+        return int(self._ws_view(lay.rare_tiles, 1).cpu().item())
+
+    def halo_n(self, sys: int = 0) -> np.ndarray:
+        """Tile headers of the last build (halo size, longest row, per-pair
+        image bit), as unsigned 32-bit words."""
+        lay = self.layout(sys)
+        tiles = (self.n_local[sys] + 63) // 64
+        return self._ws_view(lay.halo_n, tiles).cpu().numpy().view(np.uint32)
 
     def halo_sizes(self, sys: int = 0) -> np.ndarray:
         lay = self.layout(sys)

@@ -38,13 +38,13 @@ struct SysDev {
     int32_t n_local;        // rows integrated
     int32_t n_total;        // locals + ghosts (rows binned / neighbours)
     int32_t n_cap;          // rows reserved for this system
-    int32_t pad1;
+    int32_t bond_stride;    // entries per particle of the partner table (same for all systems)
     int64_t nl0;            // first neighbour-list entry of this system
     int64_t cell0;          // first cell of this system
     int32_t tile0;          // first local tile (64 rows) of this system
     int32_t tile0_all;      // first tile over all rows (locals + ghosts)
     int32_t pair;           // Pair
-    int32_t bond_cap;       // partner slots per particle (0 = none)
+    int32_t bond_cap;       // partner slots used by this system (0 = none), <= bond_stride
     double rc2;             // cut-off^2 (FP64 test, both precisions)
     double rl2;             // (r_cut + r_buff)^2
     double disp2;           // (r_buff / 2)^2

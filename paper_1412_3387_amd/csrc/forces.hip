@@ -351,7 +351,7 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
         // bonds: FENE + WCA with partner rows indexed by tag
         if (S.bond_cap > 0) {
             const int32_t tg = a.tag[i];
-            const int64_t prow = (row0 + tg) * S.bond_cap;
+            const int64_t prow = (row0 + tg) * S.bond_stride;
             for (int b = 0; b < S.bond_cap; ++b) {
                 const int32_t tp = partners[prow + b];
                 if (tp < 0) continue;
@@ -406,11 +406,21 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
             if (S.per[2]) x.z = fold(x.z, S.lo[2], Lz);
             a.pos_out[i] = x;
             a.vel_out[i] = v;
-            const double4 xb = xbuild[i];
-            const double bx = min_image(x.x - xb.x, Lx, iLx);
-            const double by = min_image(x.y - xb.y, Ly, iLy);
-            const double bz = min_image(x.z - xb.z, Lz, iLz);
-            if ((bx * bx + by * by) + bz * bz > S.disp2) *a.flag_set = 1;
+            // displacement check (Sec. 4.2) on the steps of the check period,
+            // counted from the last build; a rebuild at the first check after a
+            // build may have come late when the period is above one (Sec. 6.1:
+            // a dangerous build)
+            const int since1 = a.since ? *a.since + 1 : 1;
+            if (a.check_period <= 1 || since1 % a.check_period == 0) {
+                const double4 xb = xbuild[i];
+                const double bx = min_image(x.x - xb.x, Lx, iLx);
+                const double by = min_image(x.y - xb.y, Ly, iLy);
+                const double bz = min_image(x.z - xb.z, Lz, iLz);
+                if ((bx * bx + by * by) + bz * bz > S.disp2) {
+                    *a.flag_set = 1;
+                    if (a.check_period > 1 && since1 == a.check_period) latch(st, 10 /*DANGEROUS_BUILD*/, 0);
+                }
+            }
         } else {
             if (a.mode == MODE_LAST) a.vel_out[i] = v;
             if (MIXED) {

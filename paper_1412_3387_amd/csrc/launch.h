@@ -49,6 +49,9 @@ struct LaunchCtx {
     int32_t *flag;                 // rebuild flag read by the rebuild kernels
     int32_t *build_count;
     uint32_t *step_counter;        // advanced by the binning launch when set (graph steps)
+    int32_t *since;                // steps since the last build: the binning launch resets it on a
+                                   // build and otherwise adds since_inc (1 in step(), 0 elsewhere)
+    int32_t since_inc;
     Status *status;
     double *partials;              // 3 doubles per wave
     double *thermo;                // 4 doubles per system
@@ -71,6 +74,8 @@ struct ForceLaunch {
     int32_t energy;   // write the energy into force.w
     int32_t mixed;
     int32_t pair;     // one Pair for every system of the launch, or -1 = mixed batch
+    const int32_t *since;   // steps since the last build before this step (device), or nullptr
+    int32_t check_period;   // displacement check every this many steps since the build (>= 1)
 };
 
 void launch_bin(const LaunchCtx &L, const double4 *pos);
@@ -85,6 +90,8 @@ size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
 int force_row_over_read();
 int force_halo_entry_bytes(int pair);
 size_t fast_build_lds_bytes(int nlist_cap);
+int nlist_lanes_per_row();  // lanes that scan one row in the framed build
+int nlist_block();          // threads per workgroup of the framed build
 size_t build_plan_bytes(int64_t tiles);
 hipError_t prepare_nlist(int nlist_cap);
 // Raises the dynamic-LDS limit of the rare-tile force kernels (init time).

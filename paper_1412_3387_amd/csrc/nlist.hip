@@ -56,11 +56,16 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
                                              int32_t *__restrict__ cell_count,
                                              int32_t *__restrict__ cell_idx, int cell_cap,
                                              const int32_t *__restrict__ flag, Status *st,
-                                             uint32_t *step_counter, int32_t *slow_n, int32_t *rare_n)
+                                             uint32_t *step_counter, int32_t *slow_n, int32_t *rare_n,
+                                             int32_t *since, int since_inc)
 {
     // the binning launch follows every fused step launch: it also advances
-    // the device step counter read by graph-replayed steps
-    if (step_counter && blockIdx.x == 0 && threadIdx.x == 0) *step_counter += 1u;
+    // the device step counter read by graph-replayed steps, and the count of
+    // steps since the last build read by the displacement check
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (step_counter) *step_counter += 1u;
+        if (since) *since = *flag ? 0 : *since + since_inc;
+    }
     if (*flag == 0) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *slow_n = 0;
@@ -486,7 +491,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 #pragma unroll
             for (int b = 0; b < kMaxBondCap; ++b) part[b] = -1;
             if (active) {
-                const int64_t prow = (row0 + tag[i]) * S.bond_cap;
+                const int64_t prow = (row0 + tag[i]) * S.bond_stride;
                 for (int b = 0; b < S.bond_cap && b < kMaxBondCap; ++b) part[b] = partners[prow + b];
             }
         }
@@ -1316,7 +1321,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 const int32_t it = (int32_t)(row0 + r0 + t);
                 int32_t part[kMaxBondCap];
                 if constexpr (EXCL) {
-                    const int64_t prow = (row0 + tag[it]) * S.bond_cap;
+                    const int64_t prow = (row0 + tag[it]) * S.bond_stride;
 #pragma unroll
                     for (int bnd = 0; bnd < kMaxBondCap; ++bnd)
                         part[bnd] = bnd < S.bond_cap ? partners[prow + bnd] : -1;
@@ -1482,7 +1487,7 @@ void launch_bin(const LaunchCtx &L, const double4 *pos)
     const int blocks = capped(((int64_t)L.tiles_all * kWave + 255) / 256);
     hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.tprefix_all, L.n_sys,
                        L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.status,
-                       L.step_counter, L.slow_n, L.rare_n);
+                       L.step_counter, L.slow_n, L.rare_n, L.since, L.since_inc);
 }
 
 void launch_cell_sort(const LaunchCtx &L, const double4 *pos)
@@ -1514,6 +1519,9 @@ int nlist_row_stride(int cap)
     if (((r / 2) & 1) == 0) r += 2;
     return r;
 }
+
+int nlist_lanes_per_row() { return kWave; }
+int nlist_block() { return kFastThreads; }
 
 size_t fast_build_lds_bytes(int cap) { return sizeof(FastShared) + (size_t)kTile * nlist_row_stride(cap) * 2; }
 

@@ -74,7 +74,12 @@ bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         if (q.halo_cap < 0 || q.halo_cap > 65535) return false;
         if (q.tpp_force < 0 || q.tpp_force > 16 || (q.tpp_force & (q.tpp_force - 1))) return false;
         if (q.bond_cap < 0 || q.bond_cap > kMaxBondCap) return false;
-        if (q.check_period < 0) return false;
+        if (q.check_period < 0 || q.check_period != p[0].check_period) return false;
+        // the build's launch shape is fixed (reported by hoomd_autotune); the
+        // force pass runs 64 rows x tpp_force lanes per workgroup
+        if (q.tpp_nlist != 0 && q.tpp_nlist != nlist_lanes_per_row()) return false;
+        if (q.block_nlist != 0 && q.block_nlist != nlist_block()) return false;
+        if (q.block_force != 0 && (q.tpp_force == 0 || q.block_force != 64 * q.tpp_force)) return false;
         if (b.n_local < 0 || b.n_cap < b.n_local || b.n_cap > (int64_t)1 << 30) return false;
         if (b.n_bonds < 0 || (b.n_bonds > 0 && q.bond_cap == 0)) return false;
         const double rl = pair_cut(q) + q.r_buff;
@@ -167,6 +172,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         S.tile0_all = (int32_t)tile_all;
         S.pair = q.pair;
         S.bond_cap = q.bond_cap;
+        S.bond_stride = Lo.bond_cap;  // the partner table's row stride, shared by all systems
         S.rc2 = rc * rc;
         S.rl2 = rl * rl;
         S.disp2 = 0.25 * q.r_buff * q.r_buff;
@@ -273,6 +279,7 @@ struct hoomd_ctx {
     bool built;        // a neighbour list exists for the current rows
     int64_t ghosts;    // ghost rows appended over all systems (no sorting then)
     int tpp_nlist, block_nlist, tpp_force, block_force;
+    int check_period;  // displacement check every this many steps after a build
     int last_log_rows;
     uint64_t steps_done;
     // phase timing (hoomd_profile)
@@ -307,8 +314,8 @@ void default_tuning(hoomd_ctx *c)
     // workgroup; the force pass runs W lanes per row, one tile per 64 W
     // threads
     const double per_cu = (double)c->lay.tiles_local * 64.0 / 256.0;
-    c->tpp_nlist = 4;
-    c->block_nlist = 256;
+    c->tpp_nlist = nlist_lanes_per_row();
+    c->block_nlist = nlist_block();
     c->tpp_force = per_cu > 2048 ? 4 : 8;
     if (c->prm[0].tpp_force > 0) c->tpp_force = c->prm[0].tpp_force;
     c->block_force = 64 * c->tpp_force;
@@ -335,16 +342,19 @@ size_t mark(hoomd_ctx *c)
 }
 
 // Device flags: 0 and 1 rebuild flags of the two buffer parities, 2 the flag
-// of explicit builds, 4 build counter, 5 step counter of replayed steps, 6
+// of explicit builds, 3 steps since the last build, 4 build counter, 5 step counter of replayed steps, 6
 // tiles passed from the framed build to the general one, 7 tiles the force
 // pass handles in its second launch.
 int32_t *flag_ptr(hoomd_ctx *c, int k) { return ws_ptr<int32_t>(c, c->lay.flags) + k; }
 
 // Queue the rebuild sequence: bin -> per-cell sort -> neighbour rows.  Every
-// kernel returns at once when *flag is clear.
-void queue_rebuild(hoomd_ctx *c, const double4 *pos, const int32_t *tag, int32_t *flag)
+// kernel returns at once when *flag is clear.  The binning launch also keeps
+// the count of steps since the last build: reset by a build, else advanced by
+// since_inc (1 after a step, 0 after an explicit build request).
+void queue_rebuild(hoomd_ctx *c, const double4 *pos, const int32_t *tag, int32_t *flag, int since_inc)
 {
     c->L.flag = flag;
+    c->L.since_inc = since_inc;
     launch_bin(c->L, pos);
     launch_cell_sort(c->L, pos);
     launch_nlist(c->L, pos, tag, c->tpp_nlist, c->block_nlist);
@@ -357,6 +367,8 @@ ForceLaunch base_force(hoomd_ctx *c)
     F.force = c->arr.force;
     F.mixed = c->mixed;
     F.pair = c->pair_uniform;
+    F.since = flag_ptr(c, 3);
+    F.check_period = c->check_period;
     return F;
 }
 
@@ -377,7 +389,7 @@ void queue_mid_step(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V, b
     F.flag_set = flag_ptr(c, p);
     F.flag_clear = flag_ptr(c, p ^ 1);
     launch_force(c->L, F, c->tpp_force, c->block_force);
-    queue_rebuild(c, P[p ^ 1], c->arr.tag, flag_ptr(c, p));
+    queue_rebuild(c, P[p ^ 1], c->arr.tag, flag_ptr(c, p), 1);
 }
 
 // Pairs of middle steps in the long captured run: one graph launch per 16
@@ -461,6 +473,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
         return HOOMD_E_ARG;
     }
     c->built = false;
+    c->check_period = params[0].check_period > 1 ? params[0].check_period : 1;
     c->last_log_rows = 0;
     c->steps_done = 0;
 
@@ -491,6 +504,8 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.has_bonds = nb_total > 0;
     L.flag = flag_ptr(c, 0);
     L.build_count = flag_ptr(c, 4);
+    L.since = flag_ptr(c, 3);
+    L.since_inc = 0;
     L.slow_list = ws_ptr<int32_t>(c, lay.slow_list);
     L.slow_n = flag_ptr(c, 6);
     L.rare_list = ws_ptr<int32_t>(c, lay.rare_list);
@@ -606,7 +621,7 @@ int build_nlist(hoomd_ctx *c, int32_t force_rebuild)
         launch_set_flag(c->L, flag, 0);
         launch_disp_check(c->L, pos, flag);
     }
-    queue_rebuild(c, pos, c->arr.tag, flag);
+    queue_rebuild(c, pos, c->arr.tag, flag, 0);
     c->built = true;
     return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
 }
@@ -714,7 +729,7 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
             launch_set_flag(c->L, flag, 1);
         }
         const size_t r0 = mark(c);
-        queue_rebuild(c, P[p ^ 1], tag, flag);
+        queue_rebuild(c, P[p ^ 1], tag, flag, 1);
         if (c->profiling) c->ev_rebuild.emplace_back(r0, mark(c));
         ++s;
     }
@@ -889,6 +904,9 @@ int hoomd_get_layout(hoomd_ctx *c, int32_t sys, hoomd_layout *out)
     out->cell_offset = S.cell0;
     out->tile_offset = S.tile0;
     out->general_tiles = c->L.slow_n;
+    out->rare_tiles = c->L.rare_n;
+    out->halo_lds = c->L.halo_lds;
+    out->pad_ = 0;
     return HOOMD_OK;
 }
 

@@ -81,3 +81,52 @@ def test_init_rejects_bad_arguments_without_device_work(hlib):
     assert hlib.hoomd_init(C.byref(h), C.byref(p), 1, C.byref(box), C.byref(arr), 1, 16, None) == 3
     assert hlib.build_nlist(None, 1) == 1 and hlib.step(None, 0, 1, 0) == 1
     assert hlib.compute_forces(None, 0, 0) == 1
+
+
+def test_tuning_and_check_period_fields_are_validated(hlib):
+    """The launch-shape fields accept 0 or the values the library runs
+    (hoomd_autotune reports them); the check period must be >= 0 and equal in
+    all systems."""
+    from paper_1412_3387_amd import binding as B
+
+    def ws(**kw):
+        p = B.ModelParams(precision=B.MIXED, **kw).to_c(0.8442)
+        box = B.Box()
+        for a in range(3):
+            box.L[a] = 16.796
+            box.periodic[a] = 1
+        box.n_local = box.n_cap = 4000
+        return hlib.hoomd_workspace_bytes(C.byref(p), 1, C.byref(box))
+
+    assert ws() > 0
+    assert ws(tpp_nlist=64, block_nlist=512) > 0
+    assert ws(tpp_nlist=4) == 0 and ws(block_nlist=256) == 0
+    for w in (1, 2, 4, 8, 16):
+        assert ws(tpp_force=w, block_force=64 * w) > 0
+        assert ws(tpp_force=w, block_force=64 * w + 64) == 0
+    assert ws(tpp_force=3) == 0 and ws(tpp_force=32) == 0
+    assert ws(block_force=256) == 0  # a block size needs an explicit lane count
+    assert ws(check_period=0) > 0 and ws(check_period=5) > 0 and ws(check_period=-1) == 0
+    # two systems with different check periods
+    ps = (B.Params * 2)(B.ModelParams(check_period=2).to_c(0.8442), B.ModelParams(check_period=3).to_c(0.8442))
+    boxes = (B.Box * 2)()
+    for b in boxes:
+        for a in range(3):
+            b.L[a] = 16.796
+            b.periodic[a] = 1
+        b.n_local = b.n_cap = 4000
+    assert hlib.hoomd_workspace_bytes(ps, 2, boxes) == 0
+    ps[1].check_period = 2
+    assert hlib.hoomd_workspace_bytes(ps, 2, boxes) > 0
+
+
+def test_layout_struct_matches_header(hlib):
+    """hoomd_layout as the binding declares it has the header's fields, in
+    order (names parsed from the header)."""
+    import re
+    from paper_1412_3387_amd import binding as B
+    txt = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^}]*)\} hoomd_layout;", txt).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b(\w+)(?:\[\d+\])?;", body)
+    assert names == [f[0] for f in B.Layout._fields_]

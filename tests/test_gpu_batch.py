@@ -85,5 +85,5 @@ def test_batch_short_run_fp64(orc, B):
                                      bonds=sy.bonds, bond_prm=[30.0, 1.5])
         x, v, f, tag = ctx.host_state(k)
         x, v = by_tag(tag, x, v)
-        assert np.max(np.abs(min_image_diff(x, xo, sy.L))) < 1e-9
-        assert np.max(np.abs(v - vo)) < 1e-8
+        assert np.max(np.abs(min_image_diff(x, xo, sy.L))) <= 1e-10
+        assert np.max(np.abs(v - vo)) <= 1e-10

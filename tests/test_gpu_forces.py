@@ -33,7 +33,7 @@ def _forces(B, sys_, p, timestep=0, flags=1):
 @pytest.mark.parametrize("w", [1, 2, 4, 8, 16])
 def test_lj_forces_small(orc, B, prec, w):
     s = inputs.lj_small()
-    p = B.ModelParams(precision=prec, tpp_force=w, block_force=128)
+    p = B.ModelParams(precision=prec, tpp_force=w, block_force=64 * w)
     f, th, _ = _forces(B, s, p)
     F, u, wv, nc = orc.pair_forces("lj", s.pos, s.L, LJ)
     assert frel(f[:, :3], F) <= TOL[prec]

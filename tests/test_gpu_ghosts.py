@@ -28,7 +28,11 @@ def _dir_to(s_from, s_to, g=3):
     return k if k < 13 else k - 1
 
 
-def _loopback(B, sd, precision=1, update_shift=None):
+def _rec_bytes(fields):
+    return 8 * (3 * bool(fields & 1) + 3 * bool(fields & 2) + bool(fields & 4))
+
+
+def _loopback(B, sd, precision=1, update_shift=None, fields=None, update_dv=None):
     import torch
     full = sd.full
     L = full.L
@@ -45,9 +49,10 @@ def _loopback(B, sd, precision=1, update_shift=None):
         params.append(B.ModelParams(precision=precision, nlist_cap=160))
     ctx = B.Context(params, systems)
     dev = ctx.device
-    fields = B.FIELD_POS | B.FIELD_TAG
+    if fields is None:
+        fields = B.FIELD_POS | B.FIELD_TAG
     cap = 8 * max(ctx.n_local)
-    rec = 32
+    rec = _rec_bytes(fields)
     sends, counts, offs = [], [], []
     for s in range(27):
         buf = torch.zeros(cap * rec, dtype=torch.uint8, device=dev)
@@ -74,10 +79,13 @@ def _loopback(B, sd, precision=1, update_shift=None):
     ctx.check()
     out = dict(ctx=ctx, counts=hc, offsets=ho, sends=sends, n_recv=n_recv)
     if update_shift is not None:
-        # move every local of the other subdomains, re-gather, re-send
+        # move every local of the other subdomains (and change their
+        # velocities), re-gather, re-send
         for s in range(1, 27):
             o, n = ctx.offsets[s], ctx.n_local[s]
             ctx.pos[o:o + n, :3] += torch.as_tensor(update_shift, device=dev, dtype=torch.float64)
+            if update_dv is not None:
+                ctx.vel[o:o + n, :3] += torch.as_tensor(update_dv, device=dev, dtype=torch.float64)
             ctx.pack_ghosts(s, sd.lo(s), sd.hi(s), W, B.GHOST_UPDATE, fields, sends[s], cap,
                             counts[s], offs[s])
         recv = gather_recv()
@@ -87,25 +95,36 @@ def _loopback(B, sd, precision=1, update_shift=None):
 
 
 @pytest.mark.parametrize("cells", [12, 60])
-def test_ghost_select_pack_exact(orc, B, cells):
+@pytest.mark.parametrize("with_vel", [False, True])
+def test_ghost_select_pack_exact(orc, B, cells, with_vel):
+    """Send lists and records against the oracle's masks, with and without
+    velocities in the record (DPD ghosts carry velocities and IDs)."""
     sd = inputs.lj_subdomain_box(grid=3, cells=cells)
-    r = _loopback(B, sd)
+    fields = B.FIELD_POS | B.FIELD_TAG | (B.FIELD_VEL if with_vel else 0)
+    rec = _rec_bytes(fields)
+    r = _loopback(B, sd, fields=fields)
     for s in (0, 5, 13, 26):
         loc = sd.local(s)
         m = orc.ghost_masks(sd.full.pos[loc], sd.lo(s), sd.hi(s), W)
         cnt, off, idx = orc.ghost_list(m)
         assert np.array_equal(r["counts"][s], cnt) and np.array_equal(r["offsets"][s], off)
-        buf = r["sends"][s][: len(idx) * 32].cpu().numpy()
-        recs = buf.view(np.float64).reshape(-1, 4)
-        tags = buf.view(np.int32).reshape(-1, 8)[:, 6]
+        buf = r["sends"][s][: len(idx) * rec].cpu().numpy()
+        recs = buf.view(np.float64).reshape(-1, rec // 8)
+        tags = buf.view(np.int32).reshape(-1, rec // 4)[:, -2]
         assert np.array_equal(tags, loc[idx])
         assert np.array_equal(recs[:, :3], sd.full.pos[loc[idx]])
+        if with_vel:
+            assert np.array_equal(recs[:, 3:6], sd.full.vel[loc[idx]])
 
 
 @pytest.mark.parametrize("cells", [12, 60])
-def test_ghost_receive_set_and_local_forces(orc, B, cells):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ghost_receive_set_and_local_forces(orc, B, cells, prec):
+    """Receive set of subdomain 0 exact; its local forces from locals +
+    ghosts equal the full-box forces (FP64 within 1e-12 F_rms, mixed within
+    1e-5 F_rms)."""
     sd = inputs.lj_subdomain_box(grid=3, cells=cells)
-    r = _loopback(B, sd, precision=0)
+    r = _loopback(B, sd, precision=prec)
     ctx = r["ctx"]
     full = sd.full
     ridx, rimg = orc.ghost_receive(full.pos, sd.owner, 0, full.L, sd.lo(0), sd.hi(0), W)
@@ -127,13 +146,19 @@ def test_ghost_receive_set_and_local_forces(orc, B, cells):
     pick = np.sort(rng.choice(n0, min(n0, 256), replace=False))
     F, u, w, nc = orc.pair_forces("lj", full.pos, full.L, LJ, which=loc[pick])
     fr = np.sqrt(np.mean(np.sum(F * F, axis=1)))
-    assert np.max(np.abs(f[pick] - F)) <= 1e-12 * fr
+    err = np.max(np.sqrt(np.sum((f[pick] - F) ** 2, axis=1))) / fr
+    assert err <= (1e-12 if prec == 0 else 1e-5), err
 
 
-def test_ghost_update_mode(orc, B):
-    sd = inputs.lj_subdomain_box(grid=3, cells=12)
+@pytest.mark.parametrize("cells", [12, 60])
+def test_ghost_update_mode(orc, B, cells):
+    """UPDATE re-gathers positions and velocities of the stored send lists:
+    the same ghosts arrive, moved, with their new velocities."""
+    sd = inputs.lj_subdomain_box(grid=3, cells=cells)
     shift = np.array([0.013, -0.007, 0.002])
-    r = _loopback(B, sd, update_shift=shift)
+    dv = np.array([0.5, -0.25, 0.125])
+    fields = B.FIELD_POS | B.FIELD_VEL | B.FIELD_TAG
+    r = _loopback(B, sd, update_shift=shift, fields=fields, update_dv=dv)
     ctx = r["ctx"]
     moved = inputs.wrap(sd.full.pos + shift, sd.full.L)
     # ownership is unchanged by the update: the same particles, new images
@@ -145,6 +170,8 @@ def test_ghost_update_mode(orc, B):
     og, oref = np.argsort(gtag), np.argsort(ridx)
     assert np.array_equal(gtag[og], ridx[oref])
     assert np.allclose(gpos[og], rimg[oref] + shift, atol=1e-12)
+    gvel = ctx.vel[o + n0:o + n0 + r["n_recv"], :3].cpu().numpy()
+    assert np.array_equal(gvel[og], sd.full.vel[ridx[oref]] + dv)
     del moved
 
 

@@ -78,7 +78,7 @@ def test_neighbor_sets_ragged_sizes(orc, B, n):
     else:
         s = inputs.lj_fluid(n, 3, 4)
         pos, L = s.pos, s.L
-    ctx = _ctx(B, pos, np.zeros_like(pos), L, tpp_nlist=4)
+    ctx = _ctx(B, pos, np.zeros_like(pos), L)
     ctx.build_nlist(True)
     ctx.check()
     assert neighbor_sets_equal(orc, ctx, pos, L, 2.5, 0.4) == []
