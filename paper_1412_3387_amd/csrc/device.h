@@ -140,6 +140,13 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double scale, int
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+// Workgroup barrier for kernels whose waves share data only through LDS:
+// waits until this wave's LDS (and scalar) accesses are done, but not for its
+// global loads and stores, which stay in flight across the barrier (a full
+// __syncthreads() also waits for those).  The memory clobber keeps the
+// compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
     const int l = lane_id();

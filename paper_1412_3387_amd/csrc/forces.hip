@@ -410,14 +410,16 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
             // counted from the last build; a rebuild at the first check after a
             // build may have come late when the period is above one (Sec. 6.1:
             // a dangerous build)
-            const int since1 = a.since ? *a.since + 1 : 1;
+            const int since1 = a.since ? a.since[s] + 1 : 1;
             if (a.check_period <= 1 || since1 % a.check_period == 0) {
                 const double4 xb = xbuild[i];
                 const double bx = min_image(x.x - xb.x, Lx, iLx);
                 const double by = min_image(x.y - xb.y, Ly, iLy);
                 const double bz = min_image(x.z - xb.z, Lz, iLz);
                 if ((bx * bx + by * by) + bz * bz > S.disp2) {
+                    // this system's list is rebuilt after the step
                     *a.flag_set = 1;
+                    a.sflag_set[s] = 1;
                     if (a.check_period > 1 && since1 == a.check_period) latch(st, 10 /*DANGEROUS_BUILD*/, 0);
                 }
             }
@@ -464,7 +466,10 @@ template <int W, bool MIXED, int POT, bool LOG>
 __global__ __launch_bounds__(1024) void k_force(FORCE_ARGS)
 {
     extern __shared__ double lds[];
-    if (a.flag_clear && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
+    if (a.flag_clear && blockIdx.x == 0) {
+        if (threadIdx.x == 0) *a.flag_clear = 0;
+        for (int q = threadIdx.x; q < n_sys; q += blockDim.x) a.sflag_clear[q] = 0;
+    }
     const int tile = die_tile(blockIdx.x, gridDim.x);
     const int32_t hn = halo_n[tile];
     if (hn < 0 || (hn & 0xFFFF) > halo_lds) return;
@@ -536,11 +541,18 @@ __global__ __launch_bounds__(1024) void k_thermo_reduce(const SysDev *__restrict
 
 __global__ void k_set_flag(int32_t *flag, int32_t v) { *flag = v; }
 
-// Sets *flag when some local particle moved more than r_buff / 2 (minimum
-// image) since the positions recorded at the last build.
+__global__ void k_set_flags(int32_t *flag, int32_t *sflag, int n_sys, int32_t v)
+{
+    if (threadIdx.x == 0) *flag = v;
+    for (int s = threadIdx.x; s < n_sys; s += blockDim.x) sflag[s] = v;
+}
+
+// Sets *flag and the flag of the particle's system when some local particle
+// moved more than r_buff / 2 (minimum image) since the positions recorded at
+// the last build.
 __global__ void k_disp_check(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
                              int n_sys, int tiles, const double4 *__restrict__ pos,
-                             const double4 *__restrict__ xbuild, int32_t *flag)
+                             const double4 *__restrict__ xbuild, int32_t *flag, int32_t *sflag)
 {
     const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (g >= tiles) return;
@@ -553,7 +565,10 @@ __global__ void k_disp_check(const SysDev *__restrict__ sys, const int32_t *__re
     const double bx = min_image(x.x - xb.x, S.L[0], S.invL[0]);
     const double by = min_image(x.y - xb.y, S.L[1], S.invL[1]);
     const double bz = min_image(x.z - xb.z, S.L[2], S.invL[2]);
-    if ((bx * bx + by * by) + bz * bz > S.disp2) *flag = 1;
+    if ((bx * bx + by * by) + bz * bz > S.disp2) {
+        *flag = 1;
+        sflag[s] = 1;
+    }
 }
 
 // rtag[row0 + tag[i]] = i over all rows of every system.
@@ -681,13 +696,18 @@ void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value)
     hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, L.stream, flag, value);
 }
 
-void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag)
+void launch_set_flags(const LaunchCtx &L, int32_t *flag, int32_t *sflag, int32_t value)
+{
+    hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(256), 0, L.stream, flag, sflag, L.n_sys, value);
+}
+
+void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag, int32_t *sflag)
 {
     const int threads = 256;
     const int blocks = (L.tiles_local * kWave + threads - 1) / threads;
     if (blocks == 0) return;
     hipLaunchKernelGGL(k_disp_check, dim3(blocks), dim3(threads), 0, L.stream, L.sys,
-                       L.tprefix_local, L.n_sys, L.tiles_local, pos, L.xbuild, flag);
+                       L.tprefix_local, L.n_sys, L.tiles_local, pos, L.xbuild, flag, sflag);
 }
 
 void launch_rtag(const LaunchCtx &L, const int32_t *tag)

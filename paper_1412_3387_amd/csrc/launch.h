@@ -46,11 +46,12 @@ struct LaunchCtx {
     int32_t *slow_n;               // their number (cleared by the binning launch)
     int32_t *rare_list;            // tiles the force pass handles in its second launch
     int32_t *rare_n;               // their number (cleared by the binning launch)
-    int32_t *flag;                 // rebuild flag read by the rebuild kernels
+    int32_t *flag;                 // rebuild flag read by the rebuild kernels (some system needs one)
+    int32_t *sflag;                // per-system rebuild flags of the same slot (n_sys entries)
     int32_t *build_count;
     uint32_t *step_counter;        // advanced by the binning launch when set (graph steps)
-    int32_t *since;                // steps since the last build: the binning launch resets it on a
-                                   // build and otherwise adds since_inc (1 in step(), 0 elsewhere)
+    int32_t *since;                // per system, steps since its last build: the binning launch resets
+                                   // it on a build and otherwise adds since_inc (1 in step(), 0 elsewhere)
     int32_t since_inc;
     Status *status;
     double *partials;              // 3 doubles per wave
@@ -67,6 +68,8 @@ struct ForceLaunch {
     void *force;
     int32_t *flag_set;
     int32_t *flag_clear;
+    int32_t *sflag_set;     // per-system flags of flag_set / flag_clear (n_sys entries each)
+    int32_t *sflag_clear;
     uint32_t timestep;
     const uint32_t *timestep_ptr;  // when set, the timestep is read from the device
     int32_t mode;
@@ -74,7 +77,7 @@ struct ForceLaunch {
     int32_t energy;   // write the energy into force.w
     int32_t mixed;
     int32_t pair;     // one Pair for every system of the launch, or -1 = mixed batch
-    const int32_t *since;   // steps since the last build before this step (device), or nullptr
+    const int32_t *since;   // per system, steps since its last build before this step, or nullptr
     int32_t check_period;   // displacement check every this many steps since the build (>= 1)
 };
 
@@ -84,8 +87,10 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
 void launch_force(const LaunchCtx &L, const ForceLaunch &F, int w, int block);
 void launch_thermo_reduce(const LaunchCtx &L, int w, int log_row, double timestep);
 void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value);
+// Sets a rebuild flag and all per-system flags of its slot.
+void launch_set_flags(const LaunchCtx &L, int32_t *flag, int32_t *sflag, int32_t value);
 void launch_rtag(const LaunchCtx &L, const int32_t *tag);
-void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag);
+void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag, int32_t *sflag);
 size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
 int force_row_over_read();
 int force_halo_entry_bytes(int pair);

@@ -55,16 +55,18 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
                                              const double4 *__restrict__ pos,
                                              int32_t *__restrict__ cell_count,
                                              int32_t *__restrict__ cell_idx, int cell_cap,
-                                             const int32_t *__restrict__ flag, Status *st,
+                                             const int32_t *__restrict__ flag,
+                                             const int32_t *__restrict__ sflag, Status *st,
                                              uint32_t *step_counter, int32_t *slow_n, int32_t *rare_n,
                                              int32_t *since, int since_inc)
 {
     // the binning launch follows every fused step launch: it also advances
-    // the device step counter read by graph-replayed steps, and the count of
-    // steps since the last build read by the displacement check
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (step_counter) *step_counter += 1u;
-        if (since) *since = *flag ? 0 : *since + since_inc;
+    // the device step counter read by graph-replayed steps, and each system's
+    // count of steps since its last build read by the displacement check
+    if (blockIdx.x == 0) {
+        if (step_counter && threadIdx.x == 0) *step_counter += 1u;
+        if (since)
+            for (int s = threadIdx.x; s < n_sys; s += blockDim.x) since[s] = sflag[s] ? 0 : since[s] + since_inc;
     }
     if (*flag == 0) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
     const int waves = (int)(gridDim.x * blockDim.x) >> 6;
     for (int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); g < tiles; g += waves) {
         const int s = find_sys(tprefix, n_sys, g);
+        if (!sflag[s]) continue;  // this system keeps its list
         const SysDev &S = sys[s];
         const int r = (g - S.tile0_all) * kTile + lane;
         const bool valid = r < S.n_total;
@@ -133,13 +136,16 @@ __device__ __forceinline__ void cell_sort_waves(int64_t wfirst, int64_t wstep, c
                                                 int n_sys, const double4 *__restrict__ pos, int64_t n_cells,
                                                 const int32_t *__restrict__ cell_count,
                                                 int32_t *__restrict__ cell_size, int32_t *__restrict__ cell_idx,
-                                                float4 *__restrict__ cell_xf, int cell_cap)
+                                                float4 *__restrict__ cell_xf, int cell_cap,
+                                                const int32_t *__restrict__ sflag)
 {
     const int lane = lane_id();
     for (int64_t c = wfirst; c < n_cells; c += wstep) {
+        const int s = find_sys_cell(sys, n_sys, c);
+        if (!sflag[s]) continue;  // this system keeps its list
         int m = cell_count[c];
         m = m < cell_cap ? m : cell_cap;
-        const SysDev &S = sys[find_sys_cell(sys, n_sys, c)];
+        const SysDev &S = sys[s];
         const int64_t key = c - S.cell0;
         const int cx = (int)(key % S.bins[0]), cy = (int)((key / S.bins[0]) % S.bins[1]),
                   cz = (int)(key / ((int64_t)S.bins[0] * S.bins[1]));
@@ -248,6 +254,8 @@ __device__ __forceinline__ int block_scan(int32_t *a, int n, int32_t *scan)
 }
 
 // The same with wave-level shuffles: two barriers instead of 2 log2(NT).
+// The barriers order LDS accesses only (the caller's global accesses may stay
+// in flight).
 template <int NT>
 __device__ __forceinline__ int block_scan_w(int32_t *a, int n, int32_t *wsum)
 {
@@ -270,7 +278,7 @@ __device__ __forceinline__ int block_scan_w(int32_t *a, int n, int32_t *wsum)
         if (lane >= off) inc += y;
     }
     if (lane == kWave - 1) wsum[w] = inc;
-    __syncthreads();
+    lds_barrier();
     int before = 0, total = 0;
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
@@ -285,7 +293,7 @@ __device__ __forceinline__ int block_scan_w(int32_t *a, int n, int32_t *wsum)
             a[b + k] = run;
             run += v[k];
         }
-    __syncthreads();
+    lds_barrier();
     return total;
 }
 
@@ -689,7 +697,6 @@ constexpr int kBoxWords = kBoxMax / 32;
 constexpr int kUMax = 256;           // distinct cells of a framed tile
 constexpr int kFastSlotMax = 8192;   // members of a framed tile's stencil cells
 constexpr int kRuns = 9;
-constexpr float kBand = 1.0f / 1024.0f;
 static_assert(kUMax <= 256, "slot map holds distinct cells as bytes");
 
 // DPP lane move within rows of 16 lanes (every lane of the wave active).
@@ -750,7 +757,8 @@ struct FastShared {
     int32_t scan[kFastWaves];            // per-wave totals of the block scans
     uint8_t smap[kFastChunk];            // distinct cell of each slot of the chunk
     double xref[3];                      // first row's position: the frame reference
-    int32_t info[4];                     // distinct cells, per-pair image flag, longest row, slots
+    int32_t info[5];                     // distinct cells, per-pair image flag, longest row, slots,
+                                         // FP32 decision band (float bits)
 };
 
 // Per-tile plan of the framed build, written by k_cells_and_plan and read by
@@ -836,7 +844,8 @@ struct PlanShared {
 __device__ __forceinline__ void plan_tiles(
     PlanShared &ps, int pb, int npb, const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
     int n_sys, int tiles, const double4 *__restrict__ pos, const int32_t *__restrict__ cell_count, int cell_cap,
-    double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan)
+    double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan,
+    const int32_t *__restrict__ sflag)
 {
     uint32_t *box = ps.box;
     int32_t *bpre = ps.bpre;
@@ -848,6 +857,7 @@ __device__ __forceinline__ void plan_tiles(
     die_range(pb, npb, tiles, tfirst, tend, tstep);
     for (int tile = (int)tfirst; tile < tend; tile += tstep) {
         const int s = find_sys(tprefix, n_sys, tile);
+        if (!sflag[s]) continue;  // this system keeps its list
         const SysDev &S = sys[s];
         const double Ls[3] = {S.L[0], S.L[1], S.L[2]};
         const int bins[3] = {S.bins[0], S.bins[1], S.bins[2]};
@@ -1050,7 +1060,17 @@ __device__ __forceinline__ void plan_tiles(
         int pp = 0;
         for (int a = 0; a < 3; ++a)
             if (per[a] && (double)(ehi[a] - elo[a] + 3) * (Ls[a] / bins[a]) >= 0.5 * Ls[a]) pp = 1;
-        if (lane == 0) plan.hdr[tile] = make_int4(nu, nslot, pp, 0);
+        // relative band around r_list^2 inside which the FP32 distance of a
+        // candidate cannot decide the test: a bound on the FP32 rounding of
+        // frame coordinates up to E in magnitude (cell-relative position,
+        // cell corner, their sum, the row's position: |error| <= 2^-24 (4E +
+        // |dx|) per separation), propagated through r^2 and doubled
+        const double Ef = (double)fext + (double)fmaxf(cw[0], fmaxf(cw[1], cw[2]));
+        const double rl = sqrt(rl2);
+        const double eta = 0x1p-24 * (4.0 * Ef + 1.01 * rl);
+        const double dr2 = 2.0 * sqrt(3.0) * rl * eta + 3.0 * eta * eta + 3.0 * 0x1p-24 * rl2 * 1.01;
+        const float band = (float)(2.0 * (dr2 / rl2 + 3.0 * 0x1p-24));
+        if (lane == 0) plan.hdr[tile] = make_int4(nu, nslot, pp, __float_as_int(band));
     }
 }
 
@@ -1063,16 +1083,16 @@ __global__ __launch_bounds__(kWave) void k_cells_and_plan(
     const double4 *__restrict__ pos, int64_t n_cells, const int32_t *__restrict__ cell_count,
     int32_t *__restrict__ cell_size, int32_t *__restrict__ cell_idx, float4 *__restrict__ cell_xf, int cell_cap,
     double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan,
-    const int32_t *__restrict__ flag)
+    const int32_t *__restrict__ flag, const int32_t *__restrict__ sflag)
 {
     if (*flag == 0) return;
     if ((int)blockIdx.x < n_sort) {
         cell_sort_waves<CPL>(blockIdx.x, n_sort, sys, n_sys, pos, n_cells, cell_count, cell_size, cell_idx, cell_xf,
-                             cell_cap);
+                             cell_cap, sflag);
     } else {
         __shared__ PlanShared ps;
         plan_tiles(ps, (int)blockIdx.x - n_sort, (int)gridDim.x - n_sort, sys, tprefix, n_sys, tiles, pos,
-                   cell_count, cell_cap, xbuild, slow_list, slow_n, plan);
+                   cell_count, cell_cap, xbuild, slow_list, slow_n, plan, sflag);
     }
 }
 
@@ -1085,6 +1105,17 @@ __global__ void k_zero_counts(int32_t *__restrict__ cell_count, int64_t n_cells,
         cell_count[c] = 0;
 }
 
+// A plan header read through the vector memory path: the index gets a zero
+// from a vector register that the compiler cannot see through, so the read is
+// not made a scalar one (a pending scalar read would be waited for at the
+// next LDS barrier).
+__device__ __forceinline__ int4 next_header(const int4 *hdr, int tile)
+{
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    return hdr[tile + zero];
+}
+
 template <bool EXCL>
 __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_build_fast(
     const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
@@ -1095,7 +1126,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
     int32_t *__restrict__ halo, int32_t *__restrict__ halo_n, int halo_cap, PlanPtrs plan,
     int halo_lds, int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n,
     int32_t *__restrict__ cell_count, int64_t n_cells,
-    const int32_t *__restrict__ flag, int32_t *build_count, Status *st)
+    const int32_t *__restrict__ flag, const int32_t *__restrict__ sflag, int32_t *build_count, Status *st)
 {
     if (*flag == 0) return;
     // the binning counts, read by the cell sort and the plans, back to zero
@@ -1113,11 +1144,21 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
     int64_t tfirst, tend;
     int tstep;
     die_range(blockIdx.x, gridDim.x, tiles, tfirst, tend, tstep);
-    // the loader wave reads each tile's plan header one tile ahead
-    int4 hd_next = make_int4(-1, 0, 0, 0);
-    if (wv == 1 && tfirst < tend) hd_next = plan.hdr[tfirst];
+    // each tile's plan header is read one tile ahead, by every thread, with
+    // no branch, so that the read stays in flight until its use
+    int4 hd_next = next_header(plan.hdr, tfirst < tend ? tfirst : 0);
     for (int tile = (int)tfirst; tile < tend; tile += tstep) {
         const int s = find_sys(tprefix, n_sys, tile);
+        if (!sflag[s]) {
+            // a system that keeps its list: its tile goes back on the list
+            // of the force pass's second launch if its last build put it there
+            if (tid == 0) {
+                const int32_t hn = halo_n[tile];
+                if (hn < 0 || (hn & 0xFFFF) > halo_lds) rare_list[atomicAdd(rare_n, 1)] = tile;
+            }
+            hd_next = next_header(plan.hdr, tile + tstep < tend ? tile + tstep : tile);
+            continue;
+        }
         const SysDev &S = sys[s];
         const double Ls[3] = {S.L[0], S.L[1], S.L[2]};
         const double iL[3] = {S.invL[0], S.invL[1], S.invL[2]};
@@ -1128,7 +1169,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         const double rl2 = S.rl2;
         const int r0 = (tile - S.tile0) * kTile;
 
-        __syncthreads();  // LDS of the previous tile no longer read
+        lds_barrier();  // LDS of the previous tile no longer read
         // ---- 1. the tile's plan ------------------------------------------------
         // Wave 1 does this tile's global reads and no global writes: a wave's
         // wait for a read also waits for all of its earlier writes, and the
@@ -1141,6 +1182,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 sh.info[0] = hd.x;
                 sh.info[1] = hd.z;
                 sh.info[3] = hd.y;
+                sh.info[4] = hd.w;
             }
             if (hd.x > 0) {
                 const int nu_ = hd.x < kUMax ? hd.x : kUMax;
@@ -1190,8 +1232,8 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         } else if (wv == 0) {
             sh.rown[tid] = r0 + tid < n_local ? 0 : -1;
         }
-        __syncthreads();
-        if (loader && tile + tstep < tend) hd_next = plan.hdr[tile + tstep];
+        lds_barrier();
+        hd_next = next_header(plan.hdr, tile + tstep < tend ? tile + tstep : tile);
         const int nu = uni(sh.info[0]);
         const int nslot = uni(sh.info[3]);
         if (nu <= 0 || nu > kUMax || nslot > kFastSlotMax) continue;  // built by the general kernel
@@ -1199,10 +1241,13 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         for (int q = tid; q < (nslot + 31) / 32; q += kFastThreads) sh.used[q] = 0u;
         // ---- 5. stage members a chunk at a time, scan every row's lines -------------
         const bool one_chunk = nslot <= kFastChunk;
-        const float lo_f = (float)rl2 * (1.0f - kBand), hi_f = (float)rl2 * (1.0f + kBand);
+        // FP32 distances below lo_f are hits, above hi_f misses, in between
+        // the exact FP64 test decides (the band comes with the tile's plan)
+        const double band = (double)__int_as_float(uni(sh.info[4]));
+        const float lo_f = (float)(rl2 * (1.0 - band)), hi_f = (float)(rl2 * (1.0 + band));
         for (int q0 = 0; q0 < nslot; q0 += kFastChunk) {
             const int q1 = q0 + kFastChunk < nslot ? q0 + kFastChunk : nslot;
-            __syncthreads();
+            lds_barrier();
             // slot -> distinct cell of the chunk: each cell writes its index
             // over its own slots
             for (int u = tid; u < nu; u += kFastThreads) {
@@ -1211,12 +1256,12 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 qb = qb < q1 ? qb : q1;
                 for (int q = qa; q < qb; ++q) sh.smap[q - q0] = (uint8_t)u;
             }
-            __syncthreads();
+            lds_barrier();
             // staging: one coalesced read per member (cell-relative FP32
             // position and row), moved into the frame by its cell's corner;
-            // two reads of a thread in flight at once
+            // four reads of a thread in flight at once
             {
-                constexpr int kB = 2;
+                constexpr int kB = 4;
                 for (int qb = q0 + tid; qb < q1; qb += kB * kFastThreads) {
                     int us[kB], qs[kB];
                     float4 cs[kB];
@@ -1239,7 +1284,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
             // members of a line are ordered by x (cells in x order, each sorted
             // by x): cut every line, within this chunk, to the slots within the
             // half width that its y-z distance leaves (|dx|^2 <= r_list^2 - gap^2,
@@ -1267,7 +1312,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 }
                 sh.runc[t][rr] = (uint32_t)pa | ((uint32_t)(pb > pa ? pb : pa) << 16);
             }
-            __syncthreads();
+            lds_barrier();
             // lanes to lines, one thread per row: line r takes lanes [B_r, B_r+1)
             // with B_r = r + about 55 P_r / T (P_r the members of the row's lines
             // before line r in this chunk, T all of them), so every line keeps at
@@ -1299,7 +1344,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 sh.lmask[tid] = tot > 0 ? mask : 0ull;
                 if (tot == 0 && sh.rown[tid] >= 0) sh.lb[tid][0] = 0xFF;  // nothing to scan in this chunk
             }
-            __syncthreads();
+            lds_barrier();
             for (int t = wv; t < kTile; t += kFastWaves) {
                 int ntot = uni(sh.rown[t]);
                 if (ntot < 0) continue;  // inactive row
@@ -1398,7 +1443,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 if (lane == 0) sh.rown[t] = ntot;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // ---- 6. halo numbering, rows out ------------------------------------------
         // writers: every wave but the loader
         const int wid = wv == 0 ? tid : tid - kWave;
@@ -1413,7 +1458,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
         const int nwords = (nslot + 31) / 32;
         for (int q = tid; q < nwords; q += kFastThreads) sh.wpre[q] = __popc(sh.used[q]);
-        __syncthreads();
+        lds_barrier();
         const int nhalo = uni(block_scan_w<kFastThreads>(sh.wpre, nwords, sh.scan));
         if (nhalo > halo_cap) {
             if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nhalo);
@@ -1486,7 +1531,7 @@ void launch_bin(const LaunchCtx &L, const double4 *pos)
     if (L.tiles_all == 0) return;
     const int blocks = capped(((int64_t)L.tiles_all * kWave + 255) / 256);
     hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.tprefix_all, L.n_sys,
-                       L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.status,
+                       L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.sflag, L.status,
                        L.step_counter, L.slow_n, L.rare_n, L.since, L.since_inc);
 }
 
@@ -1503,11 +1548,11 @@ void launch_cell_sort(const LaunchCtx &L, const double4 *pos)
     if (L.cell_cap <= 64)
         hipLaunchKernelGGL(k_cells_and_plan<1>, grid, dim3(kWave), 0, L.stream, (int)n_sort, L.sys, L.n_sys,
                            L.tprefix_local, L.tiles_local, pos, L.n_cells, L.cell_count, L.cell_size, L.cell_idx,
-                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag);
+                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag, L.sflag);
     else
         hipLaunchKernelGGL(k_cells_and_plan<2>, grid, dim3(kWave), 0, L.stream, (int)n_sort, L.sys, L.n_sys,
                            L.tprefix_local, L.tiles_local, pos, L.n_cells, L.cell_count, L.cell_size, L.cell_idx,
-                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag);
+                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag, L.sflag);
 }
 
 int nlist_row_stride(int cap)
@@ -1565,7 +1610,7 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
                            L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.cell_count, L.n_cells, L.flag,
-                           L.build_count, L.status);
+                           L.sflag, L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<true>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
@@ -1576,7 +1621,7 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
                            L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.cell_count, L.n_cells, L.flag,
-                           L.build_count, L.status);
+                           L.sflag, L.build_count, L.status);
         hipLaunchKernelGGL(k_build_tile<false>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,

@@ -32,7 +32,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
     // byte offsets into the workspace
-    size_t sysdev, tpl, tpa, status, flags, thermo, thermo_log, partials;
+    size_t sysdev, tpl, tpa, status, flags, sysflags, thermo, thermo_log, partials;
     size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, cell_xf, halo, halo_n;
     size_t rtag, partners, slow_list, rare_list, plan, sort_ws, ghost_ws, total;
     // sizes
@@ -234,6 +234,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.tpa = take(sizeof(int32_t) * (n_sys + 1));
     Lo.status = take(sizeof(Status));
     Lo.flags = take(sizeof(int32_t) * 8);
+    Lo.sysflags = take(sizeof(int32_t) * 4 * (size_t)n_sys);
     Lo.thermo = take(sizeof(double) * 4 * n_sys);
     Lo.thermo_log = take(sizeof(double) * 5 * (size_t)n_sys * kLogRows);
     Lo.partials = take(sizeof(double) * 3 * (size_t)std::max<int64_t>(tile, 1) * 64);
@@ -342,18 +343,24 @@ size_t mark(hoomd_ctx *c)
 }
 
 // Device flags: 0 and 1 rebuild flags of the two buffer parities, 2 the flag
-// of explicit builds, 3 steps since the last build, 4 build counter, 5 step counter of replayed steps, 6
+// of explicit builds, 3 unused, 4 build counter, 5 step counter of replayed steps, 6
 // tiles passed from the framed build to the general one, 7 tiles the force
 // pass handles in its second launch.
 int32_t *flag_ptr(hoomd_ctx *c, int k) { return ws_ptr<int32_t>(c, c->lay.flags) + k; }
+
+// Per-system words, n_sys each: k = 0, 1, 2 the rebuild flags of each system
+// that go with device flags 0, 1, 2 (a batch rebuilds only the systems whose
+// particles moved far enough); k = 3 each system's steps since its last build.
+int32_t *sflag_ptr(hoomd_ctx *c, int k) { return ws_ptr<int32_t>(c, c->lay.sysflags) + (size_t)k * c->n_sys; }
 
 // Queue the rebuild sequence: bin -> per-cell sort -> neighbour rows.  Every
 // kernel returns at once when *flag is clear.  The binning launch also keeps
 // the count of steps since the last build: reset by a build, else advanced by
 // since_inc (1 after a step, 0 after an explicit build request).
-void queue_rebuild(hoomd_ctx *c, const double4 *pos, const int32_t *tag, int32_t *flag, int since_inc)
+void queue_rebuild(hoomd_ctx *c, const double4 *pos, const int32_t *tag, int slot, int since_inc)
 {
-    c->L.flag = flag;
+    c->L.flag = flag_ptr(c, slot);
+    c->L.sflag = sflag_ptr(c, slot);
     c->L.since_inc = since_inc;
     launch_bin(c->L, pos);
     launch_cell_sort(c->L, pos);
@@ -367,7 +374,7 @@ ForceLaunch base_force(hoomd_ctx *c)
     F.force = c->arr.force;
     F.mixed = c->mixed;
     F.pair = c->pair_uniform;
-    F.since = flag_ptr(c, 3);
+    F.since = sflag_ptr(c, 3);
     F.check_period = c->check_period;
     return F;
 }
@@ -388,8 +395,10 @@ void queue_mid_step(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V, b
     F.mode = MODE_MID;
     F.flag_set = flag_ptr(c, p);
     F.flag_clear = flag_ptr(c, p ^ 1);
+    F.sflag_set = sflag_ptr(c, p);
+    F.sflag_clear = sflag_ptr(c, p ^ 1);
     launch_force(c->L, F, c->tpp_force, c->block_force);
-    queue_rebuild(c, P[p ^ 1], c->arr.tag, flag_ptr(c, p), 1);
+    queue_rebuild(c, P[p ^ 1], c->arr.tag, p, 1);
 }
 
 // Pairs of middle steps in the long captured run: one graph launch per 16
@@ -504,7 +513,8 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.has_bonds = nb_total > 0;
     L.flag = flag_ptr(c, 0);
     L.build_count = flag_ptr(c, 4);
-    L.since = flag_ptr(c, 3);
+    L.sflag = nullptr;  // set with L.flag by queue_rebuild
+    L.since = sflag_ptr(c, 3);
     L.since_inc = 0;
     L.slow_list = ws_ptr<int32_t>(c, lay.slow_list);
     L.slow_n = flag_ptr(c, 6);
@@ -531,6 +541,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpa, lay.tpa_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.status, 0, sizeof(Status));
     if (e == hipSuccess) e = hipMemset(c->ws + lay.flags, 0, sizeof(int32_t) * 8);
+    if (e == hipSuccess) e = hipMemset(c->ws + lay.sysflags, 0, sizeof(int32_t) * 4 * (size_t)n_sys);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.cell_count, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(lay.n_cells, 1));
     if (e == hipSuccess) e = hipMemset(c->ws + lay.thermo, 0, sizeof(double) * 4 * n_sys);
     // bond partner rows by tag (built on the host from the caller's table)
@@ -606,6 +617,7 @@ int build_nlist(hoomd_ctx *c, int32_t force_rebuild)
 {
     if (!c) return HOOMD_E_ARG;
     int32_t *flag = flag_ptr(c, 2);
+    int32_t *sflag = sflag_ptr(c, 2);
     double4 *pos = reinterpret_cast<double4 *>(c->arr.pos);
     if (force_rebuild || !c->built) {
         // with spatial sorting enabled, every full build starts from Morton
@@ -616,12 +628,12 @@ int build_nlist(hoomd_ctx *c, int32_t force_rebuild)
                 return HOOMD_E_DEVICE;
             if (c->lay.bond_cap > 0) launch_rtag(c->L, c->arr.tag);
         }
-        launch_set_flag(c->L, flag, 1);
+        launch_set_flags(c->L, flag, sflag, 1);
     } else {
-        launch_set_flag(c->L, flag, 0);
-        launch_disp_check(c->L, pos, flag);
+        launch_set_flags(c->L, flag, sflag, 0);
+        launch_disp_check(c->L, pos, flag, sflag);
     }
-    queue_rebuild(c, pos, c->arr.tag, flag, 0);
+    queue_rebuild(c, pos, c->arr.tag, 2, 0);
     c->built = true;
     return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
 }
@@ -706,6 +718,8 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
         F.mode = s == 0 ? MODE_FIRST : (s == n_steps ? MODE_LAST : MODE_MID);
         F.flag_set = F.mode == MODE_LAST ? nullptr : flag_ptr(c, p);
         F.flag_clear = F.mode == MODE_LAST ? nullptr : flag_ptr(c, p ^ 1);
+        F.sflag_set = F.mode == MODE_LAST ? nullptr : sflag_ptr(c, p);
+        F.sflag_clear = F.mode == MODE_LAST ? nullptr : sflag_ptr(c, p ^ 1);
         F.log = logs_at(s);
         F.energy = F.mode == MODE_LAST ? 1 : 0;
         if (F.mode == MODE_LAST) F.log = F.log || log_every > 0;
@@ -717,7 +731,6 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
             ++log_row;
         }
         if (F.mode == MODE_LAST) break;
-        int32_t *flag = flag_ptr(c, p);
         if (sorts_after(s)) {
             rc = queue_morton_sort(c->L, c->sortb, P[p ^ 1], V[dpd ? p ^ 1 : 0], tag, P[p],
                                    V[dpd ? p : 1]);
@@ -726,10 +739,10 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
                 return HOOMD_E_DEVICE;
             }
             if (c->lay.bond_cap > 0) launch_rtag(c->L, tag);
-            launch_set_flag(c->L, flag, 1);
+            launch_set_flags(c->L, flag_ptr(c, p), sflag_ptr(c, p), 1);  // a sort moves every system's rows
         }
         const size_t r0 = mark(c);
-        queue_rebuild(c, P[p ^ 1], tag, flag, 1);
+        queue_rebuild(c, P[p ^ 1], tag, p, 1);
         if (c->profiling) c->ev_rebuild.emplace_back(r0, mark(c));
         ++s;
     }
