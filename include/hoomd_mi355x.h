@@ -130,6 +130,11 @@ typedef struct {
                               64 * tpp_force (one 64-row tile each)         */
     int32_t use_graph;     /* 1: step() replays captured pairs of middle steps
                               (HIP graph, captured once per context)          */
+    int32_t tune_period;   /* > 0: step() re-runs the autotuner at its first
+                              call once this many steps have passed since the
+                              last scan, or after the ghost count changed
+                              (Sec. 5.2); 0: tune only on request.  Equal in
+                              all systems                                    */
 } hoomd_params;
 
 /* Geometry of one system.  For a periodic box lo = 0 and L is the box.  For
@@ -319,10 +324,25 @@ typedef struct {
 } hoomd_layout;
 int hoomd_get_layout(hoomd_ctx *ctx, int32_t sys, hoomd_layout *out);
 
-/* Lanes per particle and block sizes in use; with do_tune != 0, first time
- * each candidate on the current state (median of 5 launches each) and keep
- * the fastest (Sec. 5.2).  Synchronises when tuning. */
-typedef struct { int32_t tpp_nlist, block_nlist, tpp_force, block_force; } hoomd_tuning;
+/* Autotuner (Sec. 5.2): launch shapes in use, and the timings of the last
+ * scan.  do_tune = 0 reports; 1 times every candidate on the current state
+ * (median of 5 launches each, after one untimed launch) and keeps the
+ * fastest; 2 takes the shapes a scan found for the same kind of context
+ * (pair potential, precision, particle count to within a factor of 2, mean
+ * neighbour count to within 4) from a process-wide cache, and scans only
+ * when there is none.  Candidates: the force pass with W = 1, 2, 4, 8, 16
+ * lanes per particle (64 W threads per workgroup); the framed list build
+ * with (lanes per row, threads per workgroup) = (64, 512), (64, 256),
+ * (32, 512), (32, 256).  A scan rebuilds the neighbour list afterwards, so
+ * the state is what it was.  Synchronises when tuning.  Fields given
+ * explicitly in hoomd_params are kept (not tuned). */
+typedef struct {
+    int32_t tpp_nlist, block_nlist, tpp_force, block_force;
+    float force_ms[5];   /* median launch time of each force candidate in the last scan (0: not timed) */
+    float build_ms[4];   /* the same for the build candidates, in the order above */
+    int32_t scans;       /* scans run by this context */
+    int32_t from_cache;  /* 1 when the shapes in use came from the cache */
+} hoomd_tuning;
 int hoomd_autotune(hoomd_ctx *ctx, int32_t do_tune, hoomd_tuning *out);
 
 /* Device time per phase of step(), measured with HIP events recorded on the

@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("fene_K", C.c_double), ("fene_R0", C.c_double), ("nlist_cap", C.c_int32),
                 ("cell_cap", C.c_int32), ("halo_cap", C.c_int32), ("sort_period", C.c_int32), ("check_period", C.c_int32),
                 ("tpp_nlist", C.c_int32), ("tpp_force", C.c_int32), ("block_nlist", C.c_int32),
-                ("block_force", C.c_int32), ("use_graph", C.c_int32)]
+                ("block_force", C.c_int32), ("use_graph", C.c_int32), ("tune_period", C.c_int32)]
 
 
 class Box(C.Structure):
@@ -72,7 +72,12 @@ class Layout(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("tpp_nlist", C.c_int32), ("block_nlist", C.c_int32), ("tpp_force", C.c_int32),
-                ("block_force", C.c_int32)]
+                ("block_force", C.c_int32), ("force_ms", C.c_float * 5), ("build_ms", C.c_float * 4),
+                ("scans", C.c_int32), ("from_cache", C.c_int32)]
+
+
+BUILD_SHAPES = [(64, 512), (64, 256), (32, 512), (32, 256)]
+FORCE_LANES = [1, 2, 4, 8, 16]
 
 
 class Profile(C.Structure):
@@ -156,6 +161,7 @@ class ModelParams:
     block_nlist: int = 0
     block_force: int = 0
     use_graph: int = 1
+    tune_period: int = 0
 
     def list_radius(self) -> float:
         rc = 2.0 ** (1.0 / 6.0) * self.sigma if self.pair == PAIR_WCA else self.r_cut
@@ -340,9 +346,11 @@ class Context:
         _check(lib().hoomd_build_count(self.h, C.byref(v)), "hoomd_build_count")
         return v.value
 
-    def autotune(self, do_tune: bool = True) -> Tuning:
+    def autotune(self, do_tune=True) -> Tuning:
+        """do_tune: False/0 report, True/1 scan, 2 use the process-wide cache
+        (scan only when it has nothing for this kind of context)."""
         t = Tuning()
-        _check(lib().hoomd_autotune(self.h, 1 if do_tune else 0, C.byref(t)), "hoomd_autotune")
+        _check(lib().hoomd_autotune(self.h, int(do_tune), C.byref(t)), "hoomd_autotune")
         return t
 
     def profile(self, mode: int) -> Optional[Profile]:

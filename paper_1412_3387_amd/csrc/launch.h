@@ -95,8 +95,9 @@ size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
 int force_row_over_read();
 int force_halo_entry_bytes(int pair);
 size_t fast_build_lds_bytes(int nlist_cap);
-int nlist_lanes_per_row();  // lanes that scan one row in the framed build
-int nlist_block();          // threads per workgroup of the framed build
+int nlist_lanes_per_row();  // lanes that scan one row in the framed build (default)
+int nlist_block();          // threads per workgroup of the framed build (default)
+bool nlist_shape_ok(int lanes_per_row, int block);  // a shape launch_nlist runs
 size_t build_plan_bytes(int64_t tiles);
 hipError_t prepare_nlist(int nlist_cap);
 // Raises the dynamic-LDS limit of the rare-tile force kernels (init time).

@@ -689,8 +689,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 // cells on a periodic axis, too many distinct cells or members) are appended
 // to a device list and built by k_build_tile.
 
-constexpr int kFastThreads = 512;
-constexpr int kFastWaves = kFastThreads / kWave;
+constexpr int kFastThreads = 512;           // threads per workgroup by default (8 waves)
+constexpr int kFastWavesMax = 8;            // waves per workgroup at most
 constexpr int kFastChunk = 2560;     // members staged at once (float4 each)
 constexpr int kBoxMax = 8192;        // cells of the frame box
 constexpr int kBoxWords = kBoxMax / 32;
@@ -752,9 +752,11 @@ struct FastShared {
     float hw[kTile][kRuns];              // half width in x of each row line
     float4 xrow[kTile];                  // row position in the frame (FP32)
     int32_t rown[kTile];                 // hits of each row so far
-    uint64_t lmask[kTile];               // per row: bit of the last lane of each line but the last
-    uint8_t lb[kTile][kRuns + 1];        // per row: first lane of each line, then 64
-    int32_t scan[kFastWaves];            // per-wave totals of the block scans
+    uint64_t lmask[kTile];               // per row: bit of the last lane of each (non-empty) line but the last
+    uint8_t lb[kTile][kRuns + 1];        // per row: first lane of each (non-empty) line, then the lanes used
+    uint8_t ln[kTile][kRuns];            // 32 lanes per row: the non-empty lines in order
+    uint8_t nk[kTile];                   // 32 lanes per row: non-empty lines in this chunk
+    int32_t scan[kFastWavesMax];         // per-wave totals of the block scans
     uint8_t smap[kFastChunk];            // distinct cell of each slot of the chunk
     double xref[3];                      // first row's position: the frame reference
     int32_t info[5];                     // distinct cells, per-pair image flag, longest row, slots,
@@ -1116,8 +1118,10 @@ __device__ __forceinline__ int4 next_header(const int4 *hdr, int tile)
     return hdr[tile + zero];
 }
 
-template <bool EXCL>
-__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_build_fast(
+// NT threads per workgroup (NT / 64 waves share a tile); LPR lanes scan one
+// row: 64 (a wave per row) or 32 (two rows per wave).
+template <bool EXCL, int NT, int LPR>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_build_fast(
     const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
     const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ partners,
     const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx,
@@ -1138,7 +1142,9 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wv = tid >> 6;
-    const uint64_t below = lanemask_lt();
+    constexpr int kWaves = NT / kWave;
+    static_assert(kWaves >= 2 && kWaves <= kFastWavesMax, "a loader wave and at least one more");
+    static_assert(LPR == 32 || LPR == 64, "a row per wave or per half wave");
     if (blockIdx.x == 0 && tid == 0) atomicAdd(build_count, 1);
 
     int64_t tfirst, tend;
@@ -1238,7 +1244,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
         const int nslot = uni(sh.info[3]);
         if (nu <= 0 || nu > kUMax || nslot > kFastSlotMax) continue;  // built by the general kernel
         const double xr[3] = {uni(sh.xref[0]), uni(sh.xref[1]), uni(sh.xref[2])};
-        for (int q = tid; q < (nslot + 31) / 32; q += kFastThreads) sh.used[q] = 0u;
+        for (int q = tid; q < (nslot + 31) / 32; q += NT) sh.used[q] = 0u;
         // ---- 5. stage members a chunk at a time, scan every row's lines -------------
         const bool one_chunk = nslot <= kFastChunk;
         // FP32 distances below lo_f are hits, above hi_f misses, in between
@@ -1250,7 +1256,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             lds_barrier();
             // slot -> distinct cell of the chunk: each cell writes its index
             // over its own slots
-            for (int u = tid; u < nu; u += kFastThreads) {
+            for (int u = tid; u < nu; u += NT) {
                 int qa = sh.ustart[u], qb = sh.ustart[u + 1];
                 qa = qa > q0 ? qa : q0;
                 qb = qb < q1 ? qb : q1;
@@ -1262,12 +1268,12 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             // four reads of a thread in flight at once
             {
                 constexpr int kB = 4;
-                for (int qb = q0 + tid; qb < q1; qb += kB * kFastThreads) {
+                for (int qb = q0 + tid; qb < q1; qb += kB * NT) {
                     int us[kB], qs[kB];
                     float4 cs[kB];
 #pragma unroll
                     for (int k = 0; k < kB; ++k) {
-                        const int q = qb + k * kFastThreads;
+                        const int q = qb + k * NT;
                         qs[k] = q;
                         us[k] = q < q1 ? (int)sh.smap[q - q0] : 0;
                     }
@@ -1276,7 +1282,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                         if (qs[k] < q1) cs[k] = cell_xf[(int64_t)sh.ucell[us[k]] * cell_cap + (qs[k] - sh.ustart[us[k]])];
 #pragma unroll
                     for (int k = 0; k < kB; ++k) {
-                        const int q = qb + k * kFastThreads;
+                        const int q = qb + k * NT;
                         if (q < q1) {
                             const float4 o = sh.uoff[us[k]];
                             sh.cp[q - q0] = make_float4(cs[k].x + o.x, cs[k].y + o.y, cs[k].z + o.z, cs[k].w);
@@ -1289,7 +1295,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             // by x): cut every line, within this chunk, to the slots within the
             // half width that its y-z distance leaves (|dx|^2 <= r_list^2 - gap^2,
             // widened by a margin for the FP32 frame coordinates)
-            for (int e = tid; e < kTile * kRuns; e += kFastThreads) {
+            for (int e = tid; e < kTile * kRuns; e += NT) {
                 const int t = e / kRuns, rr = e - kRuns * (e / kRuns);
                 const uint32_t v = sh.run[t][rr];
                 int a = (int)(v & 0xffffu), b = (int)(v >> 16);
@@ -1313,141 +1319,299 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 sh.runc[t][rr] = (uint32_t)pa | ((uint32_t)(pb > pa ? pb : pa) << 16);
             }
             lds_barrier();
-            // lanes to lines, one thread per row: line r takes lanes [B_r, B_r+1)
-            // with B_r = r + about 55 P_r / T (P_r the members of the row's lines
-            // before line r in this chunk, T all of them), so every line keeps at
-            // least one lane and longer lines get more.  Kept as the first lanes
-            // and a mask with the last lane of every line but the last.
-            if (tid < kTile) {
-                int lens[kRuns];
-                int tot = 0;
-#pragma unroll
-                for (int r = 0; r < kRuns; ++r) {
-                    const uint32_t rv = sh.runc[tid][r];
+            if constexpr (LPR == 64) {
+                // lanes to lines, one thread per row: line r takes lanes [B_r, B_r+1)
+                // with B_r = r + about 55 P_r / T (P_r the members of the row's lines
+                // before line r in this chunk, T all of them), so every line keeps at
+                // least one lane and longer lines get more.  Kept as the first lanes
+                // and a mask with the last lane of every line but the last.
+                if (tid < kTile) {
+                    int lens[kRuns];
+                    int tot = 0;
+    #pragma unroll
+                    for (int r = 0; r < kRuns; ++r) {
+                        const uint32_t rv = sh.runc[tid][r];
+                        const int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
+                        lens[r] = x1_ > x0_ ? x1_ - x0_ : 0;
+                        tot += lens[r];
+                    }
+                    const uint32_t inv = tot > 0 ? 65536u / (uint32_t)tot : 0u;  // floor(2^16 / T)
+                    uint64_t mask = 0;
+                    int pre = 0, b0 = 0;
+    #pragma unroll
+                    for (int r = 0; r < kRuns; ++r) {
+                        const int pn = pre + lens[r];
+                        const int b1 = r == kRuns - 1 ? kWave : r + 1 + (int)((55u * (uint32_t)pn * inv) >> 16);
+                        sh.lb[tid][r] = (uint8_t)b0;
+                        if (r < kRuns - 1) mask |= 1ull << (b1 - 1);
+                        b0 = b1;
+                        pre = pn;
+                    }
+                    sh.lb[tid][kRuns] = (uint8_t)kWave;
+                    sh.lmask[tid] = tot > 0 ? mask : 0ull;
+                    if (tot == 0 && sh.rown[tid] >= 0) sh.lb[tid][0] = 0xFF;  // nothing to scan in this chunk
+                }
+                lds_barrier();
+                for (int t = wv; t < kTile; t += kWaves) {
+                    int ntot = uni(sh.rown[t]);
+                    if (ntot < 0) continue;  // inactive row
+                    if (uni((int)sh.lb[t][0]) == 0xFF) continue;  // no members in this chunk
+                    // this lane's line: the lines that end before it; its lanes,
+                    // members (cut to the chunk) and stride
+                    const uint64_t lm = sh.lmask[t];
+                    int myline = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(lm >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u));
+                    myline = myline < kRuns - 1 ? myline : kRuns - 1;
+                    const int blo_ = sh.lb[t][myline], bhi_ = sh.lb[t][myline + 1];
+                    const uint32_t rv = sh.runc[t][myline];
                     const int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
-                    lens[r] = x1_ > x0_ ? x1_ - x0_ : 0;
-                    tot += lens[r];
-                }
-                const uint32_t inv = tot > 0 ? 65536u / (uint32_t)tot : 0u;  // floor(2^16 / T)
-                uint64_t mask = 0;
-                int pre = 0, b0 = 0;
-#pragma unroll
-                for (int r = 0; r < kRuns; ++r) {
-                    const int pn = pre + lens[r];
-                    const int b1 = r == kRuns - 1 ? kWave : r + 1 + (int)((55u * (uint32_t)pn * inv) >> 16);
-                    sh.lb[tid][r] = (uint8_t)b0;
-                    if (r < kRuns - 1) mask |= 1ull << (b1 - 1);
-                    b0 = b1;
-                    pre = pn;
-                }
-                sh.lb[tid][kRuns] = (uint8_t)kWave;
-                sh.lmask[tid] = tot > 0 ? mask : 0ull;
-                if (tot == 0 && sh.rown[tid] >= 0) sh.lb[tid][0] = 0xFF;  // nothing to scan in this chunk
-            }
-            lds_barrier();
-            for (int t = wv; t < kTile; t += kFastWaves) {
-                int ntot = uni(sh.rown[t]);
-                if (ntot < 0) continue;  // inactive row
-                if (uni((int)sh.lb[t][0]) == 0xFF) continue;  // no members in this chunk
-                // this lane's line: the lines that end before it; its lanes,
-                // members (cut to the chunk) and stride
-                const uint64_t lm = sh.lmask[t];
-                int myline = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(lm >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u));
-                myline = myline < kRuns - 1 ? myline : kRuns - 1;
-                const int blo_ = sh.lb[t][myline], bhi_ = sh.lb[t][myline + 1];
-                const uint32_t rv = sh.runc[t][myline];
-                const int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
-                const int gsz = bhi_ - blo_ > 1 ? bhi_ - blo_ : 1;
-                const int base = x0_ + (lane - blo_);
-                const int end = x1_;
-                const float4 xt0 = sh.xrow[t];
-                const float4 xt = make_float4(uni(xt0.x), uni(xt0.y), uni(xt0.z), 0.f);
-                const int32_t it = (int32_t)(row0 + r0 + t);
-                int32_t part[kMaxBondCap];
-                if constexpr (EXCL) {
-                    const int64_t prow = (row0 + tag[it]) * S.bond_stride;
-#pragma unroll
-                    for (int bnd = 0; bnd < kMaxBondCap; ++bnd)
-                        part[bnd] = bnd < S.bond_cap ? partners[prow + bnd] : -1;
-                }
-                uint16_t *myrow = srows + t * rstride;
-                // exact FP64 decision of a candidate whose FP32 distance is
-                // within the band around r_list
-                auto exact = [&](const float4 c) -> bool {
-                    const int32_t j = __float_as_int(c.w);
-                    const double4 xa = pos[it], xb = pos[j];
-                    const double cj[3] = {(double)c.x, (double)c.y, (double)c.z};
-                    const double xt3[3] = {(double)xt.x, (double)xt.y, (double)xt.z};
-                    const double pa[3] = {xa.x, xa.y, xa.z}, pb[3] = {xb.x, xb.y, xb.z};
-                    double d[3];
-#pragma unroll
-                    for (int ax = 0; ax < 3; ++ax) {
-                        // frame images of both: k = round((frame - stored) / L)
-                        const double kj = rint((cj[ax] + xr[ax] - pb[ax]) * iL[ax]);
-                        const double ki = rint((xt3[ax] + xr[ax] - pa[ax]) * iL[ax]);
-                        d[ax] = pb[ax] - pa[ax];
-                        if (kj != ki) d[ax] = d[ax] + (kj - ki) * Ls[ax];
-                    }
-                    return norm2_exact(d[0], d[1], d[2]) < rl2 && j != it;
-                };
-                auto excluded = [&](bool hit, const float4 c) -> bool {
+                    const int gsz = bhi_ - blo_ > 1 ? bhi_ - blo_ : 1;
+                    const int base = x0_ + (lane - blo_);
+                    const int end = x1_;
+                    const float4 xt0 = sh.xrow[t];
+                    const float4 xt = make_float4(uni(xt0.x), uni(xt0.y), uni(xt0.z), 0.f);
+                    const int32_t it = (int32_t)(row0 + r0 + t);
+                    int32_t part[kMaxBondCap];
                     if constexpr (EXCL) {
-                        if (hit) {
-                            const int32_t tj = tag[__float_as_int(c.w)];
-#pragma unroll
-                            for (int bnd = 0; bnd < kMaxBondCap; ++bnd) hit = hit && part[bnd] != tj;
+                        const int64_t prow = (row0 + tag[it]) * S.bond_stride;
+    #pragma unroll
+                        for (int bnd = 0; bnd < kMaxBondCap; ++bnd)
+                            part[bnd] = bnd < S.bond_cap ? partners[prow + bnd] : -1;
+                    }
+                    uint16_t *myrow = srows + t * rstride;
+                    // exact FP64 decision of a candidate whose FP32 distance is
+                    // within the band around r_list
+                    auto exact = [&](const float4 c) -> bool {
+                        const int32_t j = __float_as_int(c.w);
+                        const double4 xa = pos[it], xb = pos[j];
+                        const double cj[3] = {(double)c.x, (double)c.y, (double)c.z};
+                        const double xt3[3] = {(double)xt.x, (double)xt.y, (double)xt.z};
+                        const double pa[3] = {xa.x, xa.y, xa.z}, pb[3] = {xb.x, xb.y, xb.z};
+                        double d[3];
+    #pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            // frame images of both: k = round((frame - stored) / L)
+                            const double kj = rint((cj[ax] + xr[ax] - pb[ax]) * iL[ax]);
+                            const double ki = rint((xt3[ax] + xr[ax] - pa[ax]) * iL[ax]);
+                            d[ax] = pb[ax] - pa[ax];
+                            if (kj != ki) d[ax] = d[ax] + (kj - ki) * Ls[ax];
                         }
+                        return norm2_exact(d[0], d[1], d[2]) < rl2 && j != it;
+                    };
+                    auto excluded = [&](bool hit, const float4 c) -> bool {
+                        if constexpr (EXCL) {
+                            if (hit) {
+                                const int32_t tj = tag[__float_as_int(c.w)];
+    #pragma unroll
+                                for (int bnd = 0; bnd < kMaxBondCap; ++bnd) hit = hit && part[bnd] != tj;
+                            }
+                        }
+                        return hit;
+                    };
+                    // a hit goes to the row's next entry (entries past the
+                    // capacity land on the row's spare slot) and marks its slot
+                    auto append = [&](bool hit, uint64_t mask, int q) {
+                        if (hit) {
+                            const int p = ntot + (int)__builtin_amdgcn_mbcnt_hi(
+                                                     (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                            myrow[p < cap ? p : cap] = (uint16_t)q;
+                            atomicOr(&sh.used[q >> 5], 1u << (q & 31));
+                        }
+                        ntot += __popcll(mask);
+                    };
+                    // every lane reads a slot of the chunk, clamped: lanes past
+                    // their line's end take no part
+                    const float4 *cq = sh.cp - q0;
+                    const int qlast = q1 - 1;
+                    for (int qa = base;; qa += 2 * gsz) {
+                        const int qb = qa + gsz;
+                        const bool ona = qa < end, onb = qb < end;
+                        if (__ballot(ona) == 0ull) break;
+                        const float4 ca = cq[qa < qlast ? qa : qlast];
+                        const float4 cb = cq[qb < qlast ? qb : qlast];
+                        const float dxa = ca.x - xt.x, dya = ca.y - xt.y, dza = ca.z - xt.z;
+                        const float dxb = cb.x - xt.x, dyb = cb.y - xt.y, dzb = cb.z - xt.z;
+                        const float r2a = dxa * dxa + dya * dya + dza * dza;
+                        const float r2b = dxb * dxb + dyb * dyb + dzb * dzb;
+                        bool ha = ona && r2a < lo_f && __float_as_int(ca.w) != it;
+                        bool hb = onb && r2b < lo_f && __float_as_int(cb.w) != it;
+                        const bool ba = ona && r2a >= lo_f && r2a <= hi_f;
+                        const bool bb = onb && r2b >= lo_f && r2b <= hi_f;
+                        if (__builtin_expect(__ballot(ba || bb) != 0ull, 0)) {
+                            if (ba) ha = exact(ca);
+                            if (bb) hb = exact(cb);
+                        }
+                        ha = excluded(ha, ca);
+                        hb = excluded(hb, cb);
+                        const uint64_t ma = __ballot(ha), mb = __ballot(hb);
+                        append(ha, ma, qa);
+                        append(hb, mb, qb);
                     }
-                    return hit;
-                };
-                // a hit goes to the row's next entry (entries past the
-                // capacity land on the row's spare slot) and marks its slot
-                auto append = [&](bool hit, uint64_t mask, int q) {
-                    if (hit) {
-                        const int p = ntot + (int)__builtin_amdgcn_mbcnt_hi(
-                                                 (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                        myrow[p < cap ? p : cap] = (uint16_t)q;
-                        atomicOr(&sh.used[q >> 5], 1u << (q & 31));
+                    if (lane == 0) sh.rown[t] = ntot;
+                }
+            } else {
+                // lanes to lines, one thread per row.  Two rows share a wave, 32
+                // lanes each, two members per lane per pass: the fewest passes P
+                // such that ceil(len / 2P) lanes for every non-empty line of the
+                // row (in this chunk) take at most 32 lanes.  Kept per row: the
+                // non-empty lines in order with their first lanes (then the lanes
+                // used), and a mask with the last lane of each line but the last.
+                if (tid < kTile) {
+                    int lens[kRuns];
+                    int tot = 0;
+    #pragma unroll
+                    for (int r = 0; r < kRuns; ++r) {
+                        const uint32_t rv = sh.runc[tid][r];
+                        const int x0_ = (int)(rv & 0xffffu), x1_ = (int)(rv >> 16);
+                        lens[r] = x1_ > x0_ ? x1_ - x0_ : 0;
+                        tot += lens[r];
                     }
-                    ntot += __popcll(mask);
-                };
-                // every lane reads a slot of the chunk, clamped: lanes past
-                // their line's end take no part
+                    // at 2P >= the longest line every non-empty line takes one
+                    // lane (at most nine), so the search ends
+                    int d = 2 * ((tot + 63) >> 6);
+                    d = d > 2 ? d : 2;
+                    for (;;) {
+                        int lanes = 0;
+    #pragma unroll
+                        for (int r = 0; r < kRuns; ++r) lanes += (lens[r] + d - 1) / d;
+                        if (lanes <= 32) break;
+                        d += 2;
+                    }
+                    uint32_t mask = 0u;
+                    int nk = 0, b0 = 0;
+    #pragma unroll
+                    for (int r = 0; r < kRuns; ++r) {
+                        if (lens[r] == 0) continue;
+                        if (nk > 0) mask |= 1u << (b0 - 1);
+                        sh.ln[tid][nk] = (uint8_t)r;
+                        sh.lb[tid][nk] = (uint8_t)b0;
+                        b0 += (lens[r] + d - 1) / d;
+                        ++nk;
+                    }
+                    sh.lb[tid][nk] = (uint8_t)b0;
+                    sh.lmask[tid] = mask;
+                    sh.nk[tid] = (uint8_t)nk;
+                }
+                lds_barrier();
+                // rows t0 (lanes 0-31) and t0 + 1 (lanes 32-63) of each wave
+                const int hh = lane >> 5, hl = lane & 31;
                 const float4 *cq = sh.cp - q0;
                 const int qlast = q1 - 1;
-                for (int qa = base;; qa += 2 * gsz) {
-                    const int qb = qa + gsz;
-                    const bool ona = qa < end, onb = qb < end;
-                    if (__ballot(ona) == 0ull) break;
-                    const float4 ca = cq[qa < qlast ? qa : qlast];
-                    const float4 cb = cq[qb < qlast ? qb : qlast];
-                    const float dxa = ca.x - xt.x, dya = ca.y - xt.y, dza = ca.z - xt.z;
-                    const float dxb = cb.x - xt.x, dyb = cb.y - xt.y, dzb = cb.z - xt.z;
-                    const float r2a = dxa * dxa + dya * dya + dza * dza;
-                    const float r2b = dxb * dxb + dyb * dyb + dzb * dzb;
-                    bool ha = ona && r2a < lo_f && __float_as_int(ca.w) != it;
-                    bool hb = onb && r2b < lo_f && __float_as_int(cb.w) != it;
-                    const bool ba = ona && r2a >= lo_f && r2a <= hi_f;
-                    const bool bb = onb && r2b >= lo_f && r2b <= hi_f;
-                    if (__builtin_expect(__ballot(ba || bb) != 0ull, 0)) {
-                        if (ba) ha = exact(ca);
-                        if (bb) hb = exact(cb);
+                for (int t0 = 2 * wv; t0 < kTile; t0 += 2 * kWaves) {
+                    const int t = t0 + hh;
+                    const int nk = sh.nk[t];
+                    int ntot = sh.rown[t];
+                    const bool row_on = ntot >= 0 && nk > 0;  // an active row with members in this chunk
+                    if (__ballot(row_on) == 0ull) continue;
+                    // this lane's line: the lines that end before it; its lanes,
+                    // members (cut to the chunk) and stride.  Lanes without a line
+                    // start at the chunk's first slot with nothing to scan.
+                    int base = q0, end = q0, gsz = 1;
+                    if (row_on) {
+                        const int used_lanes = sh.lb[t][nk];
+                        if (hl < used_lanes) {
+                            int k = __popc(sh.lmask[t] & ((1u << hl) - 1u));
+                            k = k < nk - 1 ? k : nk - 1;
+                            const int r = sh.ln[t][k];
+                            const int blo_ = sh.lb[t][k], bhi_ = sh.lb[t][k + 1];
+                            const uint32_t rv = sh.runc[t][r];
+                            gsz = bhi_ - blo_;
+                            base = (int)(rv & 0xffffu) + (hl - blo_);
+                            end = (int)(rv >> 16);
+                        }
                     }
-                    ha = excluded(ha, ca);
-                    hb = excluded(hb, cb);
-                    const uint64_t ma = __ballot(ha), mb = __ballot(hb);
-                    append(ha, ma, qa);
-                    append(hb, mb, qb);
+                    const float4 xt = sh.xrow[t];
+                    const int32_t it = (int32_t)(row0 + r0 + t);
+                    int32_t part[kMaxBondCap];
+                    if constexpr (EXCL) {
+    #pragma unroll
+                        for (int bnd = 0; bnd < kMaxBondCap; ++bnd) part[bnd] = -1;
+                        if (row_on) {
+                            const int64_t prow = (row0 + tag[it]) * S.bond_stride;
+    #pragma unroll
+                            for (int bnd = 0; bnd < kMaxBondCap; ++bnd)
+                                part[bnd] = bnd < S.bond_cap ? partners[prow + bnd] : -1;
+                        }
+                    }
+                    uint16_t *myrow = srows + t * rstride;
+                    // exact FP64 decision of a candidate whose FP32 distance is
+                    // within the band around r_list
+                    auto exact = [&](const float4 c) -> bool {
+                        const int32_t j = __float_as_int(c.w);
+                        const double4 xa = pos[it], xb = pos[j];
+                        const double cj[3] = {(double)c.x, (double)c.y, (double)c.z};
+                        const double xt3[3] = {(double)xt.x, (double)xt.y, (double)xt.z};
+                        const double pa[3] = {xa.x, xa.y, xa.z}, pb[3] = {xb.x, xb.y, xb.z};
+                        double d[3];
+    #pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            // frame images of both: k = round((frame - stored) / L)
+                            const double kj = rint((cj[ax] + xr[ax] - pb[ax]) * iL[ax]);
+                            const double ki = rint((xt3[ax] + xr[ax] - pa[ax]) * iL[ax]);
+                            d[ax] = pb[ax] - pa[ax];
+                            if (kj != ki) d[ax] = d[ax] + (kj - ki) * Ls[ax];
+                        }
+                        return norm2_exact(d[0], d[1], d[2]) < rl2 && j != it;
+                    };
+                    auto excluded = [&](bool hit, const float4 c) -> bool {
+                        if constexpr (EXCL) {
+                            if (hit) {
+                                const int32_t tj = tag[__float_as_int(c.w)];
+    #pragma unroll
+                                for (int bnd = 0; bnd < kMaxBondCap; ++bnd) hit = hit && part[bnd] != tj;
+                            }
+                        }
+                        return hit;
+                    };
+                    // a hit goes to its row's next entry (entries past the
+                    // capacity land on the row's spare slot); the count of each
+                    // half of the wave is its own row's
+                    auto append = [&](bool hit, int q) {
+                        const uint64_t m = __ballot(hit);
+                        const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
+                        if (hit) {
+                            const int below = hh ? (int)__builtin_amdgcn_mbcnt_hi(mhi, 0u)
+                                                 : (int)__builtin_amdgcn_mbcnt_lo(mlo, 0u);
+                            const int p = ntot + below;
+                            myrow[p < cap ? p : cap] = (uint16_t)q;
+                        }
+                        ntot += hh ? __popc(mhi) : __popc(mlo);
+                    };
+                    // every lane reads a slot of the chunk, clamped: lanes past
+                    // their line's end take no part
+                    for (int qa = base;; qa += 2 * gsz) {
+                        const int qb = qa + gsz;
+                        const bool ona = qa < end, onb = qb < end;
+                        if (__ballot(ona) == 0ull) break;
+                        const float4 ca = cq[qa < qlast ? qa : qlast];
+                        const float4 cb = cq[qb < qlast ? qb : qlast];
+                        const float dxa = ca.x - xt.x, dya = ca.y - xt.y, dza = ca.z - xt.z;
+                        const float dxb = cb.x - xt.x, dyb = cb.y - xt.y, dzb = cb.z - xt.z;
+                        const float r2a = dxa * dxa + dya * dya + dza * dza;
+                        const float r2b = dxb * dxb + dyb * dyb + dzb * dzb;
+                        const bool la = r2a < lo_f, lb2 = r2b < lo_f;
+                        bool ha = ona && la && __float_as_int(ca.w) != it;
+                        bool hb = onb && lb2 && __float_as_int(cb.w) != it;
+                        const bool ba = ona && !la && r2a <= hi_f;
+                        const bool bb = onb && !lb2 && r2b <= hi_f;
+                        if (__builtin_expect(__ballot(ba || bb) != 0ull, 0)) {
+                            if (ba) ha = exact(ca);
+                            if (bb) hb = exact(cb);
+                        }
+                        ha = excluded(ha, ca);
+                        hb = excluded(hb, cb);
+                        append(ha, qa);
+                        append(hb, qb);
+                    }
+                    if (hl == 0 && row_on) sh.rown[t] = ntot;
                 }
-                if (lane == 0) sh.rown[t] = ntot;
             }
         }
         lds_barrier();
         // ---- 6. halo numbering, rows out ------------------------------------------
         // writers: every wave but the loader
         const int wid = wv == 0 ? tid : tid - kWave;
-        constexpr int kWriters = kFastThreads - kWave;
+        constexpr int kWriters = NT - kWave;
         const bool act0 = tid < kTile && r0 + tid < n_local;
         const int64_t i0 = row0 + r0 + tid;
         if (wv == 0) {
@@ -1456,10 +1620,26 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             n = wave_max_full(n < cap ? n : cap);
             if (tid == 0) sh.info[2] = n;
         }
+        if constexpr (LPR == 32) {
+            // the staged slots that some row lists (the 64-lane scan marks
+            // them as it finds them)
+            lds_barrier();
+            const int kmax_ = uni(sh.info[2]);
+            for (int e = tid; e < kmax_ * kTile; e += NT) {
+                const int t = e & (kTile - 1), k = e >> 6;
+                int n = sh.rown[t];
+                n = n < cap ? n : cap;
+                if (k < n) {
+                    const int q = srows[t * rstride + k];
+                    atomicOr(&sh.used[q >> 5], 1u << (q & 31));
+                }
+            }
+            lds_barrier();  // every mark made before the words are counted
+        }
         const int nwords = (nslot + 31) / 32;
-        for (int q = tid; q < nwords; q += kFastThreads) sh.wpre[q] = __popc(sh.used[q]);
+        for (int q = tid; q < nwords; q += NT) sh.wpre[q] = __popc(sh.used[q]);
         lds_barrier();
-        const int nhalo = uni(block_scan_w<kFastThreads>(sh.wpre, nwords, sh.scan));
+        const int nhalo = uni(block_scan_w<NT>(sh.wpre, nwords, sh.scan));
         if (nhalo > halo_cap) {
             if (tid == 0) latch(st, 11 /*HALO_OVERFLOW*/, nhalo);
             if (act0) nn[i0] = 0;
@@ -1567,6 +1747,10 @@ int nlist_row_stride(int cap)
 
 int nlist_lanes_per_row() { return kWave; }
 int nlist_block() { return kFastThreads; }
+bool nlist_shape_ok(int lanes_per_row, int block)
+{
+    return (lanes_per_row == 32 || lanes_per_row == 64) && (block == 256 || block == 512);
+}
 
 size_t fast_build_lds_bytes(int cap) { return sizeof(FastShared) + (size_t)kTile * nlist_row_stride(cap) * 2; }
 
@@ -1580,21 +1764,52 @@ size_t build_plan_bytes(int64_t tiles)
            r(sizeof(float) * t * kTile * kRuns);
 }
 
+template <bool EXCL, int NT, int LPR>
+static hipError_t fast_attr(int dyn)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_build_fast<EXCL, NT, LPR>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+}
+
 hipError_t prepare_nlist(int cap)
 {
     const int dyn = kTile * nlist_row_stride(cap) * 2;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_build_fast<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_build_fast<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    return e;
+    const hipError_t es[8] = {fast_attr<false, 512, 64>(dyn), fast_attr<false, 256, 64>(dyn),
+                              fast_attr<false, 512, 32>(dyn), fast_attr<false, 256, 32>(dyn),
+                              fast_attr<true, 512, 64>(dyn),  fast_attr<true, 256, 64>(dyn),
+                              fast_attr<true, 512, 32>(dyn),  fast_attr<true, 256, 32>(dyn)};
+    for (hipError_t e : es)
+        if (e != hipSuccess) return e;
+    return hipSuccess;
 }
 
+template <bool EXCL, int NT, int LPR>
+static void fast_inst(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int blocks, int rs, size_t dyn,
+                      const PlanPtrs &plan)
+{
+    hipLaunchKernelGGL((k_build_fast<EXCL, NT, LPR>), dim3(blocks), dim3(NT), dyn, L.stream, L.sys, L.tprefix_local,
+                       L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size, L.cell_idx, L.cell_xf, L.cell_cap,
+                       L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n, L.halo_cap, plan, L.halo_lds, L.rare_list,
+                       L.rare_n, L.cell_count, L.n_cells, L.flag, L.sflag, L.build_count, L.status);
+}
+
+template <bool EXCL>
+static void fast_shape(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int blocks, int rs, size_t dyn,
+                       const PlanPtrs &plan, int w, int block)
+{
+    if (w == 32) {
+        if (block == 256) fast_inst<EXCL, 256, 32>(L, pos, tag, blocks, rs, dyn, plan);
+        else fast_inst<EXCL, 512, 32>(L, pos, tag, blocks, rs, dyn, plan);
+    } else {
+        if (block == 256) fast_inst<EXCL, 256, 64>(L, pos, tag, blocks, rs, dyn, plan);
+        else fast_inst<EXCL, 512, 64>(L, pos, tag, blocks, rs, dyn, plan);
+    }
+}
+
+// w: lanes per row of the framed build (64 or 32); block: its threads per
+// workgroup (512 or 256).  The general build's shape is fixed.
 void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int w, int block)
 {
-    (void)w;
-    (void)block;
     if (L.tiles_local == 0) {
         // no framed scan to clear the cell counts
         if (L.n_cells > 0)
@@ -1606,22 +1821,14 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
     const size_t dyn = (size_t)kTile * rs * 2;
     const PlanPtrs plan = plan_ptrs(L.plan, L.tiles_local);
     if (L.has_bonds) {
-        hipLaunchKernelGGL(k_build_fast<true>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
-                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
-                           L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
-                           L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.cell_count, L.n_cells, L.flag,
-                           L.sflag, L.build_count, L.status);
+        fast_shape<true>(L, pos, tag, blocks, rs, dyn, plan, w, block);
         hipLaunchKernelGGL(k_build_tile<true>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
                            L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
                            nullptr, L.status);
     } else {
-        hipLaunchKernelGGL(k_build_fast<false>, dim3(blocks), dim3(kFastThreads), dyn, L.stream, L.sys,
-                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
-                           L.cell_idx, L.cell_xf, L.cell_cap, L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n,
-                           L.halo_cap, plan, L.halo_lds, L.rare_list, L.rare_n, L.cell_count, L.n_cells, L.flag,
-                           L.sflag, L.build_count, L.status);
+        fast_shape<false>(L, pos, tag, blocks, rs, dyn, plan, w, block);
         hipLaunchKernelGGL(k_build_tile<false>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
                            L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/hoomd_mi355x.h"
@@ -75,10 +77,14 @@ bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         if (q.tpp_force < 0 || q.tpp_force > 16 || (q.tpp_force & (q.tpp_force - 1))) return false;
         if (q.bond_cap < 0 || q.bond_cap > kMaxBondCap) return false;
         if (q.check_period < 0 || q.check_period != p[0].check_period) return false;
-        // the build's launch shape is fixed (reported by hoomd_autotune); the
-        // force pass runs 64 rows x tpp_force lanes per workgroup
-        if (q.tpp_nlist != 0 && q.tpp_nlist != nlist_lanes_per_row()) return false;
-        if (q.block_nlist != 0 && q.block_nlist != nlist_block()) return false;
+        if (q.tune_period < 0 || q.tune_period != p[0].tune_period) return false;
+        if (q.tpp_force != p[0].tpp_force || q.block_force != p[0].block_force) return false;
+        // launch shapes: the framed build takes 64 or 32 lanes per row and 512
+        // or 256 threads per workgroup (one shape for all systems); the force
+        // pass runs 64 rows x tpp_force lanes per workgroup
+        if (q.tpp_nlist != 0 && !nlist_shape_ok(q.tpp_nlist, nlist_block())) return false;
+        if (q.block_nlist != 0 && !nlist_shape_ok(nlist_lanes_per_row(), q.block_nlist)) return false;
+        if (q.tpp_nlist != p[0].tpp_nlist || q.block_nlist != p[0].block_nlist) return false;
         if (q.block_force != 0 && (q.tpp_force == 0 || q.block_force != 64 * q.tpp_force)) return false;
         if (b.n_local < 0 || b.n_cap < b.n_local || b.n_cap > (int64_t)1 << 30) return false;
         if (b.n_bonds < 0 || (b.n_bonds > 0 && q.bond_cap == 0)) return false;
@@ -280,6 +286,13 @@ struct hoomd_ctx {
     bool built;        // a neighbour list exists for the current rows
     int64_t ghosts;    // ghost rows appended over all systems (no sorting then)
     int tpp_nlist, block_nlist, tpp_force, block_force;
+    // autotuner state: shapes fixed by the caller are not tuned
+    bool fixed_force, fixed_nlist;
+    int tune_period;
+    uint64_t last_tune_step;
+    bool retune;
+    int scans, from_cache;
+    float force_ms[5], build_ms[4];
     int check_period;  // displacement check every this many steps after a build
     int last_log_rows;
     uint64_t steps_done;
@@ -292,7 +305,7 @@ struct hoomd_ctx {
     // [p][1] 2 kLongPairs steps
     hipStream_t cap_stream;
     hipGraphExec_t graph_exec[2][2];
-    int graph_tpp[2][2];
+    int graph_sig[2][2];  // launch shapes the graph was captured with
     ~hoomd_ctx()
     {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -317,6 +330,10 @@ void default_tuning(hoomd_ctx *c)
     const double per_cu = (double)c->lay.tiles_local * 64.0 / 256.0;
     c->tpp_nlist = nlist_lanes_per_row();
     c->block_nlist = nlist_block();
+    if (c->prm[0].tpp_nlist > 0) c->tpp_nlist = c->prm[0].tpp_nlist;
+    if (c->prm[0].block_nlist > 0) c->block_nlist = c->prm[0].block_nlist;
+    c->fixed_nlist = c->prm[0].tpp_nlist > 0 || c->prm[0].block_nlist > 0;
+    c->fixed_force = c->prm[0].tpp_force > 0;
     c->tpp_force = per_cu > 2048 ? 4 : 8;
     if (c->prm[0].tpp_force > 0) c->tpp_force = c->prm[0].tpp_force;
     c->block_force = 64 * c->tpp_force;
@@ -408,7 +425,8 @@ constexpr int kLongPairs = 8;
 int ensure_step_graph(hoomd_ctx *c, int p, int kind, double4 *const *P, double4 *const *V, bool dpd)
 {
     hipGraphExec_t &ge = c->graph_exec[p][kind];
-    if (ge && c->graph_tpp[p][kind] == c->tpp_force) return HOOMD_OK;
+    const int sig = c->tpp_force | (c->tpp_nlist << 8) | (c->block_nlist << 16);
+    if (ge && c->graph_sig[p][kind] == sig) return HOOMD_OK;
     if (ge) {
         (void)hipGraphExecDestroy(ge);
         ge = nullptr;
@@ -436,9 +454,13 @@ int ensure_step_graph(hoomd_ctx *c, int p, int kind, double4 *const *P, double4 
         ge = nullptr;
         return HOOMD_E_DEVICE;
     }
-    c->graph_tpp[p][kind] = c->tpp_force;
+    c->graph_sig[p][kind] = sig;
     return HOOMD_OK;
 }
+
+// Scans every candidate launch shape (or takes a cached choice); defined
+// with the autotuner below.
+int tune_now(hoomd_ctx *c, bool use_cache);
 
 }  // namespace
 
@@ -483,6 +505,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     }
     c->built = false;
     c->check_period = params[0].check_period > 1 ? params[0].check_period : 1;
+    c->tune_period = params[0].tune_period;
     c->last_log_rows = 0;
     c->steps_done = 0;
 
@@ -664,6 +687,11 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
         if (c->lay.sys[s].n_total != c->lay.sys[s].n_local || !c->box[s].periodic[0] ||
             !c->box[s].periodic[1] || !c->box[s].periodic[2])
             return HOOMD_E_STATE;  // stepping a subdomain needs particle migration
+    if (c->tune_period > 0 &&
+        (c->retune || c->scans + c->from_cache == 0 || c->steps_done - c->last_tune_step >= (uint64_t)c->tune_period)) {
+        const int trc = tune_now(c, false);
+        if (trc) return trc;
+    }
     int rc = build_nlist(c, 0);
     if (rc) return rc;
 
@@ -847,6 +875,7 @@ int unpack_ghosts(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, u
     u.tag = c->arr.tag;
     if (queue_ghost_unpack(c->stream, u)) return HOOMD_E_DEVICE;
     if (mode == HOOMD_GHOST_SELECT) {
+        if (S.n_total != S.n_local + n_recv) c->retune = c->tune_period > 0;  // the shape changed
         c->ghosts += (int64_t)(S.n_local + n_recv) - S.n_total;
         S.n_total = (int32_t)(S.n_local + n_recv);
         HIP_OK(hipMemcpyAsync(ws_ptr<SysDev>(c, c->lay.sysdev) + sys, &S, sizeof(SysDev),
@@ -944,42 +973,168 @@ static float median5(hoomd_ctx *c, Fn launch, hipEvent_t e0, hipEvent_t e1)
     return t[2];
 }
 
-extern "C" {
+// ---------------------------------------------------------------------------
+// Autotuner (Sec. 5.2): time every candidate launch shape on the live state,
+// keep the fastest, remember it per kind of context for the process.
+// ---------------------------------------------------------------------------
 
-int hoomd_autotune(hoomd_ctx *c, int32_t do_tune, hoomd_tuning *out)
+namespace {
+
+constexpr int kBuildShapes[4][2] = {{64, 512}, {64, 256}, {32, 512}, {32, 256}};
+
+struct TuneEntry {
+    int tpp_force, tpp_nlist, block_nlist;
+    float force_ms[5], build_ms[4];
+};
+std::mutex g_tune_mu;
+std::map<uint64_t, TuneEntry> g_tune_cache;
+
+// Kind of context: pair potential, precision, bonds, particle count (power of
+// two) and the mean neighbour count of system 0 (bins of 4) from its density
+// and list radius.
+uint64_t tune_key(const hoomd_ctx *c)
 {
-    if (!c) return HOOMD_E_ARG;
-    if (do_tune) {
-        // a current neighbour list, then the force pass over lanes per row
-        // (the workgroup is 64 rows x W lanes)
-        int rc = build_nlist(c, 0);
-        if (rc) return rc;
-        const double4 *pos = reinterpret_cast<const double4 *>(c->arr.pos);
-        hipEvent_t e0, e1;
-        HIP_OK(hipEventCreate(&e0));
-        HIP_OK(hipEventCreate(&e1));
-        float best = 1e30f;
-        int bw = c->tpp_force;
+    int64_t n = 0;
+    for (const auto &b : c->box) n += b.n_local;
+    int nb = 0;
+    while (nb < 62 && ((int64_t)1 << (nb + 1)) <= n) ++nb;
+    const hoomd_params &q = c->prm[0];
+    const hoomd_box &b = c->box[0];
+    const double rho = (double)std::max<int64_t>(b.n_cap, 1) / (b.L[0] * b.L[1] * b.L[2]);
+    const double rl = pair_cut(q) + q.r_buff;
+    const int nbar = (int)std::min(4.0 / 3.0 * M_PI * rl * rl * rl * rho / 4.0, 4095.0);
+    return (uint64_t)(c->pair_uniform + 1) | ((uint64_t)c->mixed << 4) | ((uint64_t)(c->lay.bond_cap > 0) << 5) |
+           ((uint64_t)nb << 8) | ((uint64_t)nbar << 16);
+}
+
+int tune_now(hoomd_ctx *c, bool use_cache)
+{
+    const uint64_t key = tune_key(c);
+    if (use_cache) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const TuneEntry &E = it->second;
+            if (!c->fixed_force) {
+                c->tpp_force = E.tpp_force;
+                c->block_force = 64 * E.tpp_force;
+            }
+            if (!c->fixed_nlist) {
+                c->tpp_nlist = E.tpp_nlist;
+                c->block_nlist = E.block_nlist;
+            }
+            std::copy(E.force_ms, E.force_ms + 5, c->force_ms);
+            std::copy(E.build_ms, E.build_ms + 4, c->build_ms);
+            c->from_cache = 1;
+            c->last_tune_step = c->steps_done;
+            c->retune = false;
+            return HOOMD_OK;
+        }
+    }
+    // a current neighbour list, cells and plans
+    int rc = build_nlist(c, 0);
+    if (rc) return rc;
+    const double4 *pos = reinterpret_cast<const double4 *>(c->arr.pos);
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return HOOMD_E_DEVICE;
+    }
+    std::fill(c->force_ms, c->force_ms + 5, 0.f);
+    std::fill(c->build_ms, c->build_ms + 4, 0.f);
+    if (!c->fixed_force) {
+        // the force pass over lanes per row (the workgroup is 64 rows x W lanes)
         ForceLaunch F = base_force(c);
         F.pos = pos;
         F.vel = reinterpret_cast<const double4 *>(c->arr.vel);
         F.vel_out = reinterpret_cast<double4 *>(c->arr.vel);
         F.mode = MODE_FORCE;
-        for (int w = 1; w <= 16; w <<= 1) {
+        float best = 1e30f;
+        int bw = c->tpp_force;
+        for (int k = 0; k < 5; ++k) {
+            const int w = 1 << k;
             const float t = median5(c, [&] { launch_force(c->L, F, w, 64 * w); }, e0, e1);
-            if (t < best) { best = t; bw = w; }
+            c->force_ms[k] = t;
+            if (t < best) {
+                best = t;
+                bw = w;
+            }
         }
         c->tpp_force = bw;
         c->block_force = 64 * bw;
-        HIP_OK(hipEventDestroy(e0));
-        HIP_OK(hipEventDestroy(e1));
-        HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    if (!c->fixed_nlist && c->lay.tiles_local > 0) {
+        // the list build over its shapes, on the cells and plans just made:
+        // each timed launch redoes the framed and the general build (the list
+        // of tiles for the force pass's second launch is emptied first)
+        int32_t *flag = flag_ptr(c, 2), *sflag = sflag_ptr(c, 2);
+        float best = 1e30f;
+        int bk = 0;
+        for (int k = 0; k < 4; ++k) {
+            const int w = kBuildShapes[k][0], b = kBuildShapes[k][1];
+            const float t = median5(c,
+                                    [&] {
+                                        launch_set_flag(c->L, flag_ptr(c, 7), 0);
+                                        launch_set_flags(c->L, flag, sflag, 1);
+                                        c->L.flag = flag;
+                                        c->L.sflag = sflag;
+                                        launch_nlist(c->L, pos, c->arr.tag, w, b);
+                                    },
+                                    e0, e1);
+            c->build_ms[k] = t;
+            if (t < best) {
+                best = t;
+                bk = k;
+            }
+        }
+        c->tpp_nlist = kBuildShapes[bk][0];
+        c->block_nlist = kBuildShapes[bk][1];
+        // a whole rebuild with the chosen shape leaves the state as it was
+        launch_set_flags(c->L, flag, sflag, 1);
+        queue_rebuild(c, pos, c->arr.tag, 2, 0);
+    }
+    const bool ok = hipStreamSynchronize(c->stream) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return HOOMD_E_DEVICE;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        TuneEntry E{};
+        E.tpp_force = c->tpp_force;
+        E.tpp_nlist = c->tpp_nlist;
+        E.block_nlist = c->block_nlist;
+        std::copy(c->force_ms, c->force_ms + 5, E.force_ms);
+        std::copy(c->build_ms, c->build_ms + 4, E.build_ms);
+        g_tune_cache[key] = E;
+    }
+    ++c->scans;
+    c->from_cache = 0;
+    c->last_tune_step = c->steps_done;
+    c->retune = false;
+    return HOOMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hoomd_autotune(hoomd_ctx *c, int32_t do_tune, hoomd_tuning *out)
+{
+    if (!c || do_tune < 0 || do_tune > 2) return HOOMD_E_ARG;
+    if (do_tune) {
+        const int rc = tune_now(c, do_tune == 2);
+        if (rc) return rc;
     }
     if (out) {
         out->tpp_nlist = c->tpp_nlist;
         out->block_nlist = c->block_nlist;
         out->tpp_force = c->tpp_force;
         out->block_force = c->block_force;
+        for (int k = 0; k < 5; ++k) out->force_ms[k] = c->force_ms[k];
+        for (int k = 0; k < 4; ++k) out->build_ms[k] = c->build_ms[k];
+        out->scans = c->scans;
+        out->from_cache = c->from_cache;
     }
     return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
 }

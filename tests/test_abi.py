@@ -99,8 +99,10 @@ def test_tuning_and_check_period_fields_are_validated(hlib):
         return hlib.hoomd_workspace_bytes(C.byref(p), 1, C.byref(box))
 
     assert ws() > 0
-    assert ws(tpp_nlist=64, block_nlist=512) > 0
-    assert ws(tpp_nlist=4) == 0 and ws(block_nlist=256) == 0
+    for w, b in ((64, 512), (64, 256), (32, 512), (32, 256)):
+        assert ws(tpp_nlist=w, block_nlist=b) > 0
+    assert ws(tpp_nlist=4) == 0 and ws(block_nlist=128) == 0 and ws(tpp_nlist=16, block_nlist=512) == 0
+    assert ws(tune_period=100) > 0 and ws(tune_period=-1) == 0
     for w in (1, 2, 4, 8, 16):
         assert ws(tpp_force=w, block_force=64 * w) > 0
         assert ws(tpp_force=w, block_force=64 * w + 64) == 0
