@@ -92,8 +92,7 @@ def run_precision(B, inputs, torch, s, prec, steps, warmup, tune, fixed=None, pr
     out = dict(ms=max(gpu_ms, 1e-9), wall=wall, prof=prof, prof_steps=ps, prof_ms=prof_ms,
                prof_builds=ctx.build_count() - b1, nbar=nbar, builds=builds,
                drift=abs(E1 - E0) / abs(E0), T_end=float(log[-1, 0, 4]),
-               tuning=dict(tpp_nlist=tuning.tpp_nlist, block_nlist=tuning.block_nlist,
-                           tpp_force=tuning.tpp_force, block_force=tuning.block_force))
+               tuning=_tuning_dict(tuning))
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -125,14 +124,21 @@ def force_check(B, torch, s):
     return {"max_err_over_Frms": err, "tolerance": 1e-5, "pass": err <= 1e-5, "F_rms": frms}
 
 
+def _tuning_dict(t):
+    return {"tpp_force": t.tpp_force, "block_force": t.block_force, "tpp_nlist": t.tpp_nlist,
+            "block_nlist": t.block_nlist, "force_ms": [round(x, 4) for x in t.force_ms],
+            "build_ms": [round(x, 4) for x in t.build_ms], "scans": t.scans, "from_cache": t.from_cache}
+
+
 def other_workload(B, torch, label, params, systems, steps, warmup, t0=0):
     """Mixed-precision throughput of a secondary workload (context beside the
-    headline: the same product path, captured steps replayed): total
-    particles x steps / device time of `steps` steps after `warmup` steps
-    that start at step t0 (the context sorts the rows at init)."""
+    headline: the same product path, captured steps replayed, launch shapes
+    chosen by the autotuner): total particles x steps / device time of
+    `steps` steps after `warmup` steps that start at step t0 (the context
+    sorts the rows at init)."""
     ctx = B.Context(params, systems)
     ctx.build_nlist(True)
-    tuning = ctx.autotune(False)  # the default lanes per row and block sizes
+    tuning = ctx.autotune(1)
     ctx.step(t0, warmup)
     ctx.check()
     torch.cuda.synchronize()
@@ -148,10 +154,147 @@ def other_workload(B, torch, label, params, systems, steps, warmup, t0=0):
     n = sum(int(sy["pos"].shape[0]) for sy in systems)
     out = {"workload": label, "value": n * steps / (ms / 1e3), "unit": "particle-timesteps/s",
            "steps_per_s": steps / (ms / 1e3), "particles": n, "systems": len(systems), "steps": steps,
-           "rebuilds": ctx.build_count() - b0,
-           "precision": "mixed", "tuning": {"tpp_force": tuning.tpp_force, "tpp_nlist": tuning.tpp_nlist}}
+           "rebuilds": ctx.build_count() - b0, "precision": "mixed", "tuning": _tuning_dict(tuning)}
     ctx.close()
     del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_per_system(B, torch, params, systems, steps, warmup):
+    """The same ensemble with every system in a context of its own, stepped
+    one context after another on one stream (per-system launches, each
+    context's steps replayed as captured graphs), for comparison with the one
+    batched context."""
+    ctxs = [B.Context([p], [sy]) for p, sy in zip(params, systems)]
+    for c in ctxs:
+        c.build_nlist(True)
+        c.autotune(2)
+        c.step(0, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for c in ctxs:
+        c.step(warmup, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.check()
+    ms = e0.elapsed_time(e1)
+    n = sum(int(sy["pos"].shape[0]) for sy in systems)
+    for c in ctxs:
+        c.close()
+    del ctxs
+    torch.cuda.empty_cache()
+    return {"value": n * steps / (ms / 1e3), "unit": "particle-timesteps/s", "steps": steps,
+            "launches": "one context per system, stepped in turn"}
+
+
+def subdomain_phases(B, inputs, torch, reps=200):
+    """The one-GPU share of the strong-scaling shape: subdomain 0 of the
+    864,000-particle LJ box cut 3 x 3 x 3 (32,000 locals, ghost layer 2.9),
+    mixed precision.  The ghost exchange between the 27 subdomains is done
+    once as device copies on this GPU to obtain subdomain 0's receive
+    buffer (a stand-in for the transport).  Per phase, the HIP-event time of
+    one call averaged over `reps` calls: ghost selection + packing of
+    subdomain 0's send list, the per-step re-gather (update) of that list,
+    unpacking of its receive buffer (select, and update in place), the local
+    forces; then one step's worth of subdomain 0 (update pack, update unpack,
+    local forces) launched eagerly and replayed as a captured graph."""
+    import numpy as np
+    W, margin = 2.9, 0.25
+    sd = inputs.lj_subdomain_box(grid=3, cells=60)
+    full = sd.full
+    frame = sd.side + 2 * (W + margin)
+    rho = full.n / float(np.prod(full.L))
+    n_cap = int(1.2 * rho * frame ** 3) + 64
+    fields = B.FIELD_POS | B.FIELD_TAG
+    rec = 32
+    dev = torch.device("cuda:0")
+    s_side = torch.cuda.Stream()
+    with torch.cuda.stream(s_side):
+        # all 27 subdomains in one context: every send list, then the slices
+        # destined for subdomain 0
+        systems, params = [], []
+        for k in range(27):
+            loc = sd.local(k)
+            systems.append(dict(pos=full.pos[loc], vel=full.vel[loc], tag=loc.astype(np.int32),
+                                L=np.full(3, frame), lo=sd.lo(k) - W - margin, periodic=(0, 0, 0), n_cap=n_cap))
+            params.append(B.ModelParams(precision=B.MIXED, nlist_cap=160))
+        ctx27 = B.Context(params, systems)
+        cap = 8 * max(ctx27.n_local)
+        sends, counts, offs = [], [], []
+        for k in range(27):
+            buf = torch.zeros(cap * rec, dtype=torch.uint8, device=dev)
+            cnt = torch.zeros(26, dtype=torch.int32, device=dev)
+            off = torch.zeros(26, dtype=torch.int32, device=dev)
+            ctx27.pack_ghosts(k, sd.lo(k), sd.hi(k), W, B.GHOST_SELECT, fields, buf, cap, cnt, off)
+            sends.append(buf)
+            counts.append(cnt)
+            offs.append(off)
+        ctx27.check()
+        hc = [c.cpu().numpy() for c in counts]
+        ho = [o.cpu().numpy() for o in offs]
+        pieces = []
+        for k in range(1, 27):
+            a = np.array([k % 3, (k // 3) % 3, k // 9])
+            d = (np.zeros(3, dtype=np.int64) - a + 1) % 3 - 1
+            dk = int((d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1))
+            dk = dk if dk < 13 else dk - 1
+            pieces.append(sends[k][int(ho[k][dk]) * rec:(int(ho[k][dk]) + int(hc[k][dk])) * rec])
+        recv = torch.cat(pieces).contiguous()
+        n_recv = recv.numel() // rec
+        ctx27.close()
+        del ctx27, sends
+        # subdomain 0 alone: its own context on a stream that can be captured
+        ctx = B.Context([B.ModelParams(precision=B.MIXED, nlist_cap=160)],
+                        [systems[0]])
+        send = torch.zeros(cap * rec, dtype=torch.uint8, device=dev)
+        cnt = torch.zeros(26, dtype=torch.int32, device=dev)
+        off = torch.zeros(26, dtype=torch.int32, device=dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+
+        def timed(fn, n=reps):
+            fn()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) * 1e3 / n
+
+        lo0, hi0 = sd.lo(0), sd.hi(0)
+        out = {"workload": "lj_subdomain_32k", "locals": int(ctx.n_local[0]), "ghosts": int(n_recv),
+               "send_entries": None, "precision": "mixed"}
+        out["select_pack_us"] = timed(lambda: ctx.pack_ghosts(0, lo0, hi0, W, B.GHOST_SELECT, fields, send, cap,
+                                                              cnt, off))
+        out["send_entries"] = int(cnt.sum().item())
+        out["update_pack_us"] = timed(lambda: ctx.pack_ghosts(0, lo0, hi0, W, B.GHOST_UPDATE, fields, send, cap,
+                                                              cnt, off))
+        out["unpack_select_us"] = timed(lambda: ctx.unpack_ghosts(0, recv, n_recv, fields, B.GHOST_SELECT, full.L),
+                                        n=20)
+        out["unpack_update_us"] = timed(lambda: ctx.unpack_ghosts(0, recv, n_recv, fields, B.GHOST_UPDATE, full.L))
+        ctx.compute_forces(0, 0)
+        out["local_forces_us"] = timed(lambda: ctx.compute_forces(0, 0))
+
+        def one_step():
+            ctx.pack_ghosts(0, lo0, hi0, W, B.GHOST_UPDATE, fields, send, cap, cnt, off)
+            ctx.unpack_ghosts(0, recv, n_recv, fields, B.GHOST_UPDATE, full.L)
+            ctx.compute_forces(0, 0)
+
+        out["step_eager_us"] = timed(one_step)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s_side):
+            one_step()
+        out["step_graph_us"] = timed(g.replay)
+        ctx.check()
+        out["graph_speedup"] = out["step_eager_us"] / out["step_graph_us"]
+        ctx.close()
+        del g, ctx
+    torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return out
 
@@ -181,8 +324,16 @@ def other_workloads(B, inputs, torch, steps, warmup):
                   for sy in batch]
         systems = [dict(pos=sy.pos, vel=sy.vel, L=sy.L, bonds=sy.bonds, tag=sy.tag) for sy in batch]
         res["batch_256"] = other_workload(B, torch, "batch_256", params, systems, steps, warmup)
+        res["batch_256"]["per_system_launches"] = batch_per_system(B, torch, params, systems,
+                                                                   max(steps // 5, 20), warmup)
+        res["batch_256"]["batched_over_per_system"] = (res["batch_256"]["value"] /
+                                                       res["batch_256"]["per_system_launches"]["value"])
     except Exception as e:
         res["batch_256"] = {"error": repr(e)}
+    try:
+        res["subdomain_32k"] = subdomain_phases(B, inputs, torch)
+    except Exception as e:
+        res["subdomain_32k"] = {"error": repr(e)}
     return res
 
 
@@ -275,7 +426,17 @@ def cpu_baseline(s, seconds):
             break
         m = min(s.n, int(m * max(2.0, min(16.0, seconds / max(t, 1e-3)))))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": m / t, "unit": "particle-timesteps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "host_logical_cpus": os.cpu_count(),
             "sample": (f"FP64 brute-force forces of {m} random particles against all {s.n} "
                        f"(O(N) each, minimum image), {t:.1f} s; the integration is negligible "
                        f"beside it")}
