@@ -66,8 +66,8 @@ __host__ __device__ constexpr int halo_entry_bytes(int pot) { return pot == PAIR
 // Rows may be read this many entries past their end (two passes of the
 // widest split): the neighbour list is padded by as many tile columns.
 constexpr int kRowOverRead = 2 * 4 * 16;
-constexpr int kRareGrid = 256;  // workgroups of the launch over the rare tiles
-constexpr size_t kRareLds = 96 * 1024;  // LDS of a workgroup of that launch, at most
+constexpr int kRareGrid = 1024;  // workgroups of the launch over the rare tiles
+constexpr size_t kRareLds = 40 * 1024;  // LDS of a workgroup of that launch, at most (four per CU)
 
 // One tile of the fused step.  RARE selects the code for tiles with a
 // per-pair image or a halo larger than the LDS staging area; the main

@@ -22,6 +22,7 @@ struct LaunchCtx {
     const SysDev *sys;
     const int32_t *tprefix_local;  // n_sys+1 prefix of local tiles
     const int32_t *tprefix_all;    // n_sys+1 prefix of tiles over all rows
+    const int64_t *cprefix;        // n_sys+1 prefix of cells
     int tiles_local;
     int tiles_all;
     int64_t n_cells;

@@ -111,13 +111,15 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
     }
 }
 
-// System owning a cell (largest s with sys[s].cell0 <= c).
-__device__ __forceinline__ int find_sys_cell(const SysDev *__restrict__ sys, int n_sys, int64_t c)
+// System owning a cell: largest s with cprefix[s] <= c (cprefix holds each
+// system's first cell; a compact array, so the search stays in the scalar
+// cache).
+__device__ __forceinline__ int find_sys_cell(const int64_t *__restrict__ cprefix, int n_sys, int64_t c)
 {
     int lo = 0, hi = n_sys;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (sys[mid].cell0 <= c) lo = mid;
+        if (cprefix[mid] <= c) lo = mid;
         else hi = mid;
     }
     return lo;
@@ -133,7 +135,7 @@ __device__ __forceinline__ int find_sys_cell(const SysDev *__restrict__ sys, int
 // cleared by the framed scan.  cell_cap <= 64 * CPL.
 template <int CPL>
 __device__ __forceinline__ void cell_sort_waves(int64_t wfirst, int64_t wstep, const SysDev *__restrict__ sys,
-                                                int n_sys, const double4 *__restrict__ pos, int64_t n_cells,
+                                                const int64_t *__restrict__ cprefix, int n_sys, const double4 *__restrict__ pos, int64_t n_cells,
                                                 const int32_t *__restrict__ cell_count,
                                                 int32_t *__restrict__ cell_size, int32_t *__restrict__ cell_idx,
                                                 float4 *__restrict__ cell_xf, int cell_cap,
@@ -141,7 +143,7 @@ __device__ __forceinline__ void cell_sort_waves(int64_t wfirst, int64_t wstep, c
 {
     const int lane = lane_id();
     for (int64_t c = wfirst; c < n_cells; c += wstep) {
-        const int s = find_sys_cell(sys, n_sys, c);
+        const int s = find_sys_cell(cprefix, n_sys, c);
         if (!sflag[s]) continue;  // this system keeps its list
         int m = cell_count[c];
         m = m < cell_cap ? m : cell_cap;
@@ -847,7 +849,8 @@ __device__ __forceinline__ void plan_tiles(
     PlanShared &ps, int pb, int npb, const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
     int n_sys, int tiles, const double4 *__restrict__ pos, const int32_t *__restrict__ cell_count, int cell_cap,
     double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan,
-    const int32_t *__restrict__ sflag)
+    const int32_t *__restrict__ sflag, const int32_t *__restrict__ halo_n, int halo_lds,
+    int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n)
 {
     uint32_t *box = ps.box;
     int32_t *bpre = ps.bpre;
@@ -859,7 +862,16 @@ __device__ __forceinline__ void plan_tiles(
     die_range(pb, npb, tiles, tfirst, tend, tstep);
     for (int tile = (int)tfirst; tile < tend; tile += tstep) {
         const int s = find_sys(tprefix, n_sys, tile);
-        if (!sflag[s]) continue;  // this system keeps its list
+        if (!sflag[s]) {
+            // a system that keeps its list: its tile goes back on the list of
+            // the force pass's second launch if its last build put it there
+            // (the binning launch before this one emptied that list)
+            if (lane == 0) {
+                const int32_t hn = halo_n[tile];
+                if (hn < 0 || (hn & 0xFFFF) > halo_lds) rare_list[atomicAdd(rare_n, 1)] = tile;
+            }
+            continue;
+        }
         const SysDev &S = sys[s];
         const double Ls[3] = {S.L[0], S.L[1], S.L[2]};
         const int bins[3] = {S.bins[0], S.bins[1], S.bins[2]};
@@ -1081,20 +1093,22 @@ __device__ __forceinline__ void plan_tiles(
 // workgroups sort cells while the others plan tiles.
 template <int CPL>
 __global__ __launch_bounds__(kWave) void k_cells_and_plan(
-    int n_sort, const SysDev *__restrict__ sys, int n_sys, const int32_t *__restrict__ tprefix, int tiles,
+    int n_sort, const SysDev *__restrict__ sys, const int64_t *__restrict__ cprefix, int n_sys,
+    const int32_t *__restrict__ tprefix, int tiles,
     const double4 *__restrict__ pos, int64_t n_cells, const int32_t *__restrict__ cell_count,
     int32_t *__restrict__ cell_size, int32_t *__restrict__ cell_idx, float4 *__restrict__ cell_xf, int cell_cap,
     double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan,
-    const int32_t *__restrict__ flag, const int32_t *__restrict__ sflag)
+    const int32_t *__restrict__ flag, const int32_t *__restrict__ sflag, const int32_t *__restrict__ halo_n,
+    int halo_lds, int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n)
 {
     if (*flag == 0) return;
     if ((int)blockIdx.x < n_sort) {
-        cell_sort_waves<CPL>(blockIdx.x, n_sort, sys, n_sys, pos, n_cells, cell_count, cell_size, cell_idx, cell_xf,
-                             cell_cap, sflag);
+        cell_sort_waves<CPL>(blockIdx.x, n_sort, sys, cprefix, n_sys, pos, n_cells, cell_count, cell_size, cell_idx,
+                             cell_xf, cell_cap, sflag);
     } else {
         __shared__ PlanShared ps;
         plan_tiles(ps, (int)blockIdx.x - n_sort, (int)gridDim.x - n_sort, sys, tprefix, n_sys, tiles, pos,
-                   cell_count, cell_cap, xbuild, slow_list, slow_n, plan, sflag);
+                   cell_count, cell_cap, xbuild, slow_list, slow_n, plan, sflag, halo_n, halo_lds, rare_list, rare_n);
     }
 }
 
@@ -1156,12 +1170,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     for (int tile = (int)tfirst; tile < tend; tile += tstep) {
         const int s = find_sys(tprefix, n_sys, tile);
         if (!sflag[s]) {
-            // a system that keeps its list: its tile goes back on the list
-            // of the force pass's second launch if its last build put it there
-            if (tid == 0) {
-                const int32_t hn = halo_n[tile];
-                if (hn < 0 || (hn & 0xFFFF) > halo_lds) rare_list[atomicAdd(rare_n, 1)] = tile;
-            }
+            // a system that keeps its list (the binning launch has put its
+            // tile back on the second force launch's list if needed)
             hd_next = next_header(plan.hdr, tile + tstep < tend ? tile + tstep : tile);
             continue;
         }
@@ -1726,13 +1736,15 @@ void launch_cell_sort(const LaunchCtx &L, const double4 *pos)
     const PlanPtrs plan = plan_ptrs(L.plan, L.tiles_local);
     const dim3 grid((unsigned)(n_sort + n_plan));
     if (L.cell_cap <= 64)
-        hipLaunchKernelGGL(k_cells_and_plan<1>, grid, dim3(kWave), 0, L.stream, (int)n_sort, L.sys, L.n_sys,
+        hipLaunchKernelGGL(k_cells_and_plan<1>, grid, dim3(kWave), 0, L.stream, (int)n_sort, L.sys, L.cprefix, L.n_sys,
                            L.tprefix_local, L.tiles_local, pos, L.n_cells, L.cell_count, L.cell_size, L.cell_idx,
-                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag, L.sflag);
+                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag, L.sflag,
+                           L.halo_n, L.halo_lds, L.rare_list, L.rare_n);
     else
-        hipLaunchKernelGGL(k_cells_and_plan<2>, grid, dim3(kWave), 0, L.stream, (int)n_sort, L.sys, L.n_sys,
+        hipLaunchKernelGGL(k_cells_and_plan<2>, grid, dim3(kWave), 0, L.stream, (int)n_sort, L.sys, L.cprefix, L.n_sys,
                            L.tprefix_local, L.tiles_local, pos, L.n_cells, L.cell_count, L.cell_size, L.cell_idx,
-                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag, L.sflag);
+                           L.cell_xf, L.cell_cap, L.xbuild, L.slow_list, L.slow_n, plan, L.flag, L.sflag,
+                           L.halo_n, L.halo_lds, L.rare_list, L.rare_n);
 }
 
 int nlist_row_stride(int cap)

@@ -34,7 +34,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
     // byte offsets into the workspace
-    size_t sysdev, tpl, tpa, status, flags, sysflags, thermo, thermo_log, partials;
+    size_t sysdev, tpl, tpa, cpre, status, flags, sysflags, thermo, thermo_log, partials;
     size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, cell_xf, halo, halo_n;
     size_t rtag, partners, slow_list, rare_list, plan, sort_ws, ghost_ws, total;
     // sizes
@@ -42,6 +42,7 @@ struct Layout {
     int cell_cap, nlist_cap, bond_cap, halo_cap, halo_lds;
     std::vector<SysDev> sys;
     std::vector<int32_t> tpl_host, tpa_host;
+    std::vector<int64_t> cpre_host;
 };
 
 double pair_cut(const hoomd_params &p)
@@ -106,6 +107,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     int64_t row = 0, tile = 0, tile_all = 0, cell = 0, nl = 0;
     Lo.tpl_host.push_back(0);
     Lo.tpa_host.push_back(0);
+    Lo.cpre_host.push_back(0);
     Lo.halo_cap = 64;
     Lo.halo_lds = 64;
     for (int s = 0; s < n_sys; ++s) {
@@ -220,6 +222,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         nl += ceil_div(b.n_local, kTile) * kTile * (int64_t)Lo.nlist_cap;
         Lo.tpl_host.push_back((int32_t)tile);
         Lo.tpa_host.push_back((int32_t)tile_all);
+        Lo.cpre_host.push_back(cell);
         (void)vol;
     }
     Lo.rows = row;
@@ -238,6 +241,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.sysdev = take(sizeof(SysDev) * n_sys);
     Lo.tpl = take(sizeof(int32_t) * (n_sys + 1));
     Lo.tpa = take(sizeof(int32_t) * (n_sys + 1));
+    Lo.cpre = take(sizeof(int64_t) * (n_sys + 1));
     Lo.status = take(sizeof(Status));
     Lo.flags = take(sizeof(int32_t) * 8);
     Lo.sysflags = take(sizeof(int32_t) * 4 * (size_t)n_sys);
@@ -515,6 +519,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.sys = ws_ptr<SysDev>(c, lay.sysdev);
     L.tprefix_local = ws_ptr<int32_t>(c, lay.tpl);
     L.tprefix_all = ws_ptr<int32_t>(c, lay.tpa);
+    L.cprefix = ws_ptr<int64_t>(c, lay.cpre);
     L.tiles_local = (int)lay.tiles_local;
     L.tiles_all = (int)lay.tiles_all;
     L.n_cells = lay.n_cells;
@@ -562,6 +567,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.sysdev, lay.sys.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpl, lay.tpl_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.tpa, lay.tpa_host.data(), sizeof(int32_t) * (n_sys + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->ws + lay.cpre, lay.cpre_host.data(), sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.status, 0, sizeof(Status));
     if (e == hipSuccess) e = hipMemset(c->ws + lay.flags, 0, sizeof(int32_t) * 8);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.sysflags, 0, sizeof(int32_t) * 4 * (size_t)n_sys);

@@ -14,7 +14,7 @@ from tests.gpu_helpers import LJ, by_tag, frel, min_image_diff
 pytestmark = pytest.mark.gpu
 TOL = {0: 1e-12, 1: 1e-5}
 DPD_PRM = [25.0, 4.5, 1.0, 1.0, 0.02, 33]
-DPD_RARE_STAGE = 96 * 1024 // 52  # halo entries the second launch stages in LDS for DPD
+DPD_RARE_STAGE = 40 * 1024 // 52  # halo entries the second launch stages in LDS for DPD
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +39,7 @@ def _shuffled(sys_, seed):
 def test_dpd_forces_second_launch(orc, B, prec, n):
     """Unsorted rows of a DPD fluid: every tile spans the box, so it needs
     per-pair images; at 12,000 particles the tile halos (about 2,100
-    entries) also exceed the 1,890 entries the second launch stages in LDS,
+    entries) also exceed the 787 entries the second launch stages in LDS,
     so their tails are read from global memory (velocities and tags too)."""
     ref = inputs.dpd_fluid(n, 51, 52)
     s, perm = _shuffled(ref, 7)
