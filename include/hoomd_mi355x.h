@@ -254,6 +254,45 @@ int pack_ghosts_noalloc(const double *pos, const double *vel, const int32_t *tag
                         const hoomd_subdomain *subdomain, uint32_t fields, void *send, int64_t send_cap,
                         int32_t *counts26, int32_t *offsets26, void *stream);
 
+/* Velocity-Verlet in two halves around a ghost exchange or a migration
+ * (Sec. 3, Sec. 4.2), for subdomains whose neighbours live elsewhere:
+ *   which = 0: v += dt/2 F (F from the last compute_forces() or second half),
+ *              x += dt v (folded on periodic axes), and the displacement
+ *              check (r_buff/2 since the last build) that hoomd_rebuild_due()
+ *              reports;
+ *   which = 1: forces at `timestep` (building the list first if needed, e.g.
+ *              after ghosts were selected anew), then v += dt/2 F.
+ * The caller updates the ghosts between the halves (pack / unpack UPDATE),
+ * or, when a rebuild is due, migrates particles and selects ghosts anew.
+ * Both halves cover the local rows of every system and only queue work. */
+int integrate_half_step(hoomd_ctx *ctx, int32_t which, uint64_t timestep);
+
+/* 1 in *due when the last first half step found a particle of some system
+ * farther than r_buff/2 from its position at the last build.  Synchronises. */
+int hoomd_rebuild_due(hoomd_ctx *ctx, int32_t *due);
+
+/* Particle migration (Sec. 4.3.1) for system `sys`: every local particle
+ * outside the subdomain [lo, hi) (per axis: x >= hi goes up, x < lo goes
+ * down; it moves at most one subdomain per rebuild) leaves for the neighbour
+ * its position lies in, direction index as for ghosts.  Its position,
+ * velocity and tag are packed into `send` (record layout of pack_ghosts with
+ * all three fields, ordered by direction then row; counts26 / offsets26 as
+ * there), and the particles that stay are compacted in their order to the
+ * front of the system's rows.  The ghosts of the system are dropped (select
+ * them again after the arrivals).  *n_sent receives the number that left;
+ * more than send_cap returns HOOMD_E_GHOST_OVERFLOW (records past send_cap
+ * are not written).  Bonded systems: HOOMD_E_STATE.  Synchronises (the
+ * counts set the new local count). */
+int migrate_particles(hoomd_ctx *ctx, int32_t sys, const hoomd_subdomain *subdomain, void *send,
+                      int64_t send_cap, int32_t *counts26, int32_t *offsets26, int64_t *n_sent);
+
+/* Append n_recv migrated particles (records as migrate_particles() writes
+ * them: position, velocity, tag) after the locals of system `sys`; each
+ * position is moved to its periodic image nearest the centre of the
+ * system's frame (box_L = the full periodic box).  Requires the system to
+ * hold no ghosts; exceeding n_cap returns HOOMD_E_GHOST_OVERFLOW. */
+int receive_particles(hoomd_ctx *ctx, int32_t sys, const void *recv, int64_t n_recv, const double *box_L);
+
 /* Ghost unpacking (Sec. 4.3.2: ghosts are appended after the local
  * particles; Sec. 9: DPD ghosts carry velocities and IDs).  Append
  * (HOOMD_GHOST_SELECT) or overwrite in place (HOOMD_GHOST_UPDATE)
@@ -298,6 +337,8 @@ int hoomd_build_count(hoomd_ctx *ctx, int64_t *builds);
  *          cell_size[c] (global row numbers, ascending);
  *   bins per axis.  Row i of system s is row row_offset + i of the arrays,
  *   tile t of the system is tile tile_offset + t of halo and halo_n.
+ *   The local rows of a system are tiled over its capacity n_cap, so the
+ *   tiles past n_local are empty (rows arriving by migration fill them).
  *   general_tiles: int32 count, over all systems, of the tiles that the
  *   last build handed from the framed build to the general one;
  *   rare_tiles: int32 count, over all systems, of the tiles that the force
@@ -321,6 +362,8 @@ typedef struct {
     const int32_t *rare_tiles;
     int32_t halo_lds;
     int32_t pad_;
+    int64_t n_local;   /* current local rows of the system (migration changes it) */
+    int64_t n_total;   /* locals + ghosts */
 } hoomd_layout;
 int hoomd_get_layout(hoomd_ctx *ctx, int32_t sys, hoomd_layout *out);
 

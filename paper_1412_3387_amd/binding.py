@@ -67,7 +67,8 @@ class Layout(C.Structure):
                 ("nlist_cap", C.c_int32), ("cell_cap", C.c_int32), ("halo_cap", C.c_int32),
                 ("bins", C.c_int32 * 3), ("row_offset", C.c_int64), ("cell_offset", C.c_int64),
                 ("tile_offset", C.c_int64), ("general_tiles", C.c_void_p),
-                ("rare_tiles", C.c_void_p), ("halo_lds", C.c_int32), ("pad_", C.c_int32)]
+                ("rare_tiles", C.c_void_p), ("halo_lds", C.c_int32), ("pad_", C.c_int32),
+                ("n_local", C.c_int64), ("n_total", C.c_int64)]
 
 
 class Tuning(C.Structure):
@@ -88,7 +89,8 @@ class Profile(C.Structure):
 EXPORTS = ["hoomd_workspace_bytes", "hoomd_init", "hoomd_destroy", "build_nlist",
            "compute_forces", "step", "pack_ghosts", "unpack_ghosts", "hoomd_thermo",
            "hoomd_thermo_log", "hoomd_sync_status", "hoomd_build_count", "hoomd_get_layout",
-           "hoomd_autotune", "hoomd_profile", "hoomd_strerror", "pack_ghosts_noalloc"]
+           "hoomd_autotune", "hoomd_profile", "hoomd_strerror", "pack_ghosts_noalloc",
+           "integrate_half_step", "hoomd_rebuild_due", "migrate_particles", "receive_particles"]
 
 _lib = None
 
@@ -128,6 +130,11 @@ def lib():
         L.hoomd_profile.argtypes = [P, C.c_int32, C.POINTER(Profile)]
         L.pack_ghosts_noalloc.argtypes = [P, P, P, C.c_int64, C.POINTER(Subdomain), C.c_uint32, P,
                                           C.c_int64, P, P, P]
+        L.integrate_half_step.argtypes = [P, C.c_int32, C.c_uint64]
+        L.hoomd_rebuild_due.argtypes = [P, C.POINTER(C.c_int32)]
+        L.migrate_particles.argtypes = [P, C.c_int32, C.POINTER(Subdomain), P, C.c_int64, P, P,
+                                        C.POINTER(C.c_int64)]
+        L.receive_particles.argtypes = [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_double)]
         L.hoomd_strerror.argtypes = [C.c_int]
         L.hoomd_strerror.restype = C.c_char_p
         _lib = L
@@ -319,6 +326,37 @@ class Context:
     def unpack_ghosts(self, sys: int, recv, n_recv: int, fields: int, mode: int, box_L):
         bl = (C.c_double * 3)(*[float(x) for x in box_L])
         _check(lib().unpack_ghosts(self.h, sys, _ptr(recv), n_recv, fields, mode, bl), "unpack_ghosts")
+
+    def integrate_half_step(self, which: int, timestep: int = 0):
+        _check(lib().integrate_half_step(self.h, which, timestep), "integrate_half_step")
+
+    def rebuild_due(self) -> bool:
+        v = C.c_int32()
+        _check(lib().hoomd_rebuild_due(self.h, C.byref(v)), "hoomd_rebuild_due")
+        return bool(v.value)
+
+    def _refresh_counts(self, sys: int):
+        self.n_local[sys] = int(self.layout(sys).n_local)
+
+    def migrate_particles(self, sys: int, lo, hi, send, send_cap: int, counts, offsets) -> int:
+        """Pack and remove the locals of `sys` that left [lo, hi); returns how
+        many left (their records: position, velocity, tag; 56 bytes each)."""
+        sd = Subdomain()
+        for a in range(3):
+            sd.lo[a] = float(lo[a])
+            sd.hi[a] = float(hi[a])
+        sd.width = 0.0
+        n = C.c_int64()
+        code = lib().migrate_particles(self.h, sys, C.byref(sd), _ptr(send), send_cap, _ptr(counts),
+                                       _ptr(offsets), C.byref(n))
+        self._refresh_counts(sys)
+        _check(code, "migrate_particles")
+        return n.value
+
+    def receive_particles(self, sys: int, recv, n_recv: int, box_L):
+        bl = (C.c_double * 3)(*[float(x) for x in box_L])
+        _check(lib().receive_particles(self.h, sys, _ptr(recv), n_recv, bl), "receive_particles")
+        self._refresh_counts(sys)
 
     def thermo(self) -> np.ndarray:
         out = (C.c_double * (4 * self.n_sys))()

@@ -541,6 +541,14 @@ __global__ __launch_bounds__(1024) void k_thermo_reduce(const SysDev *__restrict
 
 __global__ void k_set_flag(int32_t *flag, int32_t v) { *flag = v; }
 
+// The local and total row counts of one system's device descriptor (values
+// passed as arguments: no host memory is read when the launch runs).
+__global__ void k_set_counts(SysDev *sys, int s, int32_t n_local, int32_t n_total)
+{
+    sys[s].n_local = n_local;
+    sys[s].n_total = n_total;
+}
+
 __global__ void k_set_flags(int32_t *flag, int32_t *sflag, int n_sys, int32_t v)
 {
     if (threadIdx.x == 0) *flag = v;
@@ -562,6 +570,59 @@ __global__ void k_disp_check(const SysDev *__restrict__ sys, const int32_t *__re
     if (r >= S.n_local) return;
     const int64_t i = S.row0 + r;
     const double4 x = pos[i], xb = xbuild[i];
+    const double bx = min_image(x.x - xb.x, S.L[0], S.invL[0]);
+    const double by = min_image(x.y - xb.y, S.L[1], S.invL[1]);
+    const double bz = min_image(x.z - xb.z, S.L[2], S.invL[2]);
+    if ((bx * bx + by * by) + bz * bz > S.disp2) {
+        *flag = 1;
+        sflag[s] = 1;
+    }
+}
+
+// One half of a velocity-Verlet step over the local rows, from the force
+// array of the last force evaluation (unit mass).  which = 0: v += dt/2 F,
+// x += dt v (folded on periodic axes), and the displacement check since the
+// last build (Sec. 4.2) sets the rebuild flags; which = 1: v += dt/2 F.
+template <bool MIXED>
+__global__ void k_half_step(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys,
+                            int tiles, double4 *__restrict__ pos, double4 *__restrict__ vel,
+                            const void *__restrict__ force, int which, const double4 *__restrict__ xbuild,
+                            int32_t *flag, int32_t *sflag)
+{
+    const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (g >= tiles) return;
+    const int s = find_sys(tprefix, n_sys, g);
+    const SysDev &S = sys[s];
+    const int r = (g - S.tile0) * kTile + lane_id();
+    if (r >= S.n_local) return;
+    const int64_t i = S.row0 + r;
+    double fx, fy, fz;
+    if (MIXED) {
+        const float4 f = reinterpret_cast<const float4 *>(force)[i];
+        fx = f.x;
+        fy = f.y;
+        fz = f.z;
+    } else {
+        const double4 f = reinterpret_cast<const double4 *>(force)[i];
+        fx = f.x;
+        fy = f.y;
+        fz = f.z;
+    }
+    double4 v = vel[i];
+    v.x += S.hdt * fx;
+    v.y += S.hdt * fy;
+    v.z += S.hdt * fz;
+    vel[i] = v;
+    if (which != 0) return;
+    double4 x = pos[i];
+    x.x += S.dt * v.x;
+    x.y += S.dt * v.y;
+    x.z += S.dt * v.z;
+    if (S.per[0]) x.x = fold(x.x, S.lo[0], S.L[0]);
+    if (S.per[1]) x.y = fold(x.y, S.lo[1], S.L[1]);
+    if (S.per[2]) x.z = fold(x.z, S.lo[2], S.L[2]);
+    pos[i] = x;
+    const double4 xb = xbuild[i];
     const double bx = min_image(x.x - xb.x, S.L[0], S.invL[0]);
     const double by = min_image(x.y - xb.y, S.L[1], S.invL[1]);
     const double bz = min_image(x.z - xb.z, S.L[2], S.invL[2]);
@@ -696,6 +757,11 @@ void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value)
     hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, L.stream, flag, value);
 }
 
+void launch_set_counts(const LaunchCtx &L, int s, int32_t n_local, int32_t n_total)
+{
+    hipLaunchKernelGGL(k_set_counts, dim3(1), dim3(1), 0, L.stream, const_cast<SysDev *>(L.sys), s, n_local, n_total);
+}
+
 void launch_set_flags(const LaunchCtx &L, int32_t *flag, int32_t *sflag, int32_t value)
 {
     hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(256), 0, L.stream, flag, sflag, L.n_sys, value);
@@ -708,6 +774,20 @@ void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag, in
     if (blocks == 0) return;
     hipLaunchKernelGGL(k_disp_check, dim3(blocks), dim3(threads), 0, L.stream, L.sys,
                        L.tprefix_local, L.n_sys, L.tiles_local, pos, L.xbuild, flag, sflag);
+}
+
+void launch_half_step(const LaunchCtx &L, double4 *pos, double4 *vel, const void *force, bool mixed, int which,
+                      int32_t *flag, int32_t *sflag)
+{
+    const int threads = 256;
+    const int blocks = (L.tiles_local * kWave + threads - 1) / threads;
+    if (blocks == 0) return;
+    if (mixed)
+        hipLaunchKernelGGL(k_half_step<true>, dim3(blocks), dim3(threads), 0, L.stream, L.sys, L.tprefix_local,
+                           L.n_sys, L.tiles_local, pos, vel, force, which, L.xbuild, flag, sflag);
+    else
+        hipLaunchKernelGGL(k_half_step<false>, dim3(blocks), dim3(threads), 0, L.stream, L.sys, L.tprefix_local,
+                           L.n_sys, L.tiles_local, pos, vel, force, which, L.xbuild, flag, sflag);
 }
 
 void launch_rtag(const LaunchCtx &L, const int32_t *tag)

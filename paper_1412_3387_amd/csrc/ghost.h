@@ -17,6 +17,9 @@ struct GhostBuffers {
     int32_t *blk_sums;    // block sums of that scan
     int32_t *list;        // kGhostPerRow slots per row: system s owns [8 row0_s, 8 (row0_s + n_cap_s))
     int32_t *totals;      // entries of the stored list of each system
+    int32_t *stay;        // migration: 1 per local row that stays, scanned in place
+    int32_t *stay_sums;   // block sums of that scan
+    int32_t *counts2;     // migration: {rows leaving, rows staying}
     int64_t rows;
 };
 
@@ -56,6 +59,15 @@ GhostBuffers make_ghost_buffers(char *base, int64_t rows, int n_sys);
 int queue_ghost_select(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g);
 int queue_ghost_update(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g);
 int queue_ghost_unpack(hipStream_t stream, const UnpackArgs &u);
+
+// Migration of the local rows that left the subdomain [g.lo, g.hi) (Sec.
+// 4.3.1): each leaving row goes to the one neighbour its position lies in
+// (direction index as for ghosts), packed into g.send ordered by direction
+// then row (counts / offsets per direction as for ghosts); the rows that stay
+// are compacted in order to the front of the system's rows with the scratch
+// arrays pos_tmp / vel_tmp / tag_tmp.  B.counts2 receives {left, stayed}.
+int queue_migrate(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g, double4 *pos, double4 *vel,
+                  int32_t *tag, double4 *pos_tmp, double4 *vel_tmp, int32_t *tag_tmp);
 
 // Selection + packing with the library's fixed device scratch instead of a
 // workspace (no stored list, no status word): rows [0, n_local) of g.pos.

@@ -25,12 +25,13 @@ size_t ghost_workspace_bytes(int64_t rows, int n_sys)
     const int64_t blocks = (rows + kGhostBlock - 1) / kGhostBlock;
     return a256(sizeof(uint32_t) * rows) + a256(sizeof(int32_t) * 26 * (size_t)blocks) +
            a256(sizeof(int32_t) * scan_sums_len(26 * blocks)) +
-           a256(sizeof(int32_t) * kGhostPerRow * (size_t)rows) + a256(sizeof(int32_t) * n_sys) + 256;
+           a256(sizeof(int32_t) * kGhostPerRow * (size_t)rows) + a256(sizeof(int32_t) * n_sys) +
+           a256(sizeof(int32_t) * rows) + a256(sizeof(int32_t) * scan_sums_len(rows)) + a256(sizeof(int32_t) * 2) +
+           256;
 }
 
 GhostBuffers make_ghost_buffers(char *base, int64_t rows, int n_sys)
 {
-    (void)n_sys;
     GhostBuffers B{};
     const int64_t blocks = (rows + kGhostBlock - 1) / kGhostBlock;
     size_t off = 0;
@@ -38,7 +39,10 @@ GhostBuffers make_ghost_buffers(char *base, int64_t rows, int n_sys)
     B.blk_counts = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * 26 * (size_t)blocks);
     B.blk_sums = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * scan_sums_len(26 * blocks));
     B.list = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * kGhostPerRow * (size_t)rows);
-    B.totals = reinterpret_cast<int32_t *>(base + off);
+    B.totals = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * n_sys);
+    B.stay = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * rows);
+    B.stay_sums = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * scan_sums_len(rows));
+    B.counts2 = reinterpret_cast<int32_t *>(base + off);
     B.rows = rows;
     return B;
 }
@@ -196,6 +200,62 @@ __global__ void k_ghost_unpack(UnpackArgs u)
     if (u.fields & 4u) u.tag[row] = reinterpret_cast<const int32_t *>(rec + q)[0];
 }
 
+// Destination of a local row after a drift: per axis +1 at or beyond hi, -1
+// below lo, else 0; the direction's bit (index as for ghosts), or 0 when the
+// row stays.
+__device__ __forceinline__ uint32_t leave_mask(const double4 x, const GhostArgs &g)
+{
+    const double xs[3] = {x.x, x.y, x.z};
+    int d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = xs[a] >= g.hi[a] ? 1 : (xs[a] < g.lo[a] ? -1 : 0);
+    if (d[0] == 0 && d[1] == 0 && d[2] == 0) return 0u;
+    int k = (d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1);
+    k = k < 13 ? k : k - 1;
+    return 1u << k;
+}
+
+__global__ __launch_bounds__(kGhostBlock) void k_migrate_mask(GhostArgs g, int32_t *__restrict__ blk_counts,
+                                                             int nblocks, int32_t *__restrict__ stay)
+{
+    __shared__ int32_t wc[kGhostBlock / 64][26];
+    const int r = blockIdx.x * kGhostBlock + threadIdx.x;
+    uint32_t m = 0;
+    if (r < g.n_local) {
+        m = leave_mask(g.pos[g.row0 + r], g);
+        g.mask[r] = m;
+        stay[r] = m == 0u ? 1 : 0;
+    }
+    wave_dir_counts(m, wc);
+    __syncthreads();
+    if (threadIdx.x < 26) {
+        int32_t t = 0;
+        for (int w = 0; w < kGhostBlock / 64; ++w) t += wc[w][threadIdx.x];
+        blk_counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = t;
+    }
+}
+
+// Rows that stay, in order, to the front (through the scratch arrays).
+__global__ void k_migrate_compact(int64_t row0, int n_local, const int32_t *__restrict__ mask,
+                                  const int32_t *__restrict__ dst, const double4 *__restrict__ pos,
+                                  const double4 *__restrict__ vel, const int32_t *__restrict__ tag,
+                                  double4 *__restrict__ pos_tmp, double4 *__restrict__ vel_tmp,
+                                  int32_t *__restrict__ tag_tmp)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_local || mask[r] != 0) return;
+    const int64_t d = row0 + dst[r];
+    pos_tmp[d] = pos[row0 + r];
+    vel_tmp[d] = vel[row0 + r];
+    tag_tmp[d] = tag[row0 + r];
+}
+
+__global__ void k_migrate_counts(const int32_t *__restrict__ left, int32_t *__restrict__ counts2, int any_local)
+{
+    counts2[0] = *left;
+    if (!any_local) counts2[1] = 0;
+}
+
 int queue_ghost_select(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g)
 {
     const int nblocks = (g.n_local + kGhostBlock - 1) / kGhostBlock;
@@ -207,6 +267,31 @@ int queue_ghost_select(hipStream_t stream, const GhostBuffers &B, const GhostArg
     hipLaunchKernelGGL(k_ghost_totals, dim3(1), dim3(64), 0, stream, B.blk_counts, g.total, nb, g.counts,
                        g.offsets, g.send_cap, list_cap, g.status);
     hipLaunchKernelGGL(k_ghost_scatter, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+int queue_migrate(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g, double4 *pos, double4 *vel,
+                  int32_t *tag, double4 *pos_tmp, double4 *vel_tmp, int32_t *tag_tmp)
+{
+    const int nblocks = (g.n_local + kGhostBlock - 1) / kGhostBlock;
+    const int nb = nblocks > 0 ? nblocks : 1;
+    // leaving rows: direction masks and counts, the ordered send records
+    hipLaunchKernelGGL(k_migrate_mask, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb, B.stay);
+    launch_scan(stream, B.blk_counts, B.blk_counts, 26 * (int64_t)nb, g.total, B.blk_sums);
+    const int64_t list_cap = g.list ? g.list_cap : INT64_MAX;
+    hipLaunchKernelGGL(k_ghost_totals, dim3(1), dim3(64), 0, stream, B.blk_counts, g.total, nb, g.counts,
+                       g.offsets, g.send_cap, list_cap, g.status);
+    hipLaunchKernelGGL(k_ghost_scatter, dim3(nb), dim3(kGhostBlock), 0, stream, g, B.blk_counts, nb);
+    // staying rows: their new places (the scan's total is the count that
+    // stays), then the compacted copy into the scratch arrays
+    if (g.n_local > 0) {
+        launch_scan(stream, B.stay, B.stay, g.n_local, B.counts2 + 1, B.stay_sums);
+        const int blocks = (g.n_local + 255) / 256;
+        hipLaunchKernelGGL(k_migrate_compact, dim3(blocks), dim3(256), 0, stream, g.row0, g.n_local,
+                           reinterpret_cast<const int32_t *>(g.mask), B.stay, pos, vel, tag, pos_tmp, vel_tmp,
+                           tag_tmp);
+    }
+    hipLaunchKernelGGL(k_migrate_counts, dim3(1), dim3(1), 0, stream, g.total, B.counts2, g.n_local > 0 ? 1 : 0);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 

@@ -88,9 +88,15 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
 void launch_force(const LaunchCtx &L, const ForceLaunch &F, int w, int block);
 void launch_thermo_reduce(const LaunchCtx &L, int w, int log_row, double timestep);
 void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value);
+// Sets the local and total row counts in system s's device descriptor.
+void launch_set_counts(const LaunchCtx &L, int s, int32_t n_local, int32_t n_total);
 // Sets a rebuild flag and all per-system flags of its slot.
 void launch_set_flags(const LaunchCtx &L, int32_t *flag, int32_t *sflag, int32_t value);
 void launch_rtag(const LaunchCtx &L, const int32_t *tag);
+// Half a velocity-Verlet step over the local rows (which = 0: kick, drift,
+// displacement check into flag / sflag; 1: kick) from the force array.
+void launch_half_step(const LaunchCtx &L, double4 *pos, double4 *vel, const void *force, bool mixed, int which,
+                      int32_t *flag, int32_t *sflag);
 void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag, int32_t *sflag);
 size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
 int force_row_over_read();

@@ -849,7 +849,7 @@ __device__ __forceinline__ void plan_tiles(
     PlanShared &ps, int pb, int npb, const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
     int n_sys, int tiles, const double4 *__restrict__ pos, const int32_t *__restrict__ cell_count, int cell_cap,
     double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan,
-    const int32_t *__restrict__ sflag, const int32_t *__restrict__ halo_n, int halo_lds,
+    const int32_t *__restrict__ sflag, int32_t *__restrict__ halo_n, int halo_lds,
     int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n)
 {
     uint32_t *box = ps.box;
@@ -880,6 +880,15 @@ __device__ __forceinline__ void plan_tiles(
         const int n_local = S.n_local;
         const double rl2 = S.rl2;
         const int r0 = (tile - S.tile0) * kTile;
+        if (r0 >= n_local) {
+            // a tile past the local rows (room for particles that may
+            // arrive): an empty list and halo, nothing to build
+            if (lane == 0) {
+                plan.hdr[tile] = make_int4(0, 0, 0, 0);
+                halo_n[tile] = 0;
+            }
+            continue;
+        }
         const float cw[3] = {(float)(Ls[0] / bins[0]), (float)(Ls[1] / bins[1]), (float)(Ls[2] / bins[2])};
         auto pass_on = [&]() {
             if (lane == 0) {
@@ -1098,7 +1107,7 @@ __global__ __launch_bounds__(kWave) void k_cells_and_plan(
     const double4 *__restrict__ pos, int64_t n_cells, const int32_t *__restrict__ cell_count,
     int32_t *__restrict__ cell_size, int32_t *__restrict__ cell_idx, float4 *__restrict__ cell_xf, int cell_cap,
     double4 *__restrict__ xbuild, int32_t *__restrict__ slow_list, int32_t *__restrict__ slow_n, PlanPtrs plan,
-    const int32_t *__restrict__ flag, const int32_t *__restrict__ sflag, const int32_t *__restrict__ halo_n,
+    const int32_t *__restrict__ flag, const int32_t *__restrict__ sflag, int32_t *__restrict__ halo_n,
     int halo_lds, int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n)
 {
     if (*flag == 0) return;

@@ -216,10 +216,13 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         }
         Lo.sys.push_back(S);
         row += b.n_cap;
-        tile += ceil_div(b.n_local, kTile);
+        // local tiles cover the rows the system may own (its capacity), so
+        // that migration can change the local count without a new layout;
+        // tiles past the local rows are empty
+        tile += ceil_div(b.n_cap, kTile);
         tile_all += ceil_div(b.n_cap, kTile);
         cell += ncell;
-        nl += ceil_div(b.n_local, kTile) * kTile * (int64_t)Lo.nlist_cap;
+        nl += ceil_div(b.n_cap, kTile) * kTile * (int64_t)Lo.nlist_cap;
         Lo.tpl_host.push_back((int32_t)tile);
         Lo.tpa_host.push_back((int32_t)tile_all);
         Lo.cpre_host.push_back(cell);
@@ -854,6 +857,120 @@ int pack_ghosts_noalloc(const double *pos, const double *vel, const int32_t *tag
     return queue_ghost_select_static((hipStream_t)stream, g) ? HOOMD_E_DEVICE : HOOMD_OK;
 }
 
+int integrate_half_step(hoomd_ctx *c, int32_t which, uint64_t timestep)
+{
+    if (!c || (which != 0 && which != 1)) return HOOMD_E_ARG;
+    int32_t *flag = flag_ptr(c, 2), *sflag = sflag_ptr(c, 2);
+    if (which == 1) {
+        const int rc = compute_forces(c, timestep, 0);
+        if (rc) return rc;
+    } else {
+        launch_set_flags(c->L, flag, sflag, 0);  // set again by the displacement check below
+    }
+    launch_half_step(c->L, reinterpret_cast<double4 *>(c->arr.pos), reinterpret_cast<double4 *>(c->arr.vel),
+                     c->arr.force, c->mixed != 0, which, flag, sflag);
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
+}
+
+int hoomd_rebuild_due(hoomd_ctx *c, int32_t *due)
+{
+    if (!c || !due) return HOOMD_E_ARG;
+    int32_t v = 0;
+    HIP_OK(hipMemcpyAsync(&v, flag_ptr(c, 2), sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    *due = v != 0;
+    return HOOMD_OK;
+}
+
+int migrate_particles(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, void *send, int64_t send_cap,
+                      int32_t *counts26, int32_t *offsets26, int64_t *n_sent)
+{
+    if (!c || !sd || sys < 0 || sys >= c->n_sys || !counts26 || !offsets26 || !n_sent) return HOOMD_E_ARG;
+    if (send_cap < 0 || (send_cap > 0 && !send)) return HOOMD_E_ARG;
+    SysDev &S = c->lay.sys[sys];
+    if (S.bond_cap > 0) return HOOMD_E_STATE;  // bonded particles do not migrate
+    GhostArgs g{};
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = sd->lo[a];
+        g.hi[a] = sd->hi[a];
+    }
+    g.width = 0.0;
+    g.row0 = S.row0;
+    g.n_local = S.n_local;
+    g.fields = HOOMD_FIELD_POS | HOOMD_FIELD_VEL | HOOMD_FIELD_TAG;
+    g.send = send;
+    g.send_cap = send_cap;
+    g.counts = counts26;
+    g.offsets = offsets26;
+    g.pos = reinterpret_cast<const double4 *>(c->arr.pos);
+    g.vel = reinterpret_cast<const double4 *>(c->arr.vel);
+    g.tag = c->arr.tag;
+    g.status = c->L.status;
+    g.mask = c->ghostb.mask + S.row0;
+    g.list = nullptr;
+    g.list_cap = 0;
+    g.total = c->ghostb.totals + sys;
+    double4 *pt = ws_ptr<double4>(c, c->lay.pos_alt), *vt = ws_ptr<double4>(c, c->lay.vel_alt);
+    int32_t *tt = c->sortb.tag_tmp;
+    if (queue_migrate(c->stream, c->ghostb, g, reinterpret_cast<double4 *>(c->arr.pos),
+                      reinterpret_cast<double4 *>(c->arr.vel), c->arr.tag, pt, vt, tt))
+        return HOOMD_E_DEVICE;
+    if (S.n_local > 0) {
+        HIP_OK(hipMemcpyAsync(reinterpret_cast<double4 *>(c->arr.pos) + S.row0, pt + S.row0,
+                              sizeof(double4) * S.n_local, hipMemcpyDeviceToDevice, c->stream));
+        HIP_OK(hipMemcpyAsync(reinterpret_cast<double4 *>(c->arr.vel) + S.row0, vt + S.row0,
+                              sizeof(double4) * S.n_local, hipMemcpyDeviceToDevice, c->stream));
+        HIP_OK(hipMemcpyAsync(c->arr.tag + S.row0, tt + S.row0, sizeof(int32_t) * S.n_local,
+                              hipMemcpyDeviceToDevice, c->stream));
+    }
+    // the counts decide the new local count: read them (migration happens at
+    // neighbour-list builds only)
+    int32_t cnt[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(cnt, c->ghostb.counts2, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (cnt[0] + cnt[1] != S.n_local) return HOOMD_E_DEVICE;
+    c->ghosts -= (int64_t)S.n_total - S.n_local;  // the ghost layer is invalid after a migration
+    S.n_local = cnt[1];
+    S.n_total = cnt[1];
+    c->box[sys].n_local = cnt[1];
+    launch_set_counts(c->L, sys, S.n_local, S.n_total);
+    c->built = false;
+    c->retune = c->tune_period > 0;
+    *n_sent = cnt[0];
+    if (cnt[0] > send_cap) return HOOMD_E_GHOST_OVERFLOW;
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
+}
+
+int receive_particles(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, const double *box_L)
+{
+    if (!c || sys < 0 || sys >= c->n_sys || n_recv < 0 || (n_recv > 0 && !recv) || !box_L) return HOOMD_E_ARG;
+    SysDev &S = c->lay.sys[sys];
+    if (S.bond_cap > 0) return HOOMD_E_STATE;
+    if (S.n_total != S.n_local) return HOOMD_E_STATE;  // ghosts are selected after the arrivals
+    if (S.n_local + n_recv > c->box[sys].n_cap) return HOOMD_E_GHOST_OVERFLOW;
+    if (n_recv == 0) return HOOMD_OK;
+    UnpackArgs u{};
+    for (int a = 0; a < 3; ++a) {
+        u.box_L[a] = box_L[a];
+        u.center[a] = S.lo[a] + 0.5 * S.L[a];
+    }
+    u.first = S.row0 + S.n_local;
+    u.n = n_recv;
+    u.fields = HOOMD_FIELD_POS | HOOMD_FIELD_VEL | HOOMD_FIELD_TAG;
+    u.recv = recv;
+    u.pos = reinterpret_cast<double4 *>(c->arr.pos);
+    u.vel = reinterpret_cast<double4 *>(c->arr.vel);
+    u.tag = c->arr.tag;
+    if (queue_ghost_unpack(c->stream, u)) return HOOMD_E_DEVICE;
+    S.n_local += (int32_t)n_recv;
+    S.n_total = S.n_local;
+    c->box[sys].n_local = S.n_local;
+    launch_set_counts(c->L, sys, S.n_local, S.n_total);
+    c->built = false;
+    c->retune = c->tune_period > 0;
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
+}
+
 int unpack_ghosts(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, uint32_t fields,
                   int32_t mode, const double *box_L)
 {
@@ -884,9 +1001,7 @@ int unpack_ghosts(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, u
         if (S.n_total != S.n_local + n_recv) c->retune = c->tune_period > 0;  // the shape changed
         c->ghosts += (int64_t)(S.n_local + n_recv) - S.n_total;
         S.n_total = (int32_t)(S.n_local + n_recv);
-        HIP_OK(hipMemcpyAsync(ws_ptr<SysDev>(c, c->lay.sysdev) + sys, &S, sizeof(SysDev),
-                              hipMemcpyHostToDevice, c->stream));
-        HIP_OK(hipStreamSynchronize(c->stream));  // the copy reads host memory that later calls modify
+        launch_set_counts(c->L, sys, S.n_local, S.n_total);  // queued, no host wait
         c->built = false;
     }
     return HOOMD_OK;
@@ -955,6 +1070,8 @@ int hoomd_get_layout(hoomd_ctx *c, int32_t sys, hoomd_layout *out)
     out->rare_tiles = c->L.rare_n;
     out->halo_lds = c->L.halo_lds;
     out->pad_ = 0;
+    out->n_local = S.n_local;
+    out->n_total = S.n_total;
     return HOOMD_OK;
 }
 
