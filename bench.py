@@ -340,10 +340,11 @@ def other_workloads(B, inputs, torch, steps, warmup):
 COPY_BYTES = 1 << 30
 
 
-def pmc_pass(B, inputs, torch, s, fixed, steps):
+def pmc_pass(B, inputs, torch, s, fixed, steps, workload="lj"):
     """Workload for the hardware-counter passes: a plain streaming kernel of
     known size (an elementwise negation reading and writing COPY_BYTES each),
-    then eager mixed-precision steps of the LJ bulk system."""
+    then eager mixed-precision steps of the LJ bulk system (or, with
+    workload "dpd", of the 1,000,000-particle DPD fluid)."""
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
@@ -352,8 +353,13 @@ def pmc_pass(B, inputs, torch, s, fixed, steps):
     del a, b
     torch.cuda.empty_cache()
     kw = {k: int(fixed[k]) for k in ("tpp_nlist", "block_nlist", "tpp_force", "block_force")} if fixed else {}
-    p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_LJ, r_cut=2.5, r_buff=0.4, dt=0.005,
-                      sort_period=500, use_graph=0, **kw)
+    if workload == "dpd":
+        s = inputs.dpd_bulk()
+        p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=33,
+                          sort_period=100, use_graph=0, **kw)
+    else:
+        p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_LJ, r_cut=2.5, r_buff=0.4, dt=0.005,
+                          sort_period=500, use_graph=0, **kw)
     ctx = B.Context([p], [dict(pos=s.pos, vel=s.vel, L=s.L)])
     ctx.build_nlist(True)
     ctx.step(0, steps)
@@ -362,7 +368,7 @@ def pmc_pass(B, inputs, torch, s, fixed, steps):
     nbar = float(ctx._ws_view(lay.nn, s.n).double().mean().item())
     torch.cuda.synchronize()
     ctx.close()
-    print(json.dumps({"pmc_pass": True, "n": s.n, "steps": steps, "copy_bytes": COPY_BYTES,
+    print(json.dumps({"pmc_pass": True, "workload": workload, "n": s.n, "steps": steps, "copy_bytes": COPY_BYTES,
                       "mean_row": nbar}), flush=True)
 
 
@@ -461,6 +467,8 @@ def main():
                     help="use lanes/block sizes from a file written by --tuning-out (no tuning)")
     ap.add_argument("--prof-steps", type=int, default=1000,
                     help="steps of the eager window timed per launch after the timed window")
+    ap.add_argument("--pmc-workload", default="lj", choices=["lj", "dpd"],
+                    help="workload of --pmc-pass")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run the workload of a hardware-counter pass instead of the benchmark")
     ap.add_argument("--reduce-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -489,7 +497,7 @@ def main():
         with open(args.tuning_from) as f:
             fixed = json.load(f)
     if args.pmc_pass:
-        pmc_pass(B, inputs, torch, s, fixed.get("mixed"), args.steps)
+        pmc_pass(B, inputs, torch, s, fixed.get("mixed"), args.steps, args.pmc_workload)
         return
     mixed = run_precision(B, inputs, torch, s, B.MIXED, args.steps, args.warmup, not args.no_tune,
                           fixed.get("mixed"), args.prof_steps)
