@@ -66,6 +66,9 @@ def _declare(L):
     L.orc_run_nve.argtypes = [C.c_int, I64, P, P, P, P, P, I64, P, P, C.c_double, C.c_uint64,
                               I64, P, C.c_int, P]
     L.orc_run_nve.restype = C.c_int
+    L.orc_run_nvt.argtypes = [C.c_int, I64, P, P, P, P, P, I64, P, P, C.c_double, C.c_uint64,
+                              I64, P, P, P, P, P]
+    L.orc_run_nvt.restype = C.c_int
     L.orc_cell_bins.argtypes = [P, C.c_double, P]
     L.orc_cell_list.argtypes = [I64, P, P, P, P, P, P, P]
     L.orc_morton_keys.argtypes = [I64, P, P, P]
@@ -236,6 +239,34 @@ def run_nve(model: str, pos, vel, L, pair_prm, dt: float, nsteps: int, tag=None,
                            b.shape[0], _p(b), _p(bp), dt, t0, nsteps, _p(F),
                            1 if force is not None else 0, _p(th))
     return x, v, F, th, int(st)
+
+
+def run_nvt(model: str, pos, vel, L, pair_prm, dt: float, nsteps: int, T0: float, tau: float,
+            xi: float = 0.0, eta: float = 0.0, tag=None, bonds=None, bond_prm=(30.0, 1.5),
+            t0: int = 0):
+    """Nose-Hoover NVT with brute-force forces.  Returns (pos, vel, F,
+    thermo (nsteps+1, 4), ext (nsteps+1, 2) of {xi, eta}, status)."""
+    x = _f64(np.array(pos, dtype=np.float64))
+    v = _f64(np.array(vel, dtype=np.float64))
+    n = x.shape[0]
+    tag = _i32(tag) if tag is not None else np.arange(n, dtype=np.int32)
+    b = _i32(bonds).reshape(-1, 2) if bonds is not None else np.zeros((0, 2), dtype=np.int32)
+    F = np.zeros((n, 3))
+    th = np.zeros((nsteps + 1, 4))
+    ext = np.zeros((nsteps + 1, 2))
+    xe = np.array([xi, eta], dtype=np.float64)
+    nv = np.array([T0, tau], dtype=np.float64)
+    L_, pp, bp = _box(L), _f64(pair_prm), _f64(bond_prm)
+    st = lib().orc_run_nvt(MODEL[model], n, _p(x), _p(v), _p(tag), _p(L_), _p(pp),
+                           b.shape[0], _p(b), _p(bp), dt, t0, nsteps, _p(nv), _p(xe), _p(F),
+                           _p(th), _p(ext))
+    return x, v, F, th, ext, int(st)
+
+
+def nvt_conserved(thermo, ext, n: int, T0: float, tau: float):
+    """KE + PE + g T0 (tau^2 xi^2 / 2 + eta), g = 3n - 3, per row."""
+    g = 3.0 * n - 3.0
+    return thermo[:, 0] + thermo[:, 1] + g * T0 * (0.5 * tau * tau * ext[:, 0] ** 2 + ext[:, 1])
 
 
 def cell_bins(L, r_list: float) -> np.ndarray:

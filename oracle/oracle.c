@@ -421,6 +421,68 @@ ORC_API int orc_run_nve(int model, int64_t n, double *pos, double *vel, const in
 }
 
 /* ------------------------------------------------------------------------ */
+/* Nose-Hoover NVT (Sec. 6.1: the weak-scaling LJ runs use a Nose-Hoover     */
+/* thermostat that is not fully symplectic and needs one global kinetic-     */
+/* energy sum per step).  The paper gives no equations; the reading taken:   */
+/* the flow  dx/dt = v,  dv/dt = F - xi v,  dxi/dt = (T/T0 - 1) / tau^2,      */
+/* T = 2 KE / g with g = 3n - 3, advanced per step of length h as            */
+/*   v(t+h/2) = v(t) + h/2 (F(t) - xi(t) v(t))                               */
+/*   x(t+h)   = x(t) + h v(t+h/2), folded into the box                       */
+/*   xi(t+h)  = xi(t) + h/tau^2 (T(t+h/2)/T0 - 1)   (the one KE sum)         */
+/*   F(t+h)   = F(x(t+h), ...)                                               */
+/*   v(t+h)   = (v(t+h/2) + h/2 F(t+h)) / (1 + h/2 xi(t+h))                  */
+/* and eta(t+h) = eta(t) + h/2 (xi(t) + xi(t+h)) (trapezoid), deta/dt = xi.   */
+/* The flow conserves KE + PE + g T0 (tau^2 xi^2 / 2 + eta).                  */
+/* nvt = {T0, tau}; xi_eta = {xi, eta} in and out; thermo as orc_run_nve;     */
+/* ext (nsteps+1 rows of {xi, eta}) may be NULL.  Forces are computed at the  */
+/* start.  Returns as orc_run_nve.                                           */
+/* ------------------------------------------------------------------------ */
+
+ORC_API int orc_run_nvt(int model, int64_t n, double *pos, double *vel, const int32_t *tag,
+                        const double *L, const double *pprm, int64_t nb, const int32_t *bonds,
+                        const double *bprm, double dt, uint64_t t0, int64_t nsteps,
+                        const double *nvt, double *xi_eta, double *F, double *thermo, double *ext)
+{
+    double *u = (double *)calloc((size_t)n, sizeof(double));
+    double *w = (double *)calloc((size_t)n, sizeof(double));
+    const double hdt = 0.5 * dt, T0 = nvt[0], tau = nvt[1];
+    const double g = (double)(3 * n - 3);
+    double xi = xi_eta[0], eta = xi_eta[1];
+    int status = total_forces(model, n, pos, vel, tag, L, pprm, nb, bonds, bprm, t0, F, u, w);
+    if (thermo) orc_thermo(n, vel, u, w, thermo);
+    if (ext) {
+        ext[0] = xi;
+        ext[1] = eta;
+    }
+    for (int64_t s = 0; s < nsteps && status == 0; ++s) {
+        for (int64_t k = 0; k < 3 * n; ++k) vel[k] = vel[k] + hdt * (F[k] - xi * vel[k]);
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a)
+                pos[3 * i + a] = wrap1(pos[3 * i + a] + dt * vel[3 * i + a], L[a]);
+        double half[4];
+        orc_thermo(n, vel, NULL, NULL, half);
+        const double T_half = 2.0 * half[0] / g;
+        const double xi_new = xi + dt / (tau * tau) * (T_half / T0 - 1.0);
+        eta = eta + hdt * (xi + xi_new);
+        xi = xi_new;
+        status = total_forces(model, n, pos, vel, tag, L, pprm, nb, bonds, bprm,
+                              t0 + (uint64_t)s + 1u, F, u, w);
+        const double d = 1.0 + hdt * xi;
+        for (int64_t k = 0; k < 3 * n; ++k) vel[k] = (vel[k] + hdt * F[k]) / d;
+        if (thermo) orc_thermo(n, vel, u, w, thermo + 4 * (s + 1));
+        if (ext) {
+            ext[2 * (s + 1)] = xi;
+            ext[2 * (s + 1) + 1] = eta;
+        }
+    }
+    xi_eta[0] = xi;
+    xi_eta[1] = eta;
+    free(u);
+    free(w);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Cell list (Sec. 4.3.3 mentions the cell list; Fig. 4 step 1 looks up the  */
 /* cell neighbours).  bins_a = floor(L_a / r_list), reduced while a cell     */
 /* would be narrower than r_list; cell of x = floor((x - lo) * (bins / L)),  */

@@ -356,6 +356,87 @@ def test_nve_energy_conserved_on_lj_small(orc):
     assert abs(th[0, 3] - 1.2) < 1e-12
 
 
+# ---------------------------------------------------------------- NVT
+
+def test_nvt_without_coupling_is_nve(orc):
+    """xi = 0 and an infinite tau (h / tau^2 = 0): the Nose-Hoover step is
+    the velocity-Verlet step, bit for bit, and xi stays zero."""
+    s = inputs.lj_fluid(500, 5, 6)
+    x, v, F, th, st = orc.run_nve("lj", s.pos, s.vel, s.L, [1, 1, 2.5], 0.005, 30, with_thermo=True)
+    x2, v2, F2, th2, ext, st2 = orc.run_nvt("lj", s.pos, s.vel, s.L, [1, 1, 2.5], 0.005, 30,
+                                           T0=1.0, tau=1e200)
+    assert st == 0 and st2 == 0
+    assert np.array_equal(x, x2) and np.array_equal(v, v2) and np.array_equal(th, th2)
+    assert np.all(ext == 0)
+
+
+def _free_gas_nvt(orc, dt, t_end, T0, tau):
+    rng = np.random.default_rng(11)
+    L = np.array([40.0, 40.0, 40.0])
+    pos = rng.uniform(0, 40, (64, 3))
+    vel = rng.normal(size=(64, 3))
+    n = int(round(t_end / dt))
+    x, v, F, th, ext, st = orc.run_nvt("lj", pos, vel, L, [0.0, 1.0, 2.5], dt, n, T0=T0, tau=tau)
+    assert st == 0 and np.all(F == 0)
+    return vel, v, th, ext
+
+
+def test_nvt_free_gas_matches_ode_solver(orc):
+    """No forces: v(t) = v(0) exp(-zeta(t)) with zeta' = xi and
+    xi' = (T(0) exp(-2 zeta) / T0 - 1) / tau^2, solved by a high-accuracy
+    Runge-Kutta method; eta is zeta.  The discrete run converges to it at
+    second order in the step."""
+    from scipy.integrate import solve_ivp
+    T0, tau, t_end = 1.7, 0.4, 2.0
+    errs = []
+    for dt in (0.004, 0.002):
+        v0, v, th, ext = _free_gas_nvt(orc, dt, t_end, T0, tau)
+        Ti = th[0, 3]
+
+        def rhs(t, y):
+            return [y[1], (Ti * np.exp(-2.0 * y[0]) / T0 - 1.0) / tau ** 2]
+        sol = solve_ivp(rhs, (0, t_end), [0.0, 0.0], rtol=1e-12, atol=1e-13)
+        zeta, xi = sol.y[0, -1], sol.y[1, -1]
+        e = max(abs(ext[-1, 0] - xi), abs(ext[-1, 1] - zeta),
+                np.max(np.abs(v - v0 * np.exp(-zeta))) / np.max(np.abs(v0)))
+        errs.append(e)
+    assert errs[0] < 5e-4 and 3.0 < errs[0] / errs[1] < 5.0
+
+
+@pytest.fixture(scope="module")
+def melted(orc):
+    """The 500-particle LJ lattice after 1,000 NVE steps: a liquid at T ~ 0.65."""
+    s = inputs.lj_fluid(500, 5, 6)
+    x, v, F, th, st = orc.run_nve("lj", s.pos, s.vel, s.L, [1, 1, 2.5], 0.005, 1000)
+    assert st == 0
+    return x, v, s.L, s.n
+
+
+def test_nvt_extended_energy_is_conserved(orc, melted):
+    """The liquid heated towards T0 = 1: KE + PE alone changes by far more
+    than the extended energy, whose drift falls as the square of the step."""
+    x0, v0, L, n = melted
+    T0, tau = 1.0, 0.5
+    drift = []
+    for dt, steps in ((0.004, 500), (0.002, 1000)):
+        x, v, F, th, ext, st = orc.run_nvt("lj", x0, v0, L, [1, 1, 2.5], dt, steps, T0=T0, tau=tau)
+        assert st == 0
+        H = orc.nvt_conserved(th, ext, n, T0, tau)
+        E = th[:, 0] + th[:, 1]
+        drift.append(np.max(np.abs(H - H[0])))
+        assert np.max(np.abs(E - E[0])) > 1000 * drift[-1]
+    assert drift[0] / abs(H[0]) < 1e-3 and 3.0 < drift[0] / drift[1] < 5.5
+
+
+def test_nvt_holds_the_set_temperature(orc, melted):
+    """From T ~ 0.65 the thermostat brings the liquid to T0 = 1: the mean
+    temperature over steps 1,000-3,000 is within 2 % of T0."""
+    x0, v0, L, n = melted
+    x, v, F, th, ext, st = orc.run_nvt("lj", x0, v0, L, [1, 1, 2.5], 0.005, 3000, T0=1.0, tau=0.2)
+    assert st == 0 and th[0, 3] < 0.7
+    assert abs(np.mean(th[1000:, 3]) - 1.0) < 0.02
+
+
 # ---------------------------------------------------------------- thermo
 
 def test_thermo_sums(orc):
