@@ -135,7 +135,27 @@ typedef struct {
                               last scan, or after the ghost count changed
                               (Sec. 5.2); 0: tune only on request.  Equal in
                               all systems                                    */
+    int32_t integrator;    /* HOOMD_NVE or HOOMD_NVT (Sec. 6.1)              */
+    int32_t nvt_group;     /* NVT: 0 = a thermostat of its own; k > 0 = one
+                              thermostat shared by every system with group
+                              k, over their summed kinetic energy (the
+                              subdomains of one box; equal dt, nvt_T0 and
+                              nvt_tau required)                              */
+    double nvt_T0;         /* NVT: set temperature (> 0)                     */
+    double nvt_tau;        /* NVT: coupling time (> 0)                       */
 } hoomd_params;
+
+/* Integrators (Sec. 3: NVE by velocity Verlet; Sec. 6.1: the weak-scaling LJ
+ * runs use a Nose-Hoover thermostat that is not fully symplectic and takes
+ * one global kinetic-energy sum per step).  HOOMD_NVT follows the flow
+ *   dx/dt = v,  dv/dt = F - xi v,  dxi/dt = (T/T0 - 1) / tau^2,
+ * T = 2 KE / g with g = 3N - 3 (N the group's local particles), per step h:
+ *   v(t+h/2) = v(t) + h/2 (F(t) - xi(t) v(t));  x(t+h) = x(t) + h v(t+h/2);
+ *   xi(t+h) = xi(t) + h/tau^2 (T(t+h/2)/T0 - 1)   (the one KE sum);
+ *   v(t+h) = (v(t+h/2) + h/2 F(t+h)) / (1 + h/2 xi(t+h)),
+ * with eta(t+h) = eta(t) + h/2 (xi(t) + xi(t+h)).  The flow conserves
+ * KE + PE + g T0 (tau^2 xi^2 / 2 + eta). */
+enum { HOOMD_NVE = 0, HOOMD_NVT = 1 };
 
 /* Geometry of one system.  For a periodic box lo = 0 and L is the box.  For
  * a subdomain frame with ghosts the open axes have periodic = 0 and [lo, lo
@@ -202,10 +222,11 @@ enum { HOOMD_ENERGY = 1u, HOOMD_VIRIAL = 2u };
  * per-system thermo sums read by hoomd_thermo(). */
 int compute_forces(hoomd_ctx *ctx, uint64_t timestep, uint32_t flags);
 
-/* Advance every system n_steps velocity-Verlet (NVE, Sec. 3) steps with
- * rebuilds decided on the device (Sec. 4.2), the state before the call being
- * that of timestep first_timestep: per step v += dt/2 F; x += dt
- * v (folded); rebuild when needed; F <- F(x, v, t+1); v += dt/2 F.  With
+/* Advance every system n_steps velocity-Verlet (NVE, Sec. 3) or Nose-Hoover
+ * (NVT, Sec. 6.1, as stated at HOOMD_NVT) steps with rebuilds decided on the
+ * device (Sec. 4.2), the state before the call being that of timestep
+ * first_timestep: per NVE step v += dt/2 F; x += dt v (folded); rebuild when
+ * needed; F <- F(x, v, t+1); v += dt/2 F.  With
  * log_every > 0 the thermo sums are recorded every log_every steps (and at
  * the last step) in a device ring read by hoomd_thermo_log().  Morton sorts
  * happen every sort_period steps.  On return pos, vel, force and tag hold
@@ -262,6 +283,9 @@ int pack_ghosts_noalloc(const double *pos, const double *vel, const int32_t *tag
  *              reports;
  *   which = 1: forces at `timestep` (building the list first if needed, e.g.
  *              after ghosts were selected anew), then v += dt/2 F.
+ * NVT systems take the Nose-Hoover halves instead (HOOMD_NVT): the first
+ * half ends with the thermostat update over the kinetic energy of each
+ * group (Sec. 6.1: the one global sum of the step).
  * The caller updates the ghosts between the halves (pack / unpack UPDATE),
  * or, when a rebuild is due, migrates particles and selects ghosts anew.
  * Both halves cover the local rows of every system and only queue work. */
@@ -308,6 +332,14 @@ int unpack_ghosts(hoomd_ctx *ctx, int32_t sys, const void *recv, int64_t n_recv,
  * once per evaluation) of the last evaluation that asked for energies (compute_forces with flags, or a logged step), FP64, summed in a
  * fixed order.  out holds 4 * n_sys doubles.  Synchronises. */
 int hoomd_thermo(hoomd_ctx *ctx, double *out);
+
+/* Nose-Hoover state {xi, eta} of each system's thermostat (the shared one
+ * for a group; zeros for NVE systems), 2 * n_sys doubles in host memory
+ * (Sec. 6.1).  hoomd_set_thermostat() sets them (for a group, the values of
+ * its last system win).  Both synchronise.  hoomd_init() starts every
+ * thermostat at {0, 0}. */
+int hoomd_thermostat(hoomd_ctx *ctx, double *xi_eta);
+int hoomd_set_thermostat(hoomd_ctx *ctx, const double *xi_eta);
 
 /* Copy up to max_rows logged rows {timestep, KE, PE, W, T} per system
  * (row-major [row][sys][5]) of the last step() call.  Synchronises.  Returns

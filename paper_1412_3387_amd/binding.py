@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhoomd_mi355x.so")
 
 FP64, MIXED = 0, 1
 PAIR_LJ, PAIR_WCA, PAIR_DPD = 0, 1, 2
+NVE, NVT = 0, 1
 ENERGY, VIRIAL = 1, 2
 GHOST_SELECT, GHOST_UPDATE = 0, 1
 FIELD_POS, FIELD_VEL, FIELD_TAG = 1, 2, 4
@@ -43,7 +44,9 @@ class Params(C.Structure):
                 ("fene_K", C.c_double), ("fene_R0", C.c_double), ("nlist_cap", C.c_int32),
                 ("cell_cap", C.c_int32), ("halo_cap", C.c_int32), ("sort_period", C.c_int32), ("check_period", C.c_int32),
                 ("tpp_nlist", C.c_int32), ("tpp_force", C.c_int32), ("block_nlist", C.c_int32),
-                ("block_force", C.c_int32), ("use_graph", C.c_int32), ("tune_period", C.c_int32)]
+                ("block_force", C.c_int32), ("use_graph", C.c_int32), ("tune_period", C.c_int32),
+                ("integrator", C.c_int32), ("nvt_group", C.c_int32), ("nvt_T0", C.c_double),
+                ("nvt_tau", C.c_double)]
 
 
 class Box(C.Structure):
@@ -90,7 +93,8 @@ EXPORTS = ["hoomd_workspace_bytes", "hoomd_init", "hoomd_destroy", "build_nlist"
            "compute_forces", "step", "pack_ghosts", "unpack_ghosts", "hoomd_thermo",
            "hoomd_thermo_log", "hoomd_sync_status", "hoomd_build_count", "hoomd_get_layout",
            "hoomd_autotune", "hoomd_profile", "hoomd_strerror", "pack_ghosts_noalloc",
-           "integrate_half_step", "hoomd_rebuild_due", "migrate_particles", "receive_particles"]
+           "integrate_half_step", "hoomd_rebuild_due", "migrate_particles", "receive_particles",
+           "hoomd_thermostat", "hoomd_set_thermostat"]
 
 _lib = None
 
@@ -122,6 +126,8 @@ def lib():
         L.unpack_ghosts.argtypes = [P, C.c_int32, P, C.c_int64, C.c_uint32, C.c_int32,
                                     C.POINTER(C.c_double)]
         L.hoomd_thermo.argtypes = [P, C.POINTER(C.c_double)]
+        L.hoomd_thermostat.argtypes = [P, C.POINTER(C.c_double)]
+        L.hoomd_set_thermostat.argtypes = [P, C.POINTER(C.c_double)]
         L.hoomd_thermo_log.argtypes = [P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]
         L.hoomd_sync_status.argtypes = [P, C.POINTER(C.c_int64)]
         L.hoomd_build_count.argtypes = [P, C.POINTER(C.c_int64)]
@@ -169,6 +175,10 @@ class ModelParams:
     block_force: int = 0
     use_graph: int = 1
     tune_period: int = 0
+    integrator: int = 0
+    nvt_group: int = 0
+    nvt_T0: float = 1.0
+    nvt_tau: float = 1.0
 
     def list_radius(self) -> float:
         rc = 2.0 ** (1.0 / 6.0) * self.sigma if self.pair == PAIR_WCA else self.r_cut
@@ -357,6 +367,17 @@ class Context:
         bl = (C.c_double * 3)(*[float(x) for x in box_L])
         _check(lib().receive_particles(self.h, sys, _ptr(recv), n_recv, bl), "receive_particles")
         self._refresh_counts(sys)
+
+    def thermostat(self) -> np.ndarray:
+        """(n_sys, 2) Nose-Hoover {xi, eta} per system."""
+        out = (C.c_double * (2 * self.n_sys))()
+        _check(lib().hoomd_thermostat(self.h, out), "hoomd_thermostat")
+        return np.array(out[:]).reshape(self.n_sys, 2)
+
+    def set_thermostat(self, xi_eta):
+        v = np.ascontiguousarray(np.asarray(xi_eta, dtype=np.float64).reshape(self.n_sys, 2))
+        _check(lib().hoomd_set_thermostat(self.h, v.ctypes.data_as(C.POINTER(C.c_double))),
+               "hoomd_set_thermostat")
 
     def thermo(self) -> np.ndarray:
         out = (C.c_double * (4 * self.n_sys))()

@@ -53,10 +53,11 @@ struct SysDev {
     // DPD
     double dpd_A, dpd_gamma, dpd_sigma, dpd_inv_rc, dpd_inv_sqrt_dt, dpd_rc;
     uint32_t dpd_seed;
-    int32_t pad0;
+    int32_t nvt_slot;       // Nose-Hoover: first system of the thermostat group; -1 = NVE
     // FENE + WCA bonds
     double fene_K, fene_R02, wca_rc2;
     double dt, hdt;
+    double nvt_c, nvt_T0;   // Nose-Hoover: dt / tau^2 and the set temperature
 };
 
 // Workgroup b of a launch runs on accelerator die b % kDies, and each die has

@@ -112,6 +112,9 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
     const double rc2 = S.rc2;
     const T eps = (T)S.eps, sig2 = (T)S.sig2;
     const double shift = S.shift;
+    // Nose-Hoover friction of this system for the whole launch (NVE: none)
+    const bool nvt = a.thermostat != nullptr && S.nvt_slot >= 0;
+    const double xi_nh = nvt ? a.thermostat[2 * S.nvt_slot] : 0.0;
     const int r0 = (tile - S.tile0) * kTile;
     const int r = r0 + t;
     const bool active = r < n_local;
@@ -343,7 +346,7 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
         vir = segment_sum<W>(vir);
     }
 
-    double ke = 0.0;
+    double ke = 0.0, kh = 0.0;
     const bool owner = active && sl == 0;
     if (owner) {
         double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
@@ -390,12 +393,26 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
             v.x += hdt * Fx;
             v.y += hdt * Fy;
             v.z += hdt * Fz;
+            if (nvt) {
+                // the closing half of the Nose-Hoover step, implicit in v
+                const double d = 1.0 + hdt * xi_nh;
+                v.x = v.x / d;
+                v.y = v.y / d;
+                v.z = v.z / d;
+            }
         }
         if constexpr (LOG) ke = 0.5 * ((v.x * v.x + v.y * v.y) + v.z * v.z);
         if (a.mode == MODE_FIRST || a.mode == MODE_MID) {
-            v.x += hdt * Fx;
-            v.y += hdt * Fy;
-            v.z += hdt * Fz;
+            if (nvt) {
+                v.x += hdt * (Fx - xi_nh * v.x);
+                v.y += hdt * (Fy - xi_nh * v.y);
+                v.z += hdt * (Fz - xi_nh * v.z);
+                kh = 0.5 * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+            } else {
+                v.x += hdt * Fx;
+                v.y += hdt * Fy;
+                v.z += hdt * Fz;
+            }
             double4 x = xi;
             const double dt = S.dt;
             x.x += dt * v.x;
@@ -435,6 +452,13 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
         }
         e = ue;
         vir = uw;
+    }
+    if (a.khalf) {
+        // per-wave kinetic energy of the half-step velocities, summed per
+        // thermostat group after the launch
+        double k = owner ? kh : 0.0;
+        k = wave_sum(k);
+        if (lane == 0) a.khalf[gw] = k;
     }
     if constexpr (LOG) {
         double k3 = owner ? ke : 0.0;
@@ -579,6 +603,30 @@ __global__ void k_disp_check(const SysDev *__restrict__ sys, const int32_t *__re
     }
 }
 
+// x += dt v (folded on periodic axes), then the displacement check since the
+// last build (Sec. 4.2) sets the rebuild flags.
+__device__ __forceinline__ void drift_and_check(const SysDev &S, int s, int64_t i, const double4 &v,
+                                                double4 *__restrict__ pos, const double4 *__restrict__ xbuild,
+                                                int32_t *flag, int32_t *sflag)
+{
+    double4 x = pos[i];
+    x.x += S.dt * v.x;
+    x.y += S.dt * v.y;
+    x.z += S.dt * v.z;
+    if (S.per[0]) x.x = fold(x.x, S.lo[0], S.L[0]);
+    if (S.per[1]) x.y = fold(x.y, S.lo[1], S.L[1]);
+    if (S.per[2]) x.z = fold(x.z, S.lo[2], S.L[2]);
+    pos[i] = x;
+    const double4 xb = xbuild[i];
+    const double bx = min_image(x.x - xb.x, S.L[0], S.invL[0]);
+    const double by = min_image(x.y - xb.y, S.L[1], S.invL[1]);
+    const double bz = min_image(x.z - xb.z, S.L[2], S.invL[2]);
+    if ((bx * bx + by * by) + bz * bz > S.disp2) {
+        *flag = 1;
+        sflag[s] = 1;
+    }
+}
+
 // One half of a velocity-Verlet step over the local rows, from the force
 // array of the last force evaluation (unit mass).  which = 0: v += dt/2 F,
 // x += dt v (folded on periodic axes), and the displacement check since the
@@ -587,13 +635,56 @@ template <bool MIXED>
 __global__ void k_half_step(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys,
                             int tiles, double4 *__restrict__ pos, double4 *__restrict__ vel,
                             const void *__restrict__ force, int which, const double4 *__restrict__ xbuild,
-                            int32_t *flag, int32_t *sflag)
+                            int32_t *flag, int32_t *sflag, const double *__restrict__ thermostat,
+                            double *__restrict__ khalf)
 {
     const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (g >= tiles) return;
+    if (g >= tiles) return;  // whole waves
     const int s = find_sys(tprefix, n_sys, g);
     const SysDev &S = sys[s];
     const int r = (g - S.tile0) * kTile + lane_id();
+    const bool nvt = thermostat != nullptr && S.nvt_slot >= 0;
+    if (nvt) {
+        // Nose-Hoover halves; the first also leaves the tile's half-step
+        // kinetic energy for the thermostat update
+        const double xi_nh = thermostat[2 * S.nvt_slot];
+        double kh = 0.0;
+        if (r < S.n_local) {
+            const int64_t i = S.row0 + r;
+            double fx, fy, fz;
+            if (MIXED) {
+                const float4 f = reinterpret_cast<const float4 *>(force)[i];
+                fx = f.x;
+                fy = f.y;
+                fz = f.z;
+            } else {
+                const double4 f = reinterpret_cast<const double4 *>(force)[i];
+                fx = f.x;
+                fy = f.y;
+                fz = f.z;
+            }
+            double4 v = vel[i];
+            if (which != 0) {
+                const double d = 1.0 + S.hdt * xi_nh;
+                v.x = (v.x + S.hdt * fx) / d;
+                v.y = (v.y + S.hdt * fy) / d;
+                v.z = (v.z + S.hdt * fz) / d;
+                vel[i] = v;
+            } else {
+                v.x += S.hdt * (fx - xi_nh * v.x);
+                v.y += S.hdt * (fy - xi_nh * v.y);
+                v.z += S.hdt * (fz - xi_nh * v.z);
+                vel[i] = v;
+                kh = 0.5 * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+                drift_and_check(S, s, i, v, pos, xbuild, flag, sflag);
+            }
+        }
+        if (which == 0 && khalf) {
+            kh = wave_sum(kh);
+            if (lane_id() == 0) khalf[g] = kh;
+        }
+        return;
+    }
     if (r >= S.n_local) return;
     const int64_t i = S.row0 + r;
     double fx, fy, fz;
@@ -614,21 +705,44 @@ __global__ void k_half_step(const SysDev *__restrict__ sys, const int32_t *__res
     v.z += S.hdt * fz;
     vel[i] = v;
     if (which != 0) return;
-    double4 x = pos[i];
-    x.x += S.dt * v.x;
-    x.y += S.dt * v.y;
-    x.z += S.dt * v.z;
-    if (S.per[0]) x.x = fold(x.x, S.lo[0], S.L[0]);
-    if (S.per[1]) x.y = fold(x.y, S.lo[1], S.L[1]);
-    if (S.per[2]) x.z = fold(x.z, S.lo[2], S.L[2]);
-    pos[i] = x;
-    const double4 xb = xbuild[i];
-    const double bx = min_image(x.x - xb.x, S.L[0], S.invL[0]);
-    const double by = min_image(x.y - xb.y, S.L[1], S.invL[1]);
-    const double bz = min_image(x.z - xb.z, S.L[2], S.invL[2]);
-    if ((bx * bx + by * by) + bz * bz > S.disp2) {
-        *flag = 1;
-        sflag[s] = 1;
+    drift_and_check(S, s, i, v, pos, xbuild, flag, sflag);
+}
+
+// Nose-Hoover update, one workgroup per system; the first system of each
+// group sums the half-step kinetic-energy partials of the group's systems
+// (w per tile, tiles in order, a fixed order), then
+//   xi' = xi + dt/tau^2 (T/T0 - 1),  eta' = eta + dt/2 (xi + xi'),
+// with T = 2 KE / (3 N - 3) over the group's N local particles.
+__global__ __launch_bounds__(256) void k_nvt_update(const SysDev *__restrict__ sys,
+                                                    const int32_t *__restrict__ tprefix, int n_sys, int w,
+                                                    const double *__restrict__ khalf,
+                                                    double *__restrict__ thermostat)
+{
+    __shared__ double red[256];
+    const int s = blockIdx.x;
+    const SysDev &S = sys[s];
+    if (S.nvt_slot != s) return;
+    double k = 0.0;
+    int64_t n = 0;
+    for (int q = s; q < n_sys; ++q) {
+        if (sys[q].nvt_slot != s) continue;
+        n += sys[q].n_local;
+        const int64_t w0 = (int64_t)tprefix[q] * w, w1 = (int64_t)tprefix[q + 1] * w;
+        for (int64_t p = w0 + threadIdx.x; p < w1; p += blockDim.x) k += khalf[p];
+    }
+    red[threadIdx.x] = k;
+    __syncthreads();
+    for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double g = 3.0 * (double)n - 3.0;
+        const double T = g > 0 ? 2.0 * red[0] / g : S.nvt_T0;
+        const double xi = thermostat[2 * s];
+        const double xn = xi + S.nvt_c * (T / S.nvt_T0 - 1.0);
+        thermostat[2 * s + 1] = thermostat[2 * s + 1] + S.hdt * (xi + xn);
+        thermostat[2 * s] = xn;
     }
 }
 
@@ -782,12 +896,21 @@ void launch_half_step(const LaunchCtx &L, double4 *pos, double4 *vel, const void
     const int threads = 256;
     const int blocks = (L.tiles_local * kWave + threads - 1) / threads;
     if (blocks == 0) return;
+    const double *th = L.nvt ? L.thermostat : nullptr;
+    double *kh = L.nvt ? L.khalf : nullptr;
     if (mixed)
         hipLaunchKernelGGL(k_half_step<true>, dim3(blocks), dim3(threads), 0, L.stream, L.sys, L.tprefix_local,
-                           L.n_sys, L.tiles_local, pos, vel, force, which, L.xbuild, flag, sflag);
+                           L.n_sys, L.tiles_local, pos, vel, force, which, L.xbuild, flag, sflag, th, kh);
     else
         hipLaunchKernelGGL(k_half_step<false>, dim3(blocks), dim3(threads), 0, L.stream, L.sys, L.tprefix_local,
-                           L.n_sys, L.tiles_local, pos, vel, force, which, L.xbuild, flag, sflag);
+                           L.n_sys, L.tiles_local, pos, vel, force, which, L.xbuild, flag, sflag, th, kh);
+}
+
+void launch_nvt_update(const LaunchCtx &L, int w)
+{
+    if (!L.nvt) return;
+    hipLaunchKernelGGL(k_nvt_update, dim3(L.n_sys), dim3(256), 0, L.stream, L.sys, L.tprefix_local, L.n_sys, w,
+                       L.khalf, L.thermostat);
 }
 
 void launch_rtag(const LaunchCtx &L, const int32_t *tag)

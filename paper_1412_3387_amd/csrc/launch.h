@@ -57,6 +57,9 @@ struct LaunchCtx {
     Status *status;
     double *partials;              // 3 doubles per wave
     double *thermo;                // 4 doubles per system
+    double *khalf;                 // Nose-Hoover: kinetic energy of the half-step velocities, one per wave
+    double *thermostat;            // Nose-Hoover: {xi, eta} per system (used at each group's first system)
+    bool nvt;                      // some system integrates NVT
     double *thermo_log;            // rows of 5 doubles per system
 };
 
@@ -80,6 +83,8 @@ struct ForceLaunch {
     int32_t pair;     // one Pair for every system of the launch, or -1 = mixed batch
     const int32_t *since;   // per system, steps since its last build before this step, or nullptr
     int32_t check_period;   // displacement check every this many steps since the build (>= 1)
+    const double *thermostat;  // Nose-Hoover state per system (nullptr: every system NVE)
+    double *khalf;             // where the launch writes the half-step kinetic-energy partials
 };
 
 void launch_bin(const LaunchCtx &L, const double4 *pos);
@@ -97,6 +102,9 @@ void launch_rtag(const LaunchCtx &L, const int32_t *tag);
 // displacement check into flag / sflag; 1: kick) from the force array.
 void launch_half_step(const LaunchCtx &L, double4 *pos, double4 *vel, const void *force, bool mixed, int which,
                       int32_t *flag, int32_t *sflag);
+// Nose-Hoover: per thermostat group, sum the half-step kinetic-energy
+// partials (w per tile) of its systems, then advance xi and eta.
+void launch_nvt_update(const LaunchCtx &L, int w);
 void launch_disp_check(const LaunchCtx &L, const double4 *pos, int32_t *flag, int32_t *sflag);
 size_t force_lds_bytes(int pair, int halo_cap, int nlist_cap);
 int force_row_over_read();

@@ -34,7 +34,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
     // byte offsets into the workspace
-    size_t sysdev, tpl, tpa, cpre, status, flags, sysflags, thermo, thermo_log, partials;
+    size_t sysdev, tpl, tpa, cpre, status, flags, sysflags, thermo, thermo_log, partials, khalf, thermostat;
     size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, cell_xf, halo, halo_n;
     size_t rtag, partners, slow_list, rare_list, plan, sort_ws, ghost_ws, total;
     // sizes
@@ -80,6 +80,17 @@ bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         if (q.check_period < 0 || q.check_period != p[0].check_period) return false;
         if (q.tune_period < 0 || q.tune_period != p[0].tune_period) return false;
         if (q.tpp_force != p[0].tpp_force || q.block_force != p[0].block_force) return false;
+        if (q.integrator != HOOMD_NVE && q.integrator != HOOMD_NVT) return false;
+        if (q.integrator == HOOMD_NVT) {
+            if (!(q.nvt_T0 > 0) || !std::isfinite(q.nvt_T0) || !(q.nvt_tau > 0) || !std::isfinite(q.nvt_tau))
+                return false;
+            if (q.nvt_group < 0) return false;
+            // one thermostat per group: its systems share the step and the coupling
+            for (int u = 0; u < s; ++u)
+                if (q.nvt_group > 0 && p[u].integrator == HOOMD_NVT && p[u].nvt_group == q.nvt_group &&
+                    (p[u].dt != q.dt || p[u].nvt_T0 != q.nvt_T0 || p[u].nvt_tau != q.nvt_tau))
+                    return false;
+        }
         // launch shapes: the framed build takes 64 or 32 lanes per row and 512
         // or 256 threads per workgroup (one shape for all systems); the force
         // pass runs 64 rows x tpp_force lanes per workgroup
@@ -205,6 +216,19 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         S.wca_rc2 = std::pow(2.0, 1.0 / 3.0) * S.sig2;
         S.dt = q.dt;
         S.hdt = 0.5 * q.dt;
+        // Nose-Hoover: the group's first system holds the thermostat
+        S.nvt_slot = -1;
+        if (q.integrator == HOOMD_NVT) {
+            S.nvt_slot = s;
+            if (q.nvt_group > 0)
+                for (int u = 0; u < s; ++u)
+                    if (p[u].integrator == HOOMD_NVT && p[u].nvt_group == q.nvt_group) {
+                        S.nvt_slot = u;
+                        break;
+                    }
+            S.nvt_c = q.dt / (q.nvt_tau * q.nvt_tau);
+            S.nvt_T0 = q.nvt_T0;
+        }
         const int64_t ncell = (int64_t)S.bins[0] * S.bins[1] * S.bins[2];
         // capacity of a cell: twice the mean occupancy plus a margin
         if (q.cell_cap > 0) {
@@ -251,6 +275,8 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.thermo = take(sizeof(double) * 4 * n_sys);
     Lo.thermo_log = take(sizeof(double) * 5 * (size_t)n_sys * kLogRows);
     Lo.partials = take(sizeof(double) * 3 * (size_t)std::max<int64_t>(tile, 1) * 64);
+    Lo.khalf = take(sizeof(double) * (size_t)std::max<int64_t>(tile, 1) * 16);
+    Lo.thermostat = take(sizeof(double) * 2 * (size_t)n_sys);
     Lo.pos_alt = take(sizeof(double4) * rows);
     Lo.vel_alt = take(sizeof(double4) * rows);
     Lo.xbuild = take(sizeof(double4) * rows);
@@ -400,6 +426,8 @@ ForceLaunch base_force(hoomd_ctx *c)
     F.pair = c->pair_uniform;
     F.since = sflag_ptr(c, 3);
     F.check_period = c->check_period;
+    F.thermostat = c->L.nvt ? c->L.thermostat : nullptr;
+    F.khalf = nullptr;
     return F;
 }
 
@@ -421,7 +449,9 @@ void queue_mid_step(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V, b
     F.flag_clear = flag_ptr(c, p ^ 1);
     F.sflag_set = sflag_ptr(c, p);
     F.sflag_clear = sflag_ptr(c, p ^ 1);
+    if (c->L.nvt) F.khalf = c->L.khalf;
     launch_force(c->L, F, c->tpp_force, c->block_force);
+    launch_nvt_update(c->L, c->tpp_force);
     queue_rebuild(c, P[p ^ 1], c->arr.tag, p, 1);
 }
 
@@ -556,6 +586,10 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.partials = ws_ptr<double>(c, lay.partials);
     L.thermo = ws_ptr<double>(c, lay.thermo);
     L.thermo_log = ws_ptr<double>(c, lay.thermo_log);
+    L.khalf = ws_ptr<double>(c, lay.khalf);
+    L.thermostat = ws_ptr<double>(c, lay.thermostat);
+    L.nvt = false;
+    for (int s = 0; s < n_sys; ++s) L.nvt = L.nvt || params[s].integrator == HOOMD_NVT;
     c->sortb = make_sort_buffers(c->ws + lay.sort_ws, lay.rows);
     c->ghostb = make_ghost_buffers(c->ws + lay.ghost_ws, lay.rows, n_sys);
     default_tuning(c);
@@ -576,6 +610,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     if (e == hipSuccess) e = hipMemset(c->ws + lay.sysflags, 0, sizeof(int32_t) * 4 * (size_t)n_sys);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.cell_count, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(lay.n_cells, 1));
     if (e == hipSuccess) e = hipMemset(c->ws + lay.thermo, 0, sizeof(double) * 4 * n_sys);
+    if (e == hipSuccess) e = hipMemset(c->ws + lay.thermostat, 0, sizeof(double) * 2 * n_sys);
     // bond partner rows by tag (built on the host from the caller's table)
     if (e == hipSuccess && lay.bond_cap > 0) {
         std::vector<int32_t> rows((size_t)lay.rows * lay.bond_cap, -1);
@@ -760,9 +795,11 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
         F.log = logs_at(s);
         F.energy = F.mode == MODE_LAST ? 1 : 0;
         if (F.mode == MODE_LAST) F.log = F.log || log_every > 0;
+        if (c->L.nvt && F.mode != MODE_LAST) F.khalf = c->L.khalf;
         const size_t e0 = mark(c);
         launch_force(c->L, F, c->tpp_force, c->block_force);
         if (c->profiling) c->ev_force.emplace_back(e0, mark(c));
+        if (F.khalf) launch_nvt_update(c->L, c->tpp_force);
         if (F.log) {
             launch_thermo_reduce(c->L, c->tpp_force, log_row < kLogRows ? log_row : -1, (double)t);
             ++log_row;
@@ -869,6 +906,7 @@ int integrate_half_step(hoomd_ctx *c, int32_t which, uint64_t timestep)
     }
     launch_half_step(c->L, reinterpret_cast<double4 *>(c->arr.pos), reinterpret_cast<double4 *>(c->arr.vel),
                      c->arr.force, c->mixed != 0, which, flag, sflag);
+    if (which == 0) launch_nvt_update(c->L, 1);  // one wave per tile in the half-step launch
     return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
 }
 
@@ -1011,6 +1049,37 @@ int hoomd_thermo(hoomd_ctx *c, double *out)
 {
     if (!c || !out) return HOOMD_E_ARG;
     HIP_OK(hipMemcpyAsync(out, c->ws + c->lay.thermo, sizeof(double) * 4 * c->n_sys, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return HOOMD_OK;
+}
+
+int hoomd_thermostat(hoomd_ctx *c, double *xi_eta)
+{
+    if (!c || !xi_eta) return HOOMD_E_ARG;
+    std::vector<double> dev(2 * (size_t)c->n_sys);
+    HIP_OK(hipMemcpyAsync(dev.data(), c->ws + c->lay.thermostat, sizeof(double) * dev.size(), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    for (int s = 0; s < c->n_sys; ++s) {
+        const int slot = c->lay.sys[s].nvt_slot;
+        xi_eta[2 * s] = slot >= 0 ? dev[2 * (size_t)slot] : 0.0;
+        xi_eta[2 * s + 1] = slot >= 0 ? dev[2 * (size_t)slot + 1] : 0.0;
+    }
+    return HOOMD_OK;
+}
+
+int hoomd_set_thermostat(hoomd_ctx *c, const double *xi_eta)
+{
+    if (!c || !xi_eta) return HOOMD_E_ARG;
+    std::vector<double> dev(2 * (size_t)c->n_sys, 0.0);
+    for (int s = 0; s < c->n_sys; ++s) {
+        const int slot = c->lay.sys[s].nvt_slot;
+        if (slot < 0) continue;
+        dev[2 * (size_t)slot] = xi_eta[2 * s];
+        dev[2 * (size_t)slot + 1] = xi_eta[2 * s + 1];
+    }
+    HIP_OK(hipMemcpyAsync(c->ws + c->lay.thermostat, dev.data(), sizeof(double) * dev.size(), hipMemcpyHostToDevice,
+                          c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     return HOOMD_OK;
 }

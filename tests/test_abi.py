@@ -132,3 +132,45 @@ def test_layout_struct_matches_header(hlib):
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"\b(\w+)(?:\[\d+\])?;", body)
     assert names == [f[0] for f in B.Layout._fields_]
+
+
+def test_params_struct_matches_header():
+    """hoomd_params as the binding declares it has the header's fields, in
+    order (names parsed from the header)."""
+    import re
+    from paper_1412_3387_amd import binding as B
+    txt = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} hoomd_params;", txt, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in re.findall(r"([^;]+);", body):
+        _type, rest = decl.split(None, 1)  # "double eps, sigma" -> eps, sigma
+        names += [n.strip() for n in rest.split(",")]
+    assert names == [f[0] for f in B.Params._fields_]
+
+
+def test_integrator_fields_are_validated(hlib):
+    """NVT needs a positive finite set temperature and coupling time and a
+    group id >= 0; systems of one thermostat group must share dt, T0 and
+    tau; systems with their own thermostats (group 0) need not."""
+    from paper_1412_3387_amd import binding as B
+
+    def ws(*kws):
+        ps = (B.Params * len(kws))(*[B.ModelParams(**kw).to_c(0.8442) for kw in kws])
+        boxes = (B.Box * len(kws))()
+        for b in boxes:
+            for a in range(3):
+                b.L[a] = 16.796
+                b.periodic[a] = 1
+            b.n_local = b.n_cap = 4000
+        return hlib.hoomd_workspace_bytes(ps, len(kws), boxes)
+
+    nvt = dict(integrator=B.NVT, nvt_T0=1.2, nvt_tau=0.5)
+    assert ws(nvt) > 0 and ws(dict(integrator=2)) == 0
+    assert ws(dict(nvt, nvt_T0=0.0)) == 0 and ws(dict(nvt, nvt_tau=-1.0)) == 0
+    assert ws(dict(nvt, nvt_tau=float("inf"))) == 0 and ws(dict(nvt, nvt_group=-1)) == 0
+    assert ws(dict(nvt, nvt_group=1), dict(nvt, nvt_group=1)) > 0
+    assert ws(dict(nvt, nvt_group=1), dict(nvt, nvt_group=1, nvt_T0=1.0)) == 0
+    assert ws(dict(nvt, nvt_group=1), dict(nvt, nvt_group=1, dt=0.004)) == 0
+    assert ws(dict(nvt), dict(nvt, nvt_T0=1.0, dt=0.004)) > 0
+    assert ws(dict(nvt, nvt_group=1), dict(nvt, nvt_group=2, nvt_T0=1.0)) > 0

@@ -1,0 +1,190 @@
+"""GPU parity of the Nose-Hoover NVT integrator (the thermostat of the
+weak-scaling LJ runs, Sec. 6.1) against the oracle: trajectories and the
+thermostat state {xi, eta} in FP64 and mixed precision, the fused step
+(every lane count of the force pass, eager and graph-replayed) and the two
+half steps around a ghost exchange, one thermostat shared by the 27
+subdomains of a box, per-system thermostats in a batch, zero coupling
+against NVE, and the extended energy over a longer mixed run."""
+import numpy as np
+import pytest
+
+from paper_1412_3387_amd import inputs
+from tests.gpu_helpers import LJ, by_tag, min_image_diff
+
+pytestmark = pytest.mark.gpu
+T0, TAU = 1.5, 0.5
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1412_3387_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ref50(orc):
+    s = inputs.lj_small()
+    x, v, F, th, ext, st = orc.run_nvt("lj", s.pos, s.vel, s.L, LJ, 0.005, 50, T0=T0, tau=TAU)
+    assert st == 0
+    return s, x, v, th, ext
+
+
+def _nvt(B, prec, **kw):
+    return B.ModelParams(precision=prec, integrator=B.NVT, nvt_T0=T0, nvt_tau=TAU, **kw)
+
+
+@pytest.mark.parametrize("w,graph", [(1, 1), (4, 1), (16, 1), (4, 0)])
+def test_nvt_lj_small_fp64(B, ref50, w, graph):
+    s, xo, vo, tho, exto = ref50
+    ctx = B.Context([_nvt(B, B.FP64, tpp_force=w, use_graph=graph)], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+    ctx.step(0, 50, log_every=10)
+    ctx.check()
+    x, v, f, tag = ctx.host_state()
+    x, v = by_tag(tag, x, v)
+    assert np.max(np.abs(min_image_diff(x, xo, s.L))) <= 1e-10
+    assert np.max(np.abs(v - vo)) <= 1e-10
+    xe = ctx.thermostat()[0]
+    assert abs(xe[0] - exto[-1, 0]) <= 1e-10 and abs(xe[1] - exto[-1, 1]) <= 1e-10
+    assert abs(exto[-1, 0]) > 0.05  # the thermostat acted
+    for row in ctx.thermo_log()[:, 0, :]:
+        t = int(row[0])
+        assert np.allclose(row[1:], tho[t], rtol=1e-10, atol=1e-9), (t, row, tho[t])
+    assert ctx.build_count() >= 2
+
+
+def test_nvt_lj_small_mixed(B, ref50):
+    s, xo, vo, tho, exto = ref50
+    ctx = B.Context([_nvt(B, B.MIXED)], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+    ctx.step(0, 50)
+    ctx.check()
+    x, v, f, tag = ctx.host_state()
+    x, v = by_tag(tag, x, v)
+    vs = np.sqrt(np.mean(vo ** 2))
+    assert np.max(np.abs(min_image_diff(x, xo, s.L))) <= 1e-5
+    assert np.max(np.abs(v - vo)) <= 1e-5 * vs
+    xe = ctx.thermostat()[0]
+    assert abs(xe[0] - exto[-1, 0]) <= 1e-5 * abs(exto[-1, 0])
+
+
+def test_nvt_starts_from_a_set_thermostat(orc, B):
+    """xi(0) = 0.4, eta(0) = -0.1 set through the C ABI: the friction acts
+    from the first half step on."""
+    s = inputs.lj_fluid(2000, 21, 22)
+    xo, vo, F, th, ext, st = orc.run_nvt("lj", s.pos, s.vel, s.L, LJ, 0.005, 20, T0=T0, tau=TAU,
+                                         xi=0.4, eta=-0.1)
+    assert st == 0
+    ctx = B.Context([_nvt(B, B.FP64)], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+    ctx.set_thermostat([[0.4, -0.1]])
+    assert np.array_equal(ctx.thermostat(), [[0.4, -0.1]])
+    ctx.step(0, 20)
+    ctx.check()
+    x, v, f, tag = ctx.host_state()
+    x, v = by_tag(tag, x, v)
+    assert np.max(np.abs(min_image_diff(x, xo, s.L))) <= 1e-10
+    assert np.max(np.abs(v - vo)) <= 1e-10
+    assert np.max(np.abs(ctx.thermostat()[0] - ext[-1])) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nvt_without_coupling_equals_nve(B, prec):
+    """xi = 0 and tau = 1e200 (dt / tau^2 = 0): the NVT step is the NVE
+    step bit for bit, and xi stays zero."""
+    s = inputs.lj_fluid(3000, 23, 24)
+    out = []
+    for integ in (B.NVE, B.NVT):
+        p = B.ModelParams(precision=prec, integrator=integ, nvt_T0=1.0, nvt_tau=1e200)
+        ctx = B.Context([p], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+        ctx.step(0, 30)
+        ctx.check()
+        out.append(ctx.host_state())
+        if integ == B.NVT:
+            assert np.all(ctx.thermostat() == 0)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nvt_batch_each_system_its_own_thermostat(B, prec):
+    """Three systems in one context (NVE, NVT at T0 = 1.5, NVT at T0 = 0.8):
+    each evolves bit for bit as it does alone."""
+    systems = [inputs.lj_fluid(900, 31, 32), inputs.lj_fluid(1500, 33, 34), inputs.lj_fluid(2500, 35, 36)]
+    ps = [B.ModelParams(precision=prec),
+          B.ModelParams(precision=prec, integrator=B.NVT, nvt_T0=1.5, nvt_tau=0.4),
+          B.ModelParams(precision=prec, integrator=B.NVT, nvt_T0=0.8, nvt_tau=0.3)]
+    dicts = [dict(pos=s.pos, vel=s.vel, L=s.L) for s in systems]
+    batch = B.Context(ps, dicts)
+    batch.step(0, 40)
+    batch.check()
+    th = batch.thermostat()
+    assert np.all(th[0] == 0) and th[1, 0] != 0 and th[2, 0] != 0
+    for k in range(3):
+        one = B.Context([ps[k]], [dicts[k]])
+        one.step(0, 40)
+        one.check()
+        a, b = batch.host_state(k), one.host_state(0)
+        for u, w in zip(a, b):
+            assert np.array_equal(u, w), k
+        assert np.array_equal(th[k], one.thermostat()[0])
+
+
+def test_nvt_subdomains_share_one_thermostat(orc, B):
+    """The 27 subdomains of a periodic box in one context, one thermostat
+    group: the half steps around the ghost exchange and the migrations give
+    the oracle's full-box NVT trajectory and thermostat state."""
+    from tests.test_gpu_migration import Loopback, _shifted_lj_box
+    sd = _shifted_lj_box()
+    p = _nvt(B, B.FP64, nlist_cap=160, nvt_group=1)
+    lb = Loopback(B, sd, p, 2.9, 0.6, B.FIELD_POS | B.FIELD_TAG)
+    lb.select_ghosts()
+    lb.ctx.compute_forces(0, 0)
+    for k in range(40):
+        lb.step(k)
+    lb.ctx.check()
+    assert lb.migrations >= 2 and lb.moved > 0
+    x, v, owner = lb.state()
+    full = sd.full
+    xo, vo, Fo, th, ext, st = orc.run_nvt("lj", full.pos, full.vel, full.L, LJ, 0.005, 40, T0=T0, tau=TAU)
+    assert st == 0
+    assert np.max(np.abs(min_image_diff(x, xo, full.L))) <= 1e-10
+    assert np.max(np.abs(v - vo)) <= 1e-10
+    xe = lb.ctx.thermostat()
+    assert np.all(xe == xe[0])  # every subdomain reports the group's state
+    assert np.max(np.abs(xe[0] - ext[-1])) <= 1e-10 and abs(ext[-1, 0]) > 0.02
+
+
+def test_nvt_extended_energy_and_temperature_mixed(B):
+    """4,000-particle liquid (the lattice melted by 1,000 NVE steps first,
+    to T ~ 0.65), then 2,000 mixed-precision NVT steps at T0 = 1.1 x that
+    temperature, in chunks of 100: the extended energy KE + PE + g T0
+    (tau^2 xi^2 / 2 + eta) stays within 3e-4 of its start (the oracle's
+    run of this scheme on 500 particles: 1.3e-4, and 4.8e-5 for NVE; both
+    fall as dt^2) while KE + PE changes by far more, and the mean
+    temperature of the second half is within 3 % of T0."""
+    s = inputs.lj_small()
+    ctx = B.Context([B.ModelParams(precision=B.MIXED)], [dict(pos=s.pos, vel=s.vel, L=s.L)])
+    ctx.step(0, 1000, log_every=100)
+    T_melt = float(np.mean(ctx.thermo_log()[5:, 0, 4]))
+    x, v, f, tag = ctx.host_state()
+    T0 = 1.1 * T_melt
+    p = B.ModelParams(precision=B.MIXED, integrator=B.NVT, nvt_T0=T0, nvt_tau=TAU)
+    ctx = B.Context([p], [dict(pos=x, vel=v, L=s.L, tag=tag)])
+    g = 3.0 * s.n - 3.0
+    H, E, T = [], [], []
+    t = 1000
+    ctx.compute_forces(t, B.ENERGY)
+    for chunk in range(21):
+        if chunk:
+            ctx.step(t, 100, log_every=10)
+            t += 100
+            T.extend(ctx.thermo_log()[1:, 0, 4])
+        th = ctx.thermo()[0]
+        xe = ctx.thermostat()[0]
+        E.append(th[0] + th[1])
+        H.append(E[-1] + g * T0 * (0.5 * TAU * TAU * xe[0] ** 2 + xe[1]))
+    ctx.check()
+    H, E = np.array(H), np.array(E)
+    assert 0.5 < T_melt < 0.8
+    assert np.max(np.abs(H - H[0])) <= 3e-4 * abs(H[0])
+    assert np.max(np.abs(E - E[0])) > 50 * np.max(np.abs(H - H[0]))
+    assert len(T) == 200 and abs(np.mean(T[100:]) - T0) <= 0.03 * T0
