@@ -301,9 +301,10 @@ def subdomain_phases(B, inputs, torch, reps=200):
 
 def other_workloads(B, inputs, torch, steps, warmup):
     """DPD fluid (N = 1,000,000, density 3, r_cut 1, A 25, gamma 4.5, kT 1,
-    dt 0.02) and the batched ensemble (128 LJ liquids of 500..20,000
-    particles and 128 bead-spring melts of 20..400 chains of 50, FENE + WCA),
-    each in one context."""
+    dt 0.02), the batched ensemble (128 LJ liquids of 500..20,000 particles
+    and 128 bead-spring melts of 20..400 chains of 50, FENE + WCA), each in
+    one context, the 32,000-particle NVT share of the weak-scaling fluid,
+    and the per-phase times of the strong-scaling subdomain."""
     res = {}
     try:
         # DPD particles diffuse fast (dt = 0.02): a Morton sort every 100
@@ -330,6 +331,16 @@ def other_workloads(B, inputs, torch, steps, warmup):
                                                        res["batch_256"]["per_system_launches"]["value"])
     except Exception as e:
         res["batch_256"] = {"error": repr(e)}
+    try:
+        # one GPU's share of the weak-scaling runs: NVT (Nose-Hoover), packing
+        # fraction 0.2, r_cut 3.0, dt 0.002
+        w = inputs.lj_weak_share()
+        p = B.ModelParams(precision=B.MIXED, r_cut=3.0, r_buff=0.4, dt=0.002, sort_period=500,
+                          integrator=B.NVT, nvt_T0=1.2, nvt_tau=0.5)
+        res["lj_nvt_32k"] = other_workload(B, torch, "lj_nvt_32k", [p], [dict(pos=w.pos, vel=w.vel, L=w.L)],
+                                           steps, warmup)
+    except Exception as e:
+        res["lj_nvt_32k"] = {"error": repr(e)}
     try:
         res["subdomain_32k"] = subdomain_phases(B, inputs, torch)
     except Exception as e:

@@ -166,6 +166,12 @@ def lj_bulk(n: int = 2_000_000) -> System:
     return lj_fluid(n, seed_pos=21, seed_vel=22, seed_vac=23)
 
 
+def lj_weak_share(n: int = 32_000) -> System:
+    """One GPU's share of the weak-scaling LJ fluid: packing fraction 0.2
+    (number density 6 x 0.2 / pi), T = 1.2."""
+    return lj_fluid(n, 61, 62, density=6.0 * 0.2 / math.pi)
+
+
 def dpd_bulk(n: int = 1_000_000) -> System:
     """DPD fluid, N = 1,000,000 at number density 3, kT = 1."""
     return dpd_fluid(n, seed_pos=31, seed_vel=32)
