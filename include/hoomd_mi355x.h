@@ -71,9 +71,13 @@ typedef enum {
     HOOMD_E_NAN = 9,             /* a non-finite force or position          */
     HOOMD_E_DANGEROUS_BUILD = 10,/* rebuild found a particle beyond r_buff/2
                                     when the check period is > 1            */
-    HOOMD_E_HALO_OVERFLOW = 11   /* a 64-row tile needs more halo entries
+    HOOMD_E_HALO_OVERFLOW = 11,  /* a 64-row tile needs more halo entries
                                     than halo_cap (or its cell box is too
                                     large); Morton-sorted rows avoid it      */
+    HOOMD_E_BOND_GHOST = 12      /* a bond partner is neither a local particle
+                                    nor a ghost, a bond would span more than
+                                    neighbouring subdomains, or the bond rank
+                                    table was not set up (Sec. 4.3.4)       */
 } hoomd_status;
 
 /* Arithmetic of the pair and bond terms.  Positions, velocities, the
@@ -305,13 +309,18 @@ int hoomd_rebuild_due(hoomd_ctx *ctx, int32_t *due);
  * front of the system's rows.  The ghosts of the system are dropped (select
  * them again after the arrivals).  *n_sent receives the number that left;
  * more than send_cap returns HOOMD_E_GHOST_OVERFLOW (records past send_cap
- * are not written).  Bonded systems: HOOMD_E_STATE.  Synchronises (the
- * counts set the new local count). */
+ * are not written).  Synchronises (the counts set the new local count).
+ * In a context with bonds (bond_stride = the largest bond_cap, > 0) every
+ * record is followed by the particle's bond_stride partner tags (-1 none)
+ * and the directions of their owners seen from the receiver, int32 each
+ * (Sec. 4.3.4: bonds migrate with their particles): 56 + 8 bond_stride
+ * bytes per record.  With bonds, call pack_bond_ranks(HOOMD_BOND_MIGRATE)
+ * and unpack_bond_ranks() in every subdomain first. */
 int migrate_particles(hoomd_ctx *ctx, int32_t sys, const hoomd_subdomain *subdomain, void *send,
                       int64_t send_cap, int32_t *counts26, int32_t *offsets26, int64_t *n_sent);
 
 /* Append n_recv migrated particles (records as migrate_particles() writes
- * them: position, velocity, tag) after the locals of system `sys`; each
+ * them: position, velocity, tag, partner entries) after the locals of system `sys`; each
  * position is moved to its periodic image nearest the centre of the
  * system's frame (box_L = the full periodic box).  Requires the system to
  * hold no ghosts; exceeding n_cap returns HOOMD_E_GHOST_OVERFLOW. */
@@ -327,6 +336,37 @@ int receive_particles(hoomd_ctx *ctx, int32_t sys, const void *recv, int64_t n_r
  * HOOMD_E_GHOST_OVERFLOW. */
 int unpack_ghosts(hoomd_ctx *ctx, int32_t sys, const void *recv, int64_t n_recv,
                   uint32_t fields, int32_t mode, const double *box_L);
+
+/* Bonded groups across subdomains (Sec. 4.3.4, Fig. 3).  A bond is kept
+ * with each member: every row carries its partners' tags and, for each, the
+ * direction of the subdomain that owns the partner (direction codes
+ * (dz+1) 9 + (dy+1) 3 + (dx+1), 13 = this subdomain; the 26 others are sent
+ * in code order, the ghost direction index).  hoomd_init() takes, per
+ * system, every bond with a local member (tags as in `tag`; a closed
+ * periodic box must hold both members) and marks partners it does not hold
+ * as of unknown owner.  pack_ghosts(SELECT) sends each particle, beside the
+ * layer rule, to every neighbour that owns one of its partners, and
+ * unpack_ghosts(SELECT) finds every partner among the locals and ghosts (a
+ * missing one latches HOOMD_E_BOND_GHOST at the next force evaluation), so
+ * bonds need no wider ghost layer than the pair cut-off.  The owner table
+ * is kept by 16-byte messages {int32 tag of the receiver's particle, int32
+ * tag of its partner, int32 owner direction of that partner seen from the
+ * receiver, 0}, laid out per direction like pack_ghosts() (counts26 /
+ * offsets26, *n_sent; more than send_cap returns HOOMD_E_GHOST_OVERFLOW):
+ *   HOOMD_BOND_START: before the first ghost selection, every particle
+ *     with a partner of unknown owner announces itself to all 26
+ *     neighbours; the neighbour that owns the partner records where it is;
+ *   HOOMD_BOND_MIGRATE: at a rebuild, before migrate_particles(), every
+ *     particle outside [lo, hi) tells the owner of each remote partner where
+ *     it goes (entries of local partners are updated in place).
+ * Call pack_bond_ranks() in every subdomain, move the messages, then
+ * unpack_bond_ranks() in every subdomain, before any particle moves.
+ * pack_bond_ranks() synchronises; both return HOOMD_E_STATE for a system
+ * without bonds or after its rows changed without a ghost selection. */
+enum { HOOMD_BOND_START = 0, HOOMD_BOND_MIGRATE = 1 };
+int pack_bond_ranks(hoomd_ctx *ctx, int32_t sys, const hoomd_subdomain *subdomain, int32_t mode, void *send,
+                    int64_t send_cap, int32_t *counts26, int32_t *offsets26, int64_t *n_sent);
+int unpack_bond_ranks(hoomd_ctx *ctx, int32_t sys, const void *recv, int64_t n_recv, int32_t mode);
 
 /* Per-system thermo {KE, PE, W, T} (Sec. 4.3.3: energies and virial summed
  * once per evaluation) of the last evaluation that asked for energies (compute_forces with flags, or a logged step), FP64, summed in a
@@ -393,7 +433,7 @@ typedef struct {
     const int32_t *general_tiles;
     const int32_t *rare_tiles;
     int32_t halo_lds;
-    int32_t pad_;
+    int32_t bond_stride; /* partner entries per row (largest bond_cap; 0: no bonds) */
     int64_t n_local;   /* current local rows of the system (migration changes it) */
     int64_t n_total;   /* locals + ghosts */
 } hoomd_layout;

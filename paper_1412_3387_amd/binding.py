@@ -24,6 +24,8 @@ NVE, NVT = 0, 1
 ENERGY, VIRIAL = 1, 2
 GHOST_SELECT, GHOST_UPDATE = 0, 1
 FIELD_POS, FIELD_VEL, FIELD_TAG = 1, 2, 4
+BOND_START, BOND_MIGRATE = 0, 1
+BOND_RECORD_BYTES = 16
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_DEVICE", 3: "E_WORKSPACE", 4: "E_STATE",
           5: "E_NLIST_OVERFLOW", 6: "E_CELL_OVERFLOW", 7: "E_GHOST_OVERFLOW",
@@ -70,7 +72,7 @@ class Layout(C.Structure):
                 ("nlist_cap", C.c_int32), ("cell_cap", C.c_int32), ("halo_cap", C.c_int32),
                 ("bins", C.c_int32 * 3), ("row_offset", C.c_int64), ("cell_offset", C.c_int64),
                 ("tile_offset", C.c_int64), ("general_tiles", C.c_void_p),
-                ("rare_tiles", C.c_void_p), ("halo_lds", C.c_int32), ("pad_", C.c_int32),
+                ("rare_tiles", C.c_void_p), ("halo_lds", C.c_int32), ("bond_stride", C.c_int32),
                 ("n_local", C.c_int64), ("n_total", C.c_int64)]
 
 
@@ -94,7 +96,8 @@ EXPORTS = ["hoomd_workspace_bytes", "hoomd_init", "hoomd_destroy", "build_nlist"
            "hoomd_thermo_log", "hoomd_sync_status", "hoomd_build_count", "hoomd_get_layout",
            "hoomd_autotune", "hoomd_profile", "hoomd_strerror", "pack_ghosts_noalloc",
            "integrate_half_step", "hoomd_rebuild_due", "migrate_particles", "receive_particles",
-           "hoomd_thermostat", "hoomd_set_thermostat"]
+           "hoomd_thermostat", "hoomd_set_thermostat",
+           "pack_bond_ranks", "unpack_bond_ranks"]
 
 _lib = None
 
@@ -141,6 +144,9 @@ def lib():
         L.migrate_particles.argtypes = [P, C.c_int32, C.POINTER(Subdomain), P, C.c_int64, P, P,
                                         C.POINTER(C.c_int64)]
         L.receive_particles.argtypes = [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_double)]
+        L.pack_bond_ranks.argtypes = [P, C.c_int32, C.POINTER(Subdomain), C.c_int32, P, C.c_int64, P, P,
+                                      C.POINTER(C.c_int64)]
+        L.unpack_bond_ranks.argtypes = [P, C.c_int32, P, C.c_int64, C.c_int32]
         L.hoomd_strerror.argtypes = [C.c_int]
         L.hoomd_strerror.restype = C.c_char_p
         _lib = L
@@ -348,9 +354,29 @@ class Context:
     def _refresh_counts(self, sys: int):
         self.n_local[sys] = int(self.layout(sys).n_local)
 
+    def migrate_record_bytes(self) -> int:
+        """Bytes of one migration record: position, velocity, tag, and with
+        bonds the partner tags and owner directions."""
+        return 56 + 8 * self.layout(0).bond_stride
+
+    def pack_bond_ranks(self, sys: int, lo, hi, mode: int, send, send_cap: int, counts, offsets) -> int:
+        """Bond owner-table messages of `sys` (16 bytes each); returns their number."""
+        sd = Subdomain()
+        for a in range(3):
+            sd.lo[a] = float(lo[a])
+            sd.hi[a] = float(hi[a])
+        sd.width = 0.0
+        n = C.c_int64()
+        _check(lib().pack_bond_ranks(self.h, sys, C.byref(sd), mode, _ptr(send), send_cap, _ptr(counts),
+                                     _ptr(offsets), C.byref(n)), "pack_bond_ranks")
+        return n.value
+
+    def unpack_bond_ranks(self, sys: int, recv, n_recv: int, mode: int):
+        _check(lib().unpack_bond_ranks(self.h, sys, _ptr(recv), n_recv, mode), "unpack_bond_ranks")
+
     def migrate_particles(self, sys: int, lo, hi, send, send_cap: int, counts, offsets) -> int:
         """Pack and remove the locals of `sys` that left [lo, hi); returns how
-        many left (their records: position, velocity, tag; 56 bytes each)."""
+        many left (records of migrate_record_bytes() each)."""
         sd = Subdomain()
         for a in range(3):
             sd.lo[a] = float(lo[a])

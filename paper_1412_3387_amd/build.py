@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhoomd_mi355x.so")
-SOURCES = ["nlist.hip", "forces.hip", "sort.hip", "ghost.hip", "runtime.hip"]
+SOURCES = ["nlist.hip", "forces.hip", "sort.hip", "ghost.hip", "bonds.hip", "runtime.hip"]
 HEADERS = ["device.h", "launch.h", "sort.h", "ghost.h"]
 ARCH = "gfx950"
 

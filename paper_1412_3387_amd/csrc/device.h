@@ -41,6 +41,9 @@ struct SysDev {
     int32_t bond_stride;    // entries per particle of the partner table (same for all systems)
     int64_t nl0;            // first neighbour-list entry of this system
     int64_t cell0;          // first cell of this system
+    int64_t hash0;          // first slot of this system's tag -> row table (bonded systems)
+    int32_t hash_mask;      // its slots - 1 (a power of two minus one)
+    int32_t hash_pad;
     int32_t tile0;          // first local tile (64 rows) of this system
     int32_t tile0_all;      // first tile over all rows (locals + ghosts)
     int32_t pair;           // Pair

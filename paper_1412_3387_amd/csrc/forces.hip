@@ -80,8 +80,7 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
                                            const int32_t *__restrict__ nn, int cap,
                                            const int32_t *__restrict__ halo,
                                            const int32_t *__restrict__ halo_n, int halo_cap, int halo_lds,
-                                           const int32_t *__restrict__ partners,
-                                           const int32_t *__restrict__ rtag,
+                                           const int32_t *__restrict__ prow,
                                            const double4 *__restrict__ xbuild,
                                            double *__restrict__ partials, Status *st, const ForceLaunch &a)
 {
@@ -351,14 +350,16 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
     if (owner) {
         double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
         double ue = 0.5 * e, uw = 0.5 * vir;
-        // bonds: FENE + WCA with partner rows indexed by tag
+        // bonds: FENE + WCA with the partner rows found at the last change
+        // of rows (a local row or a ghost)
         if (S.bond_cap > 0) {
-            const int32_t tg = a.tag[i];
-            const int64_t prow = (row0 + tg) * S.bond_stride;
+            const int64_t pr = i * S.bond_stride;
             for (int b = 0; b < S.bond_cap; ++b) {
-                const int32_t tp = partners[prow + b];
-                if (tp < 0) continue;
-                const int64_t j = rtag[row0 + tp];
+                const int32_t j = prow[pr + b];
+                if (j < 0) {
+                    if (j == -2) latch(st, 12 /*BOND_GHOST*/, 0);  // a partner that is not here
+                    continue;
+                }
                 const double4 xj = a.pos[j];
                 const double ddx = min_image(xi.x - xj.x, Lx, iLx);
                 const double ddy = min_image(xi.y - xj.y, Ly, iLy);
@@ -479,10 +480,10 @@ __device__ __forceinline__ void force_tile(int tile, double *lds, const SysDev *
     const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys,                      \
         const uint16_t *__restrict__ nlist, const int32_t *__restrict__ nn, int cap,                     \
         const int32_t *__restrict__ halo, const int32_t *__restrict__ halo_n, int halo_cap, int halo_lds, \
-        const int32_t *__restrict__ partners, const int32_t *__restrict__ rtag,                          \
+        const int32_t *__restrict__ prow,                                                               \
         const double4 *__restrict__ xbuild, double *__restrict__ partials, Status *st,                   \
         const int32_t *__restrict__ rare_list, const int32_t *__restrict__ rare_n, ForceLaunch a
-#define FORCE_PASS sys, tprefix, n_sys, nlist, nn, cap, halo, halo_n, halo_cap, halo_lds, partners, rtag, \
+#define FORCE_PASS sys, tprefix, n_sys, nlist, nn, cap, halo, halo_n, halo_cap, halo_lds, prow, \
                    xbuild, partials, st, a
 
 // Main launch: one workgroup per tile; rare tiles return at once.
@@ -746,20 +747,6 @@ __global__ __launch_bounds__(256) void k_nvt_update(const SysDev *__restrict__ s
     }
 }
 
-// rtag[row0 + tag[i]] = i over all rows of every system.
-__global__ void k_rtag(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys,
-                       int tiles, const int32_t *__restrict__ tag, int32_t *__restrict__ rtag)
-{
-    const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (g >= tiles) return;
-    const int s = find_sys(tprefix, n_sys, g);
-    const SysDev &S = sys[s];
-    const int r = (g - S.tile0_all) * kTile + lane_id();
-    if (r >= S.n_total) return;
-    const int64_t i = S.row0 + r;
-    rtag[S.row0 + tag[i]] = (int32_t)i;
-}
-
 // ---------------------------------------------------------------------------
 
 int force_row_over_read() { return kRowOverRead; }
@@ -779,7 +766,7 @@ static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
     const size_t lds = force_lds_bytes(POT, L.halo_lds, L.nlist_cap);
     hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(L.tiles_local), dim3(W * kWave), lds, L.stream,
                        L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                       L.halo_cap, L.halo_lds, L.partners, L.rtag, L.xbuild, L.partials, L.status,
+                       L.halo_cap, L.halo_lds, L.prow, L.xbuild, L.partials, L.status,
                        L.rare_list, L.rare_n, F);
     // the launch over rare tiles runs few workgroups: it stages up to the
     // whole halo list (at most kRareLds bytes), so that oversized halos are
@@ -791,7 +778,7 @@ static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
     const size_t rare_lds = force_lds_bytes(POT, rare_lds_entries, L.nlist_cap);
     hipLaunchKernelGGL((k_force_rare<W, MIXED, POT, LOG>), dim3(rb), dim3(W * kWave), rare_lds, L.stream, L.sys,
                        L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n, L.halo_cap,
-                       rare_lds_entries, L.partners, L.rtag, L.xbuild, L.partials, L.status, L.rare_list,
+                       rare_lds_entries, L.prow, L.xbuild, L.partials, L.status, L.rare_list,
                        L.rare_n, F);
 }
 
@@ -913,13 +900,5 @@ void launch_nvt_update(const LaunchCtx &L, int w)
                        L.khalf, L.thermostat);
 }
 
-void launch_rtag(const LaunchCtx &L, const int32_t *tag)
-{
-    const int threads = 256;
-    const int blocks = (L.tiles_all * kWave + threads - 1) / threads;
-    if (blocks == 0) return;
-    hipLaunchKernelGGL(k_rtag, dim3(blocks), dim3(threads), 0, L.stream, L.sys, L.tprefix_all,
-                       L.n_sys, L.tiles_all, tag, L.rtag);
-}
 
 }  // namespace md

@@ -27,7 +27,7 @@ size_t ghost_workspace_bytes(int64_t rows, int n_sys)
            a256(sizeof(int32_t) * scan_sums_len(26 * blocks)) +
            a256(sizeof(int32_t) * kGhostPerRow * (size_t)rows) + a256(sizeof(int32_t) * n_sys) +
            a256(sizeof(int32_t) * rows) + a256(sizeof(int32_t) * scan_sums_len(rows)) + a256(sizeof(int32_t) * 2) +
-           256;
+           a256(sizeof(int32_t) * 32) + 256;
 }
 
 GhostBuffers make_ghost_buffers(char *base, int64_t rows, int n_sys)
@@ -42,7 +42,8 @@ GhostBuffers make_ghost_buffers(char *base, int64_t rows, int n_sys)
     B.totals = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * n_sys);
     B.stay = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * rows);
     B.stay_sums = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * scan_sums_len(rows));
-    B.counts2 = reinterpret_cast<int32_t *>(base + off);
+    B.counts2 = reinterpret_cast<int32_t *>(base + off); off += a256(sizeof(int32_t) * 2);
+    B.cursor = reinterpret_cast<int32_t *>(base + off);
     B.rows = rows;
     return B;
 }
@@ -78,9 +79,11 @@ __device__ __forceinline__ uint32_t ghost_mask(const double4 x, const GhostArgs 
     return m;
 }
 
-__device__ __forceinline__ void pack_record(const GhostArgs &g, int64_t k, int64_t row)
+// Record k of the send buffer from row `row`, sent in direction `code`.
+__device__ __forceinline__ void pack_record(const GhostArgs &g, int64_t k, int64_t row, int code)
 {
-    double *rec = reinterpret_cast<double *>(static_cast<char *>(g.send) + k * ghost_record_bytes(g.fields));
+    double *rec = reinterpret_cast<double *>(static_cast<char *>(g.send) +
+                                             k * ghost_record_bytes(g.fields, g.bond_stride));
     int q = 0;
     if (g.fields & 1u) {
         const double4 x = g.pos[row];
@@ -98,7 +101,36 @@ __device__ __forceinline__ void pack_record(const GhostArgs &g, int64_t k, int64
         int32_t *t = reinterpret_cast<int32_t *>(rec + q);
         t[0] = g.tag[row];
         t[1] = 0;
+        ++q;
     }
+    if (g.fields & kFieldBonds) {
+        // a migrating row takes its partners along; their owners' directions
+        // become relative to the receiver (one step `code` away)
+        int32_t *b = reinterpret_cast<int32_t *>(rec + q);
+        for (int s = 0; s < g.bond_stride; ++s) {
+            const int32_t t = g.ptag[row * g.bond_stride + s];
+            int32_t d = -1;
+            if (t >= 0) {
+                d = dir_sub(g.pdir[row * g.bond_stride + s], code);
+                if (d < 0 && g.status) latch(g.status, 12 /*BOND_GHOST*/, 0);
+            }
+            b[s] = t;
+            b[g.bond_stride + s] = d;
+        }
+    }
+}
+
+// Directions of the partners of row `row` that live in other subdomains, as
+// send bits (Sec. 4.3.4: a particle goes as a ghost wherever a bond partner
+// is owned).
+__device__ __forceinline__ uint32_t bond_dir_mask(const GhostArgs &g, int64_t row)
+{
+    uint32_t m = 0;
+    for (int s = 0; s < g.bond_cap; ++s) {
+        const int32_t d = g.pdir[row * g.bond_stride + s];
+        if (d >= 0 && d != 13 && g.ptag[row * g.bond_stride + s] >= 0) m |= 1u << dir_index(d);
+    }
+    return m;
 }
 
 // Per-wave, per-direction counts into LDS: wc[wave][d].
@@ -120,6 +152,7 @@ __global__ __launch_bounds__(kGhostBlock) void k_ghost_mask(GhostArgs g, int32_t
     uint32_t m = 0;
     if (r < g.n_local) {
         m = ghost_mask(g.pos[g.row0 + r], g);
+        if (g.pdir) m |= bond_dir_mask(g, g.row0 + r);
         g.mask[r] = m;
     }
     wave_dir_counts(m, wc);
@@ -163,7 +196,7 @@ __global__ __launch_bounds__(kGhostBlock) void k_ghost_scatter(GhostArgs g, cons
         int64_t p = scanned[(int64_t)d * nblocks + blockIdx.x] + __popcll(b & lt);
         for (int v = 0; v < w; ++v) p += wc[v][d];
         if (g.list && p < g.list_cap) g.list[p] = r;
-        if (p < g.send_cap) pack_record(g, p, g.row0 + r);
+        if (p < g.send_cap) pack_record(g, p, g.row0 + r, dir_of_index(d));
     }
 }
 
@@ -173,7 +206,7 @@ __global__ void k_ghost_regather(GhostArgs g)
     n = n < g.list_cap ? n : g.list_cap;
     n = n < g.send_cap ? n : g.send_cap;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-        pack_record(g, k, g.row0 + g.list[k]);
+        pack_record(g, k, g.row0 + g.list[k], 13);
 }
 
 __global__ void k_ghost_unpack(UnpackArgs u)
@@ -181,7 +214,7 @@ __global__ void k_ghost_unpack(UnpackArgs u)
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= u.n) return;
     const double *rec = reinterpret_cast<const double *>(static_cast<const char *>(u.recv) +
-                                                         k * ghost_record_bytes(u.fields));
+                                                         k * ghost_record_bytes(u.fields, u.bond_stride));
     const int64_t row = u.first + k;
     int q = 0;
     if (u.fields & 1u) {
@@ -197,7 +230,17 @@ __global__ void k_ghost_unpack(UnpackArgs u)
         u.vel[row] = make_double4(rec[q], rec[q + 1], rec[q + 2], 0.0);
         q += 3;
     }
-    if (u.fields & 4u) u.tag[row] = reinterpret_cast<const int32_t *>(rec + q)[0];
+    if (u.fields & 4u) {
+        u.tag[row] = reinterpret_cast<const int32_t *>(rec + q)[0];
+        ++q;
+    }
+    if (u.fields & kFieldBonds) {
+        const int32_t *b = reinterpret_cast<const int32_t *>(rec + q);
+        for (int s = 0; s < u.bond_stride; ++s) {
+            u.ptag[row * u.bond_stride + s] = b[s];
+            u.pdir[row * u.bond_stride + s] = b[u.bond_stride + s];
+        }
+    }
 }
 
 // Destination of a local row after a drift: per axis +1 at or beyond hi, -1
@@ -240,7 +283,9 @@ __global__ void k_migrate_compact(int64_t row0, int n_local, const int32_t *__re
                                   const int32_t *__restrict__ dst, const double4 *__restrict__ pos,
                                   const double4 *__restrict__ vel, const int32_t *__restrict__ tag,
                                   double4 *__restrict__ pos_tmp, double4 *__restrict__ vel_tmp,
-                                  int32_t *__restrict__ tag_tmp)
+                                  int32_t *__restrict__ tag_tmp, const int32_t *__restrict__ ptag,
+                                  const int32_t *__restrict__ pdir, int32_t *__restrict__ ptag_tmp,
+                                  int32_t *__restrict__ pdir_tmp, int stride)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_local || mask[r] != 0) return;
@@ -248,6 +293,10 @@ __global__ void k_migrate_compact(int64_t row0, int n_local, const int32_t *__re
     pos_tmp[d] = pos[row0 + r];
     vel_tmp[d] = vel[row0 + r];
     tag_tmp[d] = tag[row0 + r];
+    for (int s = 0; s < stride; ++s) {
+        ptag_tmp[d * stride + s] = ptag[(row0 + r) * stride + s];
+        pdir_tmp[d * stride + s] = pdir[(row0 + r) * stride + s];
+    }
 }
 
 __global__ void k_migrate_counts(const int32_t *__restrict__ left, int32_t *__restrict__ counts2, int any_local)
@@ -271,7 +320,8 @@ int queue_ghost_select(hipStream_t stream, const GhostBuffers &B, const GhostArg
 }
 
 int queue_migrate(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g, double4 *pos, double4 *vel,
-                  int32_t *tag, double4 *pos_tmp, double4 *vel_tmp, int32_t *tag_tmp)
+                  int32_t *tag, double4 *pos_tmp, double4 *vel_tmp, int32_t *tag_tmp, int32_t *ptag,
+                  int32_t *pdir, int32_t *ptag_tmp, int32_t *pdir_tmp)
 {
     const int nblocks = (g.n_local + kGhostBlock - 1) / kGhostBlock;
     const int nb = nblocks > 0 ? nblocks : 1;
@@ -289,7 +339,7 @@ int queue_migrate(hipStream_t stream, const GhostBuffers &B, const GhostArgs &g,
         const int blocks = (g.n_local + 255) / 256;
         hipLaunchKernelGGL(k_migrate_compact, dim3(blocks), dim3(256), 0, stream, g.row0, g.n_local,
                            reinterpret_cast<const int32_t *>(g.mask), B.stay, pos, vel, tag, pos_tmp, vel_tmp,
-                           tag_tmp);
+                           tag_tmp, ptag, pdir, ptag_tmp, pdir_tmp, ptag ? g.bond_stride : 0);
     }
     hipLaunchKernelGGL(k_migrate_counts, dim3(1), dim3(1), 0, stream, g.total, B.counts2, g.n_local > 0 ? 1 : 0);
     return hipGetLastError() == hipSuccess ? 0 : 1;

@@ -39,8 +39,13 @@ struct LaunchCtx {
     int halo_cap;
     int halo_lds;                  // halo entries the force pass stages in LDS
     double4 *xbuild;
-    const int32_t *partners;       // per tag: bond_cap partner tags (-1 = none)
-    int32_t *rtag;                 // row of each tag (per system offset row0)
+    int32_t *ptag;                 // per row: bond_stride partner tags (-1 = none), moved with the row
+    int32_t *pdir;                 // per row and partner: direction code of the partner's owner
+                                   // (13 = this system, -1 = not known yet)
+    int32_t *prow;                 // per row and partner: the partner's row (-1 none, -2 not present)
+    int32_t *btmp;                 // rows x bond_stride scratch (reordering ptag / pdir)
+    int2 *hash;                    // tag -> row tables of the bonded systems
+    int bond_stride;
     bool has_bonds;
     int32_t *slow_list;            // tiles the framed build passes on to the general one
     char *plan;                    // per-tile plans of the framed build (build_plan_bytes)
@@ -97,7 +102,9 @@ void launch_set_flag(const LaunchCtx &L, int32_t *flag, int32_t value);
 void launch_set_counts(const LaunchCtx &L, int s, int32_t n_local, int32_t n_total);
 // Sets a rebuild flag and all per-system flags of its slot.
 void launch_set_flags(const LaunchCtx &L, int32_t *flag, int32_t *sflag, int32_t value);
-void launch_rtag(const LaunchCtx &L, const int32_t *tag);
+// Tag -> row tables and the partner rows of the bonded systems (all of them
+// when sys < 0), from the current rows (locals and ghosts).
+void launch_bond_refresh(const LaunchCtx &L, const int32_t *tag, int sys);
 // Half a velocity-Verlet step over the local rows (which = 0: kick, drift,
 // displacement check into flag / sflag; 1: kick) from the force array.
 void launch_half_step(const LaunchCtx &L, double4 *pos, double4 *vel, const void *force, bool mixed, int which,

@@ -319,7 +319,7 @@ __device__ __forceinline__ int upper_idx(const int32_t *a, int n, int x)
 template <bool EXCL>
 __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
     const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
-    const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ partners,
+    const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ ptag,
     const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx, int cell_cap,
     uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int32_t *__restrict__ halo,
     int32_t *__restrict__ halo_n, int halo_cap, double4 *__restrict__ xbuild,
@@ -501,8 +501,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_tile(
 #pragma unroll
             for (int b = 0; b < kMaxBondCap; ++b) part[b] = -1;
             if (active) {
-                const int64_t prow = (row0 + tag[i]) * S.bond_stride;
-                for (int b = 0; b < S.bond_cap && b < kMaxBondCap; ++b) part[b] = partners[prow + b];
+                const int64_t prow = i * S.bond_stride;
+                for (int b = 0; b < S.bond_cap && b < kMaxBondCap; ++b) part[b] = ptag[prow + b];
             }
         }
         const int64_t rowbase = nl0 + (int64_t)(r >> 6) * cap * kTile + (r & 63);
@@ -1146,7 +1146,7 @@ __device__ __forceinline__ int4 next_header(const int4 *hdr, int tile)
 template <bool EXCL, int NT, int LPR>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_build_fast(
     const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix, int n_sys, int tiles,
-    const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ partners,
+    const double4 *__restrict__ pos, const int32_t *__restrict__ tag, const int32_t *__restrict__ ptag,
     const int32_t *__restrict__ cell_size, const int32_t *__restrict__ cell_idx,
     const float4 *__restrict__ cell_xf, int cell_cap,
     uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int rstride,
@@ -1392,10 +1392,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const int32_t it = (int32_t)(row0 + r0 + t);
                     int32_t part[kMaxBondCap];
                     if constexpr (EXCL) {
-                        const int64_t prow = (row0 + tag[it]) * S.bond_stride;
+                        const int64_t prow = (int64_t)it * S.bond_stride;
     #pragma unroll
                         for (int bnd = 0; bnd < kMaxBondCap; ++bnd)
-                            part[bnd] = bnd < S.bond_cap ? partners[prow + bnd] : -1;
+                            part[bnd] = bnd < S.bond_cap ? ptag[prow + bnd] : -1;
                     }
                     uint16_t *myrow = srows + t * rstride;
                     // exact FP64 decision of a candidate whose FP32 distance is
@@ -1546,10 +1546,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     #pragma unroll
                         for (int bnd = 0; bnd < kMaxBondCap; ++bnd) part[bnd] = -1;
                         if (row_on) {
-                            const int64_t prow = (row0 + tag[it]) * S.bond_stride;
+                            const int64_t prow = (int64_t)it * S.bond_stride;
     #pragma unroll
                             for (int bnd = 0; bnd < kMaxBondCap; ++bnd)
-                                part[bnd] = bnd < S.bond_cap ? partners[prow + bnd] : -1;
+                                part[bnd] = bnd < S.bond_cap ? ptag[prow + bnd] : -1;
                         }
                     }
                     uint16_t *myrow = srows + t * rstride;
@@ -1809,7 +1809,7 @@ static void fast_inst(const LaunchCtx &L, const double4 *pos, const int32_t *tag
                       const PlanPtrs &plan)
 {
     hipLaunchKernelGGL((k_build_fast<EXCL, NT, LPR>), dim3(blocks), dim3(NT), dyn, L.stream, L.sys, L.tprefix_local,
-                       L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size, L.cell_idx, L.cell_xf, L.cell_cap,
+                       L.n_sys, L.tiles_local, pos, tag, L.ptag, L.cell_size, L.cell_idx, L.cell_xf, L.cell_cap,
                        L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n, L.halo_cap, plan, L.halo_lds, L.rare_list,
                        L.rare_n, L.cell_count, L.n_cells, L.flag, L.sflag, L.build_count, L.status);
 }
@@ -1844,14 +1844,14 @@ void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, in
     if (L.has_bonds) {
         fast_shape<true>(L, pos, tag, blocks, rs, dyn, plan, w, block);
         hipLaunchKernelGGL(k_build_tile<true>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
-                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
+                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.ptag, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
                            L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
                            nullptr, L.status);
     } else {
         fast_shape<false>(L, pos, tag, blocks, rs, dyn, plan, w, block);
         hipLaunchKernelGGL(k_build_tile<false>, dim3(blocks), dim3(kBuildThreads), 0, L.stream, L.sys,
-                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.partners, L.cell_size,
+                           L.tprefix_local, L.n_sys, L.tiles_local, pos, tag, L.ptag, L.cell_size,
                            L.cell_idx, L.cell_cap, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
                            L.halo_cap, L.xbuild, L.slow_list, L.slow_n, L.halo_lds, L.rare_list, L.rare_n, L.flag,
                            nullptr, L.status);

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/hoomd_mi355x.h"
@@ -36,9 +37,9 @@ struct Layout {
     // byte offsets into the workspace
     size_t sysdev, tpl, tpa, cpre, status, flags, sysflags, thermo, thermo_log, partials, khalf, thermostat;
     size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, cell_xf, halo, halo_n;
-    size_t rtag, partners, slow_list, rare_list, plan, sort_ws, ghost_ws, total;
+    size_t ptag, pdir, prow, btmp, hash, slow_list, rare_list, plan, sort_ws, ghost_ws, total;
     // sizes
-    int64_t rows, tiles_local, tiles_all, n_cells, nlist_entries;
+    int64_t rows, tiles_local, tiles_all, n_cells, nlist_entries, hash_slots;
     int cell_cap, nlist_cap, bond_cap, halo_cap, halo_lds;
     std::vector<SysDev> sys;
     std::vector<int32_t> tpl_host, tpa_host;
@@ -115,7 +116,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.nlist_cap = 0;
     Lo.cell_cap = 0;
     Lo.bond_cap = 0;
-    int64_t row = 0, tile = 0, tile_all = 0, cell = 0, nl = 0;
+    int64_t row = 0, tile = 0, tile_all = 0, cell = 0, nl = 0, hslot = 0;
     Lo.tpl_host.push_back(0);
     Lo.tpa_host.push_back(0);
     Lo.cpre_host.push_back(0);
@@ -238,6 +239,16 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
             int cc = (int)std::ceil((2.0 * mean + 16.0) / 8.0) * 8;
             Lo.cell_cap = std::max(Lo.cell_cap, std::min(cc, 128));
         }
+        // bonded systems: a tag -> row table with at least twice as many
+        // slots as rows (locals and ghosts)
+        S.hash0 = hslot;
+        S.hash_mask = 0;
+        if (q.bond_cap > 0) {
+            int64_t h = 64;
+            while (h < 2 * b.n_cap) h *= 2;
+            S.hash_mask = (int32_t)(h - 1);
+            hslot += h;
+        }
         Lo.sys.push_back(S);
         row += b.n_cap;
         // local tiles cover the rows the system may own (its capacity), so
@@ -253,6 +264,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         (void)vol;
     }
     Lo.rows = row;
+    Lo.hash_slots = hslot;
     Lo.tiles_local = tile;
     Lo.tiles_all = tile_all;
     Lo.n_cells = cell;
@@ -290,8 +302,12 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.cell_size = take(sizeof(int32_t) * (size_t)cell);
     Lo.cell_idx = take(sizeof(int32_t) * (size_t)cell * Lo.cell_cap);
     Lo.cell_xf = take(sizeof(float4) * (size_t)cell * Lo.cell_cap);
-    Lo.rtag = take(sizeof(int32_t) * rows);
-    Lo.partners = take(sizeof(int32_t) * rows * std::max(Lo.bond_cap, 1));
+    const size_t brows = Lo.bond_cap > 0 ? rows * (size_t)Lo.bond_cap : 1;
+    Lo.ptag = take(sizeof(int32_t) * brows);
+    Lo.pdir = take(sizeof(int32_t) * brows);
+    Lo.prow = take(sizeof(int32_t) * brows);
+    Lo.btmp = take(sizeof(int32_t) * brows);
+    Lo.hash = take(sizeof(int2) * (size_t)std::max<int64_t>(Lo.hash_slots, 1));
     Lo.slow_list = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
     Lo.rare_list = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile, 1));
     Lo.plan = take(build_plan_bytes(tile));
@@ -318,6 +334,7 @@ struct hoomd_ctx {
     int pair_uniform;  // common Pair of all systems, or -1
     bool built;        // a neighbour list exists for the current rows
     int64_t ghosts;    // ghost rows appended over all systems (no sorting then)
+    std::vector<char> bond_ok;  // per system: tag -> row table and partner rows match the rows
     int tpp_nlist, block_nlist, tpp_force, block_force;
     // autotuner state: shapes fixed by the caller are not tuned
     bool fixed_force, fixed_nlist;
@@ -569,8 +586,12 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.nn = ws_ptr<int32_t>(c, lay.nn);
     L.nlist_cap = lay.nlist_cap;
     L.xbuild = ws_ptr<double4>(c, lay.xbuild);
-    L.partners = ws_ptr<int32_t>(c, lay.partners);
-    L.rtag = ws_ptr<int32_t>(c, lay.rtag);
+    L.ptag = ws_ptr<int32_t>(c, lay.ptag);
+    L.pdir = ws_ptr<int32_t>(c, lay.pdir);
+    L.prow = ws_ptr<int32_t>(c, lay.prow);
+    L.btmp = ws_ptr<int32_t>(c, lay.btmp);
+    L.hash = ws_ptr<int2>(c, lay.hash);
+    L.bond_stride = lay.bond_cap;
     L.has_bonds = nb_total > 0;
     L.flag = flag_ptr(c, 0);
     L.build_count = flag_ptr(c, 4);
@@ -611,55 +632,59 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     if (e == hipSuccess) e = hipMemset(c->ws + lay.cell_count, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(lay.n_cells, 1));
     if (e == hipSuccess) e = hipMemset(c->ws + lay.thermo, 0, sizeof(double) * 4 * n_sys);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.thermostat, 0, sizeof(double) * 2 * n_sys);
-    // bond partner rows by tag (built on the host from the caller's table)
+    // bond partner entries per row (built on the host from the caller's table)
     if (e == hipSuccess && lay.bond_cap > 0) {
-        std::vector<int32_t> rows((size_t)lay.rows * lay.bond_cap, -1);
+        // per row: partner tags and the direction of each partner's owner
+        // (13 here; -1 not known yet: a subdomain's partners beyond its
+        // frame, found by the start messages of pack_bond_ranks)
+        std::vector<int32_t> ptag((size_t)lay.rows * lay.bond_cap, -1), pdir((size_t)lay.rows * lay.bond_cap, -1);
         std::vector<int32_t> pairs;
-        // bonded systems index partner rows by tag: tags must be 0..n-1
-        {
-            std::vector<int32_t> tags((size_t)lay.rows);
-            e = hipMemcpy(tags.data(), arrays->tag, sizeof(int32_t) * lay.rows, hipMemcpyDeviceToHost);
-            for (int s = 0; s < n_sys && e == hipSuccess; ++s) {
-                std::vector<char> seen((size_t)boxes[s].n_local, 0);
-                for (int64_t r = 0; r < boxes[s].n_local; ++r) {
-                    const int32_t t = tags[(size_t)(lay.sys[s].row0 + r)];
-                    if (t < 0 || t >= boxes[s].n_local || seen[(size_t)t]) {
-                        e = hipErrorInvalidValue;
-                        break;
-                    }
-                    seen[(size_t)t] = 1;
-                }
-            }
-        }
+        std::vector<int32_t> tags((size_t)lay.rows);
+        e = hipMemcpy(tags.data(), arrays->tag, sizeof(int32_t) * lay.rows, hipMemcpyDeviceToHost);
         int64_t b0 = 0;
         for (int s = 0; s < n_sys && e == hipSuccess; ++s) {
             const int64_t nb = boxes[s].n_bonds;
-            if (nb > 0) {
+            const bool closed = boxes[s].periodic[0] && boxes[s].periodic[1] && boxes[s].periodic[2];
+            // tags of the system's rows: unique, non-negative
+            std::unordered_map<int32_t, int64_t> row_of;
+            for (int64_t r = 0; r < boxes[s].n_local && e == hipSuccess; ++r) {
+                const int32_t t = tags[(size_t)(lay.sys[s].row0 + r)];
+                if (t < 0 || !row_of.emplace(t, lay.sys[s].row0 + r).second) e = hipErrorInvalidValue;
+            }
+            if (nb > 0 && e == hipSuccess) {
                 pairs.resize((size_t)nb * 2);
                 e = hipMemcpy(pairs.data(), arrays->bonds + 2 * b0, sizeof(int32_t) * 2 * nb, hipMemcpyDeviceToHost);
                 for (int64_t k = 0; k < nb && e == hipSuccess; ++k) {
                     const int32_t ta = pairs[2 * k], tb = pairs[2 * k + 1];
-                    if (ta < 0 || tb < 0 || ta >= boxes[s].n_local || tb >= boxes[s].n_local || ta == tb) {
+                    const auto ia = row_of.find(ta), ib = row_of.find(tb);
+                    const bool la = ia != row_of.end(), lb = ib != row_of.end();
+                    // a bond has a local member; in a closed box both are local
+                    if (ta < 0 || tb < 0 || ta == tb || (!la && !lb) || (closed && !(la && lb))) {
                         e = hipErrorInvalidValue;
                         break;
                     }
-                    for (int side = 0; side < 2; ++side) {
-                        const int32_t me = side ? tb : ta, other = side ? ta : tb;
-                        int32_t *slot = &rows[(size_t)(lay.sys[s].row0 + me) * lay.bond_cap];
+                    for (int side = 0; side < 2 && e == hipSuccess; ++side) {
+                        if (!(side ? lb : la)) continue;
+                        const int64_t me = side ? ib->second : ia->second;
+                        const bool other_here = side ? la : lb;
+                        int32_t *slot = &ptag[(size_t)me * lay.bond_cap];
                         int q = 0;
                         while (q < params[s].bond_cap && slot[q] >= 0) ++q;
                         if (q == params[s].bond_cap) {
                             e = hipErrorInvalidValue;
                             break;
                         }
-                        slot[q] = other;
+                        slot[q] = side ? ta : tb;
+                        pdir[(size_t)me * lay.bond_cap + q] = other_here ? 13 : -1;
                     }
                 }
             }
             b0 += nb;
         }
         if (e == hipSuccess)
-            e = hipMemcpy(c->ws + lay.partners, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice);
+            e = hipMemcpy(c->ws + lay.ptag, ptag.data(), sizeof(int32_t) * ptag.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->ws + lay.pdir, pdir.data(), sizeof(int32_t) * pdir.size(), hipMemcpyHostToDevice);
         if (e == hipErrorInvalidValue) {
             delete c;
             return HOOMD_E_ARG;
@@ -669,7 +694,8 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
         delete c;
         return HOOMD_E_DEVICE;
     }
-    if (lay.bond_cap > 0) launch_rtag(c->L, c->arr.tag);
+    launch_bond_refresh(c->L, c->arr.tag, -1);
+    c->bond_ok.assign((size_t)n_sys, 1);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         delete c;
         return HOOMD_E_DEVICE;
@@ -693,7 +719,7 @@ int build_nlist(hoomd_ctx *c, int32_t force_rebuild)
             if (queue_morton_sort(c->L, c->sortb, pos, reinterpret_cast<double4 *>(c->arr.vel), c->arr.tag,
                                   ws_ptr<double4>(c, c->lay.pos_alt), ws_ptr<double4>(c, c->lay.vel_alt)))
                 return HOOMD_E_DEVICE;
-            if (c->lay.bond_cap > 0) launch_rtag(c->L, c->arr.tag);
+            launch_bond_refresh(c->L, c->arr.tag, -1);
         }
         launch_set_flags(c->L, flag, sflag, 1);
     } else {
@@ -812,7 +838,7 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
                 c->L.step_counter = nullptr;
                 return HOOMD_E_DEVICE;
             }
-            if (c->lay.bond_cap > 0) launch_rtag(c->L, tag);
+            launch_bond_refresh(c->L, tag, -1);
             launch_set_flags(c->L, flag_ptr(c, p), sflag_ptr(c, p), 1);  // a sort moves every system's rows
         }
         const size_t r0 = mark(c);
@@ -861,6 +887,13 @@ int pack_ghosts(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, int32_t mo
     g.list = c->ghostb.list + (int64_t)kGhostPerRow * c->lay.sys[sys].row0;
     g.list_cap = (int64_t)kGhostPerRow * c->box[sys].n_cap;
     g.total = c->ghostb.totals + sys;
+    if (c->lay.sys[sys].bond_cap > 0) {
+        // a particle also goes wherever one of its partners is owned (Sec. 4.3.4)
+        g.ptag = c->L.ptag;
+        g.pdir = c->L.pdir;
+        g.bond_stride = c->lay.bond_cap;
+        g.bond_cap = c->lay.sys[sys].bond_cap;
+    }
     int rc = mode == HOOMD_GHOST_SELECT ? queue_ghost_select(c->stream, c->ghostb, g)
                                         : queue_ghost_update(c->stream, c->ghostb, g);
     return rc ? HOOMD_E_DEVICE : HOOMD_OK;
@@ -910,6 +943,68 @@ int integrate_half_step(hoomd_ctx *c, int32_t which, uint64_t timestep)
     return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
 }
 
+int pack_bond_ranks(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, int32_t mode, void *send,
+                    int64_t send_cap, int32_t *counts26, int32_t *offsets26, int64_t *n_sent)
+{
+    if (!c || !sd || sys < 0 || sys >= c->n_sys || !counts26 || !offsets26 || !n_sent) return HOOMD_E_ARG;
+    if (mode != HOOMD_BOND_START && mode != HOOMD_BOND_MIGRATE) return HOOMD_E_ARG;
+    if (send_cap < 0 || (send_cap > 0 && !send)) return HOOMD_E_ARG;
+    const SysDev &S = c->lay.sys[sys];
+    if (S.bond_cap == 0) return HOOMD_E_STATE;
+    if (!c->bond_ok[sys]) return HOOMD_E_STATE;  // rows changed since the partner rows were found
+    BondRankArgs a{};
+    for (int k = 0; k < 3; ++k) {
+        a.lo[k] = sd->lo[k];
+        a.hi[k] = sd->hi[k];
+    }
+    a.row0 = S.row0;
+    a.n_local = S.n_local;
+    a.mode = mode;
+    a.stride = c->lay.bond_cap;
+    a.bond_cap = S.bond_cap;
+    a.pos = reinterpret_cast<const double4 *>(c->arr.pos);
+    a.tag = c->arr.tag;
+    a.ptag = c->L.ptag;
+    a.pdir = c->L.pdir;
+    a.prow = c->L.prow;
+    a.send = send;
+    a.send_cap = send_cap;
+    a.counts = counts26;
+    a.offsets = offsets26;
+    a.cursor = c->ghostb.cursor;
+    a.status = c->L.status;
+    if (queue_bond_ranks(c->stream, a, c->ghostb.cursor + 26)) return HOOMD_E_DEVICE;
+    int32_t total = 0;
+    HIP_OK(hipMemcpyAsync(&total, c->ghostb.cursor + 26, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    *n_sent = total;
+    if (total > send_cap) return HOOMD_E_GHOST_OVERFLOW;
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
+}
+
+int unpack_bond_ranks(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, int32_t mode)
+{
+    if (!c || sys < 0 || sys >= c->n_sys || n_recv < 0 || (n_recv > 0 && !recv)) return HOOMD_E_ARG;
+    if (mode != HOOMD_BOND_START && mode != HOOMD_BOND_MIGRATE) return HOOMD_E_ARG;
+    const SysDev &S = c->lay.sys[sys];
+    if (S.bond_cap == 0) return HOOMD_E_STATE;
+    if (!c->bond_ok[sys]) return HOOMD_E_STATE;  // the tag -> row table is out of date
+    BondApplyArgs a{};
+    a.recv = recv;
+    a.n = n_recv;
+    a.row0 = S.row0;
+    a.n_local = S.n_local;
+    a.mode = mode;
+    a.stride = c->lay.bond_cap;
+    a.bond_cap = S.bond_cap;
+    a.hash = c->L.hash + S.hash0;
+    a.hash_mask = S.hash_mask;
+    a.ptag = c->L.ptag;
+    a.pdir = c->L.pdir;
+    a.status = c->L.status;
+    return queue_bond_apply(c->stream, a) ? HOOMD_E_DEVICE : HOOMD_OK;
+}
+
 int hoomd_rebuild_due(hoomd_ctx *c, int32_t *due)
 {
     if (!c || !due) return HOOMD_E_ARG;
@@ -926,7 +1021,6 @@ int migrate_particles(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, void
     if (!c || !sd || sys < 0 || sys >= c->n_sys || !counts26 || !offsets26 || !n_sent) return HOOMD_E_ARG;
     if (send_cap < 0 || (send_cap > 0 && !send)) return HOOMD_E_ARG;
     SysDev &S = c->lay.sys[sys];
-    if (S.bond_cap > 0) return HOOMD_E_STATE;  // bonded particles do not migrate
     GhostArgs g{};
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = sd->lo[a];
@@ -948,10 +1042,21 @@ int migrate_particles(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, void
     g.list = nullptr;
     g.list_cap = 0;
     g.total = c->ghostb.totals + sys;
+    const bool bonded = S.bond_cap > 0;
+    if (bonded) {
+        // Sec. 4.3.4: the bonds travel with their particles
+        g.fields |= kFieldBonds;
+        g.ptag = c->L.ptag;
+        g.pdir = c->L.pdir;
+        g.bond_stride = c->lay.bond_cap;
+        g.bond_cap = S.bond_cap;
+    }
     double4 *pt = ws_ptr<double4>(c, c->lay.pos_alt), *vt = ws_ptr<double4>(c, c->lay.vel_alt);
     int32_t *tt = c->sortb.tag_tmp;
+    // the partner-row table is rebuilt at the next ghost selection: scratch here
     if (queue_migrate(c->stream, c->ghostb, g, reinterpret_cast<double4 *>(c->arr.pos),
-                      reinterpret_cast<double4 *>(c->arr.vel), c->arr.tag, pt, vt, tt))
+                      reinterpret_cast<double4 *>(c->arr.vel), c->arr.tag, pt, vt, tt, bonded ? c->L.ptag : nullptr,
+                      bonded ? c->L.pdir : nullptr, c->L.prow, c->L.btmp))
         return HOOMD_E_DEVICE;
     if (S.n_local > 0) {
         HIP_OK(hipMemcpyAsync(reinterpret_cast<double4 *>(c->arr.pos) + S.row0, pt + S.row0,
@@ -960,6 +1065,13 @@ int migrate_particles(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, void
                               sizeof(double4) * S.n_local, hipMemcpyDeviceToDevice, c->stream));
         HIP_OK(hipMemcpyAsync(c->arr.tag + S.row0, tt + S.row0, sizeof(int32_t) * S.n_local,
                               hipMemcpyDeviceToDevice, c->stream));
+        if (bonded) {
+            const size_t st = (size_t)c->lay.bond_cap;
+            HIP_OK(hipMemcpyAsync(c->L.ptag + S.row0 * st, c->L.prow + S.row0 * st,
+                                  sizeof(int32_t) * st * S.n_local, hipMemcpyDeviceToDevice, c->stream));
+            HIP_OK(hipMemcpyAsync(c->L.pdir + S.row0 * st, c->L.btmp + S.row0 * st,
+                                  sizeof(int32_t) * st * S.n_local, hipMemcpyDeviceToDevice, c->stream));
+        }
     }
     // the counts decide the new local count: read them (migration happens at
     // neighbour-list builds only)
@@ -968,6 +1080,7 @@ int migrate_particles(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, void
     HIP_OK(hipStreamSynchronize(c->stream));
     if (cnt[0] + cnt[1] != S.n_local) return HOOMD_E_DEVICE;
     c->ghosts -= (int64_t)S.n_total - S.n_local;  // the ghost layer is invalid after a migration
+    c->bond_ok[sys] = 0;                          // and so are the partner rows
     S.n_local = cnt[1];
     S.n_total = cnt[1];
     c->box[sys].n_local = cnt[1];
@@ -983,7 +1096,6 @@ int receive_particles(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_rec
 {
     if (!c || sys < 0 || sys >= c->n_sys || n_recv < 0 || (n_recv > 0 && !recv) || !box_L) return HOOMD_E_ARG;
     SysDev &S = c->lay.sys[sys];
-    if (S.bond_cap > 0) return HOOMD_E_STATE;
     if (S.n_total != S.n_local) return HOOMD_E_STATE;  // ghosts are selected after the arrivals
     if (S.n_local + n_recv > c->box[sys].n_cap) return HOOMD_E_GHOST_OVERFLOW;
     if (n_recv == 0) return HOOMD_OK;
@@ -999,7 +1111,16 @@ int receive_particles(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_rec
     u.pos = reinterpret_cast<double4 *>(c->arr.pos);
     u.vel = reinterpret_cast<double4 *>(c->arr.vel);
     u.tag = c->arr.tag;
+    if (c->lay.bond_cap > 0) {
+        // records of a bonded context carry the partner entries (a system
+        // without bonds receives empty ones)
+        u.fields |= kFieldBonds;
+        u.ptag = c->L.ptag;
+        u.pdir = c->L.pdir;
+        u.bond_stride = c->lay.bond_cap;
+    }
     if (queue_ghost_unpack(c->stream, u)) return HOOMD_E_DEVICE;
+    c->bond_ok[sys] = 0;
     S.n_local += (int32_t)n_recv;
     S.n_total = S.n_local;
     c->box[sys].n_local = S.n_local;
@@ -1017,7 +1138,6 @@ int unpack_ghosts(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, u
     if (mode != HOOMD_GHOST_SELECT && mode != HOOMD_GHOST_UPDATE) return HOOMD_E_ARG;
     if ((fields & ~7u) || !(fields & HOOMD_FIELD_POS)) return HOOMD_E_ARG;
     SysDev &S = c->lay.sys[sys];
-    if (S.bond_cap > 0) return HOOMD_E_STATE;  // bonded ghosts are not supported
     if (mode == HOOMD_GHOST_UPDATE && n_recv != S.n_total - S.n_local) return HOOMD_E_STATE;
     if (S.n_local + n_recv > c->box[sys].n_cap) {
         return HOOMD_E_GHOST_OVERFLOW;
@@ -1041,8 +1161,11 @@ int unpack_ghosts(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_recv, u
         S.n_total = (int32_t)(S.n_local + n_recv);
         launch_set_counts(c->L, sys, S.n_local, S.n_total);  // queued, no host wait
         c->built = false;
+        // partners found among the locals and the new ghosts
+        if (S.bond_cap > 0) launch_bond_refresh(c->L, c->arr.tag, sys);
+        c->bond_ok[sys] = 1;
     }
-    return HOOMD_OK;
+    return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;
 }
 
 int hoomd_thermo(hoomd_ctx *c, double *out)
@@ -1138,7 +1261,7 @@ int hoomd_get_layout(hoomd_ctx *c, int32_t sys, hoomd_layout *out)
     out->general_tiles = c->L.slow_n;
     out->rare_tiles = c->L.rare_n;
     out->halo_lds = c->L.halo_lds;
-    out->pad_ = 0;
+    out->bond_stride = c->lay.bond_cap;
     out->n_local = S.n_local;
     out->n_total = S.n_total;
     return HOOMD_OK;
@@ -1377,6 +1500,7 @@ const char *hoomd_strerror(int code)
     case HOOMD_E_NAN: return "non-finite force";
     case HOOMD_E_DANGEROUS_BUILD: return "dangerous neighbour-list build";
     case HOOMD_E_HALO_OVERFLOW: return "tile halo capacity exceeded";
+    case HOOMD_E_BOND_GHOST: return "bond partner missing or beyond the neighbouring subdomains";
     default: return "unknown status";
     }
 }

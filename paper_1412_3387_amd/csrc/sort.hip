@@ -155,6 +155,20 @@ __global__ void k_gather_rows(int64_t rows, const int32_t *__restrict__ perm, co
     tag_o[k] = tag[o];
 }
 
+// The partner entries (tags and owner directions) move with their rows.
+__global__ void k_gather_bonds(int64_t rows, int stride, const int32_t *__restrict__ perm,
+                               const int32_t *__restrict__ ptag, const int32_t *__restrict__ pdir,
+                               int32_t *__restrict__ ptag_o, int32_t *__restrict__ pdir_o)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= rows) return;
+    const int64_t o = perm[k];
+    for (int s = 0; s < stride; ++s) {
+        ptag_o[k * stride + s] = ptag[o * stride + s];
+        pdir_o[k * stride + s] = pdir[o * stride + s];
+    }
+}
+
 // One workgroup of 1024 threads: each thread sums a contiguous chunk, the
 // chunk sums are scanned in LDS, then each thread writes its chunk.
 __global__ __launch_bounds__(1024) void k_scan_single(const int32_t *in, int32_t *out, int64_t n,
@@ -279,6 +293,14 @@ int queue_morton_sort(const LaunchCtx &L, const SortBuffers &B, double4 *pos, do
     if (hipMemcpyAsync(pos, pos_tmp, sizeof(double4) * B.rows, hipMemcpyDeviceToDevice, L.stream) != hipSuccess) return 1;
     if (hipMemcpyAsync(vel, vel_tmp, sizeof(double4) * B.rows, hipMemcpyDeviceToDevice, L.stream) != hipSuccess) return 1;
     if (hipMemcpyAsync(tag, B.tag_tmp, sizeof(int32_t) * B.rows, hipMemcpyDeviceToDevice, L.stream) != hipSuccess) return 1;
+    if (L.bond_stride > 0) {
+        // the partner-row table is rebuilt after the sort: it serves as scratch
+        const size_t nb = sizeof(int32_t) * (size_t)B.rows * (size_t)L.bond_stride;
+        hipLaunchKernelGGL(k_gather_bonds, dim3(blocks), dim3(256), 0, L.stream, B.rows, L.bond_stride, B.vals[cur],
+                           L.ptag, L.pdir, L.prow, L.btmp);
+        if (hipMemcpyAsync(L.ptag, L.prow, nb, hipMemcpyDeviceToDevice, L.stream) != hipSuccess) return 1;
+        if (hipMemcpyAsync(L.pdir, L.btmp, nb, hipMemcpyDeviceToDevice, L.stream) != hipSuccess) return 1;
+    }
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 

@@ -199,6 +199,37 @@ class Subdomains:
         return np.nonzero(self.owner == s)[0]
 
 
+def stretched_chains(n_side: int = 18, a: float = 1.1, seed_pos: int = 71, seed_vel: int = 72,
+                     T: float = 1.0, noise: float = 0.05) -> System:
+    """Chains whose bonds are longer than a WCA ghost layer: a simple cubic
+    lattice of n_side^3 sites (spacing a); the rows of sites run along x in
+    the layers of even z and along y in the others, and each row holds two
+    interleaved chains (its even and its odd sites), so consecutive beads of
+    a chain are 2a apart.  Seeded +-noise a displacement, Maxwell velocities
+    at T."""
+    assert n_side % 2 == 0
+    L = n_side * a
+    idx = np.arange(n_side ** 3)
+    ix, iy, iz = idx % n_side, (idx // n_side) % n_side, idx // (n_side * n_side)
+    rp = np.random.Generator(np.random.PCG64(seed_pos))
+    pos = np.stack([ix, iy, iz], axis=1) * a + rp.uniform(-noise * a, noise * a, (idx.size, 3))
+    Lv = np.array([L, L, L])
+    pos = wrap(pos, Lv)
+    along_x = iz % 2 == 0
+    # position of each site along its row, and the row it belongs to
+    u = np.where(along_x, ix, iy)
+    row = np.where(along_x, iy, ix) + n_side * iz
+    order = np.lexsort((u, u % 2, row))  # row, parity, place along the row
+    bonds = []
+    per_chain = n_side // 2
+    for c in range(idx.size // per_chain):
+        beads = order[c * per_chain:(c + 1) * per_chain]
+        bonds.extend(zip(beads[:-1], beads[1:]))
+    vel = maxwell_velocities(idx.size, T, seed_vel)
+    return System(pos=pos, vel=vel, tag=idx.astype(np.int32), L=Lv, bonds=np.array(bonds, dtype=np.int32),
+                  kind="polymer")
+
+
 def lj_subdomain_box(grid: int = 3, cells: int = 60, seed_pos: int = 11,
                      seed_vel: int = 12) -> Subdomains:
     """864,000-particle LJ box (fcc 60^3, lattice offset a/4, +-0.05 noise)

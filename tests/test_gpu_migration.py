@@ -6,7 +6,10 @@ ghost selection, else a ghost update; second half.  Checked against the
 oracle: every particle owned once, by the subdomain its position lies in,
 after each migration; the ghost set of subdomain 0 against brute force; the
 whole trajectory against the oracle's full-box run (FP64, LJ and DPD, the
-DPD ghosts carrying velocities and tags)."""
+DPD ghosts carrying velocities and tags).  Bonded chains whose bonds are
+longer than the ghost layer step the same way with the bond owner table of
+Sec. 4.3.4 kept by its messages (a start exchange, then one before every
+migration)."""
 import numpy as np
 import pytest
 
@@ -35,7 +38,7 @@ def _dir_to(s_from, s_to, g=3):
 class Loopback:
     """27 subdomains in one context; exchanges as device copies."""
 
-    def __init__(self, B, sd, params, width, margin, ghost_fields):
+    def __init__(self, B, sd, params, width, margin, ghost_fields, bonds=None):
         import torch
         self.B, self.sd, self.torch = B, sd, torch
         full = sd.full
@@ -46,17 +49,28 @@ class Loopback:
         systems = []
         for s in range(27):
             loc = sd.local(s)
-            systems.append(dict(pos=full.pos[loc], vel=full.vel[loc], tag=loc.astype(np.int32),
-                                L=np.full(3, frame), lo=sd.lo(s) - width - margin, periodic=(0, 0, 0),
-                                n_cap=int(1.4 * rho * frame ** 3) + 64))
+            d = dict(pos=full.pos[loc], vel=full.vel[loc], tag=loc.astype(np.int32),
+                     L=np.full(3, frame), lo=sd.lo(s) - width - margin, periodic=(0, 0, 0),
+                     n_cap=int(1.4 * rho * frame ** 3) + 64)
+            if bonds is not None:
+                # every bond with a member here (tags are the full box's)
+                d["bonds"] = bonds[np.isin(bonds[:, 0], loc) | np.isin(bonds[:, 1], loc)]
+            systems.append(d)
         self.ctx = B.Context([params] * 27, systems)
+        self.bonded = bonds is not None
         self.cap = int(8 * rho * sd.side ** 3) + 256  # up to seven destinations per particle
         self.gfields = ghost_fields
         self.grec = 8 * (3 * bool(ghost_fields & 1) + 3 * bool(ghost_fields & 2) + bool(ghost_fields & 4))
         dev = self.ctx.device
         mk = lambda n, dt: torch.zeros(n, dtype=dt, device=dev)
         self.gsend = [mk(self.cap * self.grec, torch.uint8) for _ in range(27)]
-        self.msend = [mk(self.cap * 56, torch.uint8) for _ in range(27)]
+        self.mrec = self.ctx.migrate_record_bytes()
+        self.msend = [mk(self.cap * self.mrec, torch.uint8) for _ in range(27)]
+        # owner-table messages: at the start every remote partner is announced
+        # to all 26 neighbours
+        self.bcap = 26 * 2 * self.cap
+        self.bsend = [mk(self.bcap * B.BOND_RECORD_BYTES, torch.uint8) for _ in range(27)] if self.bonded else []
+        self.bond_messages = 0
         self.cnt = [mk(26, torch.int32) for _ in range(27)]
         self.off = [mk(26, torch.int32) for _ in range(27)]
         self.n_recv = [0] * 27
@@ -96,14 +110,32 @@ class Loopback:
             recv = self._gather(self.gsend, self.grec, s)
             self.ctx.unpack_ghosts(s, recv, self.n_recv[s], self.gfields, B.GHOST_UPDATE, self.L)
 
+    def bond_ranks(self, mode):
+        """Owner-table messages of every subdomain, moved, then applied."""
+        sd, rec = self.sd, self.B.BOND_RECORD_BYTES
+        for s in range(27):
+            self.bond_messages += self.ctx.pack_bond_ranks(s, sd.lo(s), sd.hi(s), mode, self.bsend[s], self.bcap,
+                                                           self.cnt[s], self.off[s])
+        for s in range(27):
+            recv = self._gather(self.bsend, rec, s)
+            self.ctx.unpack_bond_ranks(s, recv, recv.numel() // rec, mode)
+        self.ctx.check()
+
+    def start(self):
+        if self.bonded:
+            self.bond_ranks(self.B.BOND_START)
+        self.select_ghosts()
+
     def migrate(self):
         sd = self.sd
+        if self.bonded:
+            self.bond_ranks(self.B.BOND_MIGRATE)
         for s in range(27):
             self.moved += self.ctx.migrate_particles(s, sd.lo(s), sd.hi(s), self.msend[s], self.cap,
                                                      self.cnt[s], self.off[s])
         for s in range(27):
-            recv = self._gather(self.msend, 56, s)
-            self.ctx.receive_particles(s, recv, recv.numel() // 56, self.L)
+            recv = self._gather(self.msend, self.mrec, s)
+            self.ctx.receive_particles(s, recv, recv.numel() // self.mrec, self.L)
         self.ctx.check()
         self.migrations += 1
 
@@ -143,7 +175,7 @@ class Loopback:
 
 def _run(orc, B, sd, params, width, margin, fields, model, prm, dt, steps, t0=0):
     lb = Loopback(B, sd, params, width, margin, fields)
-    lb.select_ghosts()
+    lb.start()
     lb.ctx.compute_forces(t0, 0)
     for k in range(steps):
         lb.step(t0 + k)
@@ -209,3 +241,68 @@ def test_dpd_subdomains_step_with_migration(orc, B):
                             0.02, 12, t0=40)
     assert np.max(np.abs(min_image_diff(x, xo, d.L))) <= 1e-10
     assert np.max(np.abs(v - vo)) <= 1e-10
+
+
+def _chain_box():
+    """The stretched chains (bonds of about 2.2) cut 3 x 3 x 3."""
+    full = inputs.stretched_chains()
+    side = float(full.L[0]) / 3
+    c = np.clip(np.floor(full.pos / side).astype(np.int64), 0, 2)
+    owner = (c[:, 0] + 3 * (c[:, 1] + 3 * c[:, 2])).astype(np.int32)
+    return inputs.Subdomains(full=full, grid=3, side=side, owner=owner)
+
+
+CHAIN = dict(pair=1, bond_cap=2, fene_K=5.0, fene_R0=3.0, r_buff=0.2, dt=0.002)
+
+
+def test_bonded_subdomains_step_with_migration(orc, B):
+    """Chains whose bonds (about 2.2) are longer than the ghost layer
+    (WCA cut-off + buffer = 1.32): a bond's partner across a face reaches
+    its subdomain only as a ghost sent by the owner table.  60 FP64 steps with
+    migrations of bonded particles match the oracle's full-box run (WCA on
+    all pairs + FENE); subdomain 0 holds, beside the layer's ghosts, ghosts
+    that are there only as partners of its particles."""
+    sd = _chain_box()
+    full = sd.full
+    p = B.ModelParams(precision=B.FP64, **CHAIN)
+    width = 2 ** (1 / 6) + 0.2
+    lb = Loopback(B, sd, p, width, 1.5, B.FIELD_POS | B.FIELD_TAG, bonds=full.bonds)
+    lb.start()
+    start_messages = lb.bond_messages
+    lb.ctx.compute_forces(0, 0)
+    lb.ctx.check()
+    for k in range(60):
+        lb.step(k)
+    lb.ctx.check()
+    assert start_messages > 0 and lb.bond_messages > start_messages
+    assert lb.migrations >= 2 and lb.moved > 0
+    x, v, owner = lb.state()
+    xo, vo, Fo, th, st = orc.run_nve("polymer", full.pos, full.vel, full.L, [1.0, 1.0], CHAIN["dt"], 60,
+                                     bonds=full.bonds, bond_prm=(CHAIN["fene_K"], CHAIN["fene_R0"]))
+    assert st == 0
+    assert np.max(np.abs(min_image_diff(x, xo, full.L))) <= 1e-10
+    assert np.max(np.abs(v - vo)) <= 1e-10
+    # bonds split between subdomains, and ghosts that only the bonds bring
+    a, b = full.bonds[:, 0], full.bonds[:, 1]
+    assert np.count_nonzero(owner[a] != owner[b]) > 100
+    ctx = lb.ctx
+    o, n0 = ctx.offsets[0], ctx.n_local[0]
+    gtag = ctx.tag[o + n0:o + n0 + lb.n_recv[0]].cpu().numpy()
+    ridx, rimg = orc.ghost_receive(x, owner, 0, full.L, sd.lo(0), sd.hi(0), width)
+    extra = np.setdiff1d(gtag, ridx)
+    assert np.all(np.isin(ridx, gtag)) and extra.size > 0
+    mine = np.nonzero(owner == 0)[0]
+    partners = np.union1d(b[np.isin(a, mine)], a[np.isin(b, mine)])
+    assert np.all(np.isin(extra, partners))
+
+
+def test_bonded_subdomains_without_the_owner_table_report_it(B):
+    """Skipping the start exchange leaves partners across faces of unknown
+    owner: they never arrive, and the force pass reports a missing partner
+    (status 12) instead of reading a wrong row."""
+    sd = _chain_box()
+    p = B.ModelParams(precision=B.FP64, **CHAIN)
+    lb = Loopback(B, sd, p, 2 ** (1 / 6) + 0.2, 1.5, B.FIELD_POS | B.FIELD_TAG, bonds=sd.full.bonds)
+    lb.select_ghosts()
+    lb.ctx.compute_forces(0, 0)
+    assert lb.ctx.sync_status()[0] == 12
