@@ -152,9 +152,27 @@ def other_workload(B, torch, label, params, systems, steps, warmup, t0=0):
     ctx.check()
     ms = e0.elapsed_time(e1)
     n = sum(int(sy["pos"].shape[0]) for sy in systems)
+    builds = ctx.build_count() - b0
+    # eager profiled window: HIP events around every force launch and rebuild
+    ps = max(20, steps // 5)
+    ctx.profile(1)
+    ctx.step(t0 + warmup + steps, ps)
+    torch.cuda.synchronize()
+    prof = ctx.profile(2)
+    ctx.profile(0)
+    ctx.check()
+    rows = sum(int(ctx._ws_view(ctx.layout(k).nn, ctx.n_local[k]).double().sum().item())
+               for k in range(len(systems)))
+    nbar = rows / n
+    force_us = 1e3 * prof.force_ms / max(prof.force_launches, 1)
+    alg = n * (4 * nbar + 124)  # the headline's per-particle bytes of the fused force pass
     out = {"workload": label, "value": n * steps / (ms / 1e3), "unit": "particle-timesteps/s",
            "steps_per_s": steps / (ms / 1e3), "particles": n, "systems": len(systems), "steps": steps,
-           "rebuilds": ctx.build_count() - b0, "precision": "mixed", "tuning": _tuning_dict(tuning)}
+           "rebuilds": builds, "precision": "mixed", "tuning": _tuning_dict(tuning),
+           "profiled_window": {"steps": ps, "force_us_per_step": force_us,
+                               "rebuild_ms_per_build": prof.rebuild_ms / max(ctx.build_count() - b0 - builds, 1),
+                               "mean_row": nbar, "force_alg_GBps": alg / (force_us * 1e-6) / 1e9,
+                               "force_frac_of_hbm": alg / (force_us * 1e-6) / 8e12}}
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
