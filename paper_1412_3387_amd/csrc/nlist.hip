@@ -929,6 +929,12 @@ __device__ __forceinline__ void plan_tiles(
             frel[a] = (float)(xa[a] - S.lo[a]) - (float)ci * cw[a];
         }
         plan.xrow[(int64_t)tile * kTile + lane] = make_float4(xf[0], xf[1], xf[2], 0.f);
+        // spread of the rows around row 0 per axis (xf is relative to it;
+        // non-negative floats order as their bit patterns)
+        float spread[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            spread[a] = __int_as_float(wave_max_full(act ? __float_as_int(fabsf(xf[a])) : 0));
 
         // ---- frame box and the stencil-cell bitmap ----------------------------
         int blo[3], X[3];
@@ -1080,9 +1086,20 @@ __device__ __forceinline__ void plan_tiles(
             plan.run[pr + rr] = v;
             plan.hw[pr + rr] = hwv;
         }
+        // One image per halo entry (the one nearest row 0, taken by the force
+        // pass at every step) is every row's minimum image while, per
+        // periodic axis, spread + r_list + 2 r_buff < L/2: until the next
+        // build each particle moves at most r_buff/2, so a row stays within
+        // spread + r_buff of row 0 and a listed pair within r_list + r_buff,
+        // and the partner image nearest the row is within L/2 of row 0 (the
+        // rows' FP32 offsets get a margin of 1e-5 L).  Otherwise the force
+        // pass takes the minimum image per pair.
         int pp = 0;
-        for (int a = 0; a < 3; ++a)
-            if (per[a] && (double)(ehi[a] - elo[a] + 3) * (Ls[a] / bins[a]) >= 0.5 * Ls[a]) pp = 1;
+        {
+            const double rlist = sqrt(rl2), rbuff = 2.0 * sqrt(S.disp2);
+            for (int a = 0; a < 3; ++a)
+                if (per[a] && (double)spread[a] + rlist + 2.0 * rbuff + 1e-5 * Ls[a] >= 0.5 * Ls[a]) pp = 1;
+        }
         // relative band around r_list^2 inside which the FP32 distance of a
         // candidate cannot decide the test: a bound on the FP32 rounding of
         // frame coordinates up to E in magnitude (cell-relative position,
