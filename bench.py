@@ -337,9 +337,10 @@ def other_workloads(B, inputs, torch, steps, warmup):
         res["dpd_1M"] = {"error": repr(e)}
     try:
         batch = inputs.batch_ensemble()
-        params = [B.ModelParams(precision=B.MIXED, pair=B.PAIR_LJ, tpp_force=4, sort_period=500)
+        # launch shapes of the whole batch chosen by the autotuner
+        params = [B.ModelParams(precision=B.MIXED, pair=B.PAIR_LJ, sort_period=500)
                   if sy.kind == "lj" else
-                  B.ModelParams(precision=B.MIXED, pair=B.PAIR_WCA, bond_cap=2, tpp_force=4, sort_period=500)
+                  B.ModelParams(precision=B.MIXED, pair=B.PAIR_WCA, bond_cap=2, sort_period=500)
                   for sy in batch]
         systems = [dict(pos=sy.pos, vel=sy.vel, L=sy.L, bonds=sy.bonds, tag=sy.tag) for sy in batch]
         res["batch_256"] = other_workload(B, torch, "batch_256", params, systems, steps, warmup)

@@ -362,7 +362,10 @@ int unpack_ghosts(hoomd_ctx *ctx, int32_t sys, const void *recv, int64_t n_recv,
  * Call pack_bond_ranks() in every subdomain, move the messages, then
  * unpack_bond_ranks() in every subdomain, before any particle moves.
  * pack_bond_ranks() synchronises; both return HOOMD_E_STATE for a system
- * without bonds or after its rows changed without a ghost selection. */
+ * without bonds or after its rows changed without a ghost selection.  As
+ * for ghosts, the 26 neighbours of a subdomain must be distinct (three or
+ * more subdomains along every split axis), so that a particle has one copy
+ * per subdomain. */
 enum { HOOMD_BOND_START = 0, HOOMD_BOND_MIGRATE = 1 };
 int pack_bond_ranks(hoomd_ctx *ctx, int32_t sys, const hoomd_subdomain *subdomain, int32_t mode, void *send,
                     int64_t send_cap, int32_t *counts26, int32_t *offsets26, int64_t *n_sent);
