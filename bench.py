@@ -101,7 +101,9 @@ def run_precision(B, inputs, torch, s, prec, steps, warmup, tune, fixed=None, pr
 
 def force_check(B, torch, s):
     """Mixed-precision forces against the FP64 path on the starting
-    configuration: max over particles of |F_mixed - F_fp64| / F_rms."""
+    configuration: max over particles of |F_mixed - F_fp64| / F_rms.  Also
+    returns both paths' forces (tag order) for the comparison with the
+    oracle on the particles the CPU baseline computes."""
     import numpy as np
     out = {}
     for prec in (B.FP64, B.MIXED):
@@ -121,7 +123,7 @@ def force_check(B, torch, s):
     ref = out[B.FP64]
     frms = float(np.sqrt(np.mean(ref ** 2)))
     err = float(np.max(np.linalg.norm(out[B.MIXED] - ref, axis=1))) / frms
-    return {"max_err_over_Frms": err, "tolerance": 1e-5, "pass": err <= 1e-5, "F_rms": frms}
+    return {"max_err_over_Frms": err, "tolerance": 1e-5, "pass": err <= 1e-5, "F_rms": frms}, out
 
 
 def _tuning_dict(t):
@@ -454,7 +456,7 @@ def cpu_baseline(s, seconds):
     while True:
         which = np.sort(rng.choice(s.n, m, replace=False))
         t0 = time.perf_counter()
-        oracle.pair_forces("lj", s.pos, s.L, lj, which=which)
+        F_orc = oracle.pair_forces("lj", s.pos, s.L, lj, which=which)[0]
         t = time.perf_counter() - t0
         # the last, timed sample aims at `seconds` of CPU work (stops past
         # two thirds of it)
@@ -475,7 +477,7 @@ def cpu_baseline(s, seconds):
             "cpu_model": model, "host_logical_cpus": os.cpu_count(),
             "sample": (f"FP64 brute-force forces of {m} random particles against all {s.n} "
                        f"(O(N) each, minimum image), {t:.1f} s; the integration is negligible "
-                       f"beside it")}
+                       f"beside it")}, (which, F_orc)
 
 
 def main():
@@ -605,13 +607,20 @@ def main():
                         "tuning": fp64["tuning"],
                         "force_avg_us": fp64["prof"].force_ms / max(fp64["prof"].force_launches, 1) * 1e3}
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
-    line["force_check"] = force_check(B, torch, s)
+    line["force_check"], gpu_forces = force_check(B, torch, s)
     if not args.no_others:
         print("[bench] other workloads", file=sys.stderr, flush=True)
         line["others"] = other_workloads(B, inputs, torch, args.other_steps, 100)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+        line["cpu_baseline"], (which, F_orc) = cpu_baseline(s, args.cpu_seconds)
+        # both GPU paths against the oracle on the particles it computed
+        import numpy as np
+        frms = float(np.sqrt(np.mean(np.sum(F_orc ** 2, axis=1))))
+        line["force_check"]["vs_oracle"] = {
+            name: float(np.max(np.linalg.norm(gpu_forces[prec][which] - F_orc, axis=1))) / frms
+            for name, prec in (("fp64", B.FP64), ("mixed", B.MIXED))}
+        line["force_check"]["vs_oracle"]["particles"] = int(len(which))
     print(json.dumps(line), flush=True)
 
 
