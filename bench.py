@@ -319,53 +319,54 @@ def subdomain_phases(B, inputs, torch, reps=200):
     return out
 
 
-def other_workloads(B, inputs, torch, steps, warmup):
+def other_workloads(B, inputs, torch, steps, warmup, only=None):
     """DPD fluid (N = 1,000,000, density 3, r_cut 1, A 25, gamma 4.5, kT 1,
     dt 0.02), the batched ensemble (128 LJ liquids of 500..20,000 particles
     and 128 bead-spring melts of 20..400 chains of 50, FENE + WCA), each in
     one context, the 32,000-particle NVT share of the weak-scaling fluid,
-    and the per-phase times of the strong-scaling subdomain."""
-    res = {}
-    try:
+    and the per-phase times of the strong-scaling subdomain (`only`: one of
+    them, by key).  A failing workload is reported, not fatal: the headline
+    line still prints."""
+
+    def dpd():
         # DPD particles diffuse fast (dt = 0.02): a Morton sort every 100
         # steps keeps the tiles compact (every 500 lets halos outgrow the
         # per-tile list before the next sort)
         d = inputs.dpd_bulk()
         p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=33,
                           sort_period=100)
-        res["dpd_1M"] = other_workload(B, torch, "dpd_1M", [p], [dict(pos=d.pos, vel=d.vel, L=d.L)],
-                                       steps, warmup)
-    except Exception as e:  # reported, not fatal: the headline line still prints
-        res["dpd_1M"] = {"error": repr(e)}
-    try:
-        batch = inputs.batch_ensemble()
+        return other_workload(B, torch, "dpd_1M", [p], [dict(pos=d.pos, vel=d.vel, L=d.L)], steps, warmup)
+
+    def batch():
+        ens = inputs.batch_ensemble()
         # launch shapes of the whole batch chosen by the autotuner
         params = [B.ModelParams(precision=B.MIXED, pair=B.PAIR_LJ, sort_period=500)
                   if sy.kind == "lj" else
                   B.ModelParams(precision=B.MIXED, pair=B.PAIR_WCA, bond_cap=2, sort_period=500)
-                  for sy in batch]
-        systems = [dict(pos=sy.pos, vel=sy.vel, L=sy.L, bonds=sy.bonds, tag=sy.tag) for sy in batch]
-        res["batch_256"] = other_workload(B, torch, "batch_256", params, systems, steps, warmup)
-        res["batch_256"]["per_system_launches"] = batch_per_system(B, torch, params, systems,
-                                                                   max(steps // 5, 20), warmup)
-        res["batch_256"]["batched_over_per_system"] = (res["batch_256"]["value"] /
-                                                       res["batch_256"]["per_system_launches"]["value"])
-    except Exception as e:
-        res["batch_256"] = {"error": repr(e)}
-    try:
+                  for sy in ens]
+        systems = [dict(pos=sy.pos, vel=sy.vel, L=sy.L, bonds=sy.bonds, tag=sy.tag) for sy in ens]
+        r = other_workload(B, torch, "batch_256", params, systems, steps, warmup)
+        r["per_system_launches"] = batch_per_system(B, torch, params, systems, max(steps // 5, 20), warmup)
+        r["batched_over_per_system"] = r["value"] / r["per_system_launches"]["value"]
+        return r
+
+    def nvt():
         # one GPU's share of the weak-scaling runs: NVT (Nose-Hoover), packing
         # fraction 0.2, r_cut 3.0, dt 0.002
         w = inputs.lj_weak_share()
         p = B.ModelParams(precision=B.MIXED, r_cut=3.0, r_buff=0.4, dt=0.002, sort_period=500,
                           integrator=B.NVT, nvt_T0=1.2, nvt_tau=0.5)
-        res["lj_nvt_32k"] = other_workload(B, torch, "lj_nvt_32k", [p], [dict(pos=w.pos, vel=w.vel, L=w.L)],
-                                           steps, warmup)
-    except Exception as e:
-        res["lj_nvt_32k"] = {"error": repr(e)}
-    try:
-        res["subdomain_32k"] = subdomain_phases(B, inputs, torch)
-    except Exception as e:
-        res["subdomain_32k"] = {"error": repr(e)}
+        return other_workload(B, torch, "lj_nvt_32k", [p], [dict(pos=w.pos, vel=w.vel, L=w.L)], steps, warmup)
+
+    res = {}
+    for key, fn in (("dpd_1M", dpd), ("batch_256", batch), ("lj_nvt_32k", nvt),
+                    ("subdomain_32k", lambda: subdomain_phases(B, inputs, torch))):
+        if only is not None and only != key:
+            continue
+        try:
+            res[key] = fn()
+        except Exception as e:
+            res[key] = {"error": repr(e)}
     return res
 
 
@@ -493,6 +494,9 @@ def main():
     ap.add_argument("--no-others", action="store_true",
                     help="skip the secondary workloads (DPD 1M, 256-system batch)")
     ap.add_argument("--other-steps", type=int, default=1000)
+    ap.add_argument("--others-only", default=None,
+                    choices=["dpd_1M", "batch_256", "lj_nvt_32k", "subdomain_32k"],
+                    help="run one secondary workload, print its JSON line and exit (for profiling)")
     ap.add_argument("--tuning-out", default=None,
                     help="write the lanes/block sizes chosen per precision to this JSON file")
     ap.add_argument("--tuning-from", default=None,
@@ -522,6 +526,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     B.lib()
+    if args.others_only:
+        print(json.dumps(other_workloads(B, inputs, torch, args.other_steps, 100, args.others_only)), flush=True)
+        return
     s = inputs.lj_bulk(args.n)
     print(f"[bench] N={s.n} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     fixed = {}
