@@ -329,12 +329,14 @@ def other_workloads(B, inputs, torch, steps, warmup, only=None):
     line still prints."""
 
     def dpd():
-        # DPD particles diffuse fast (dt = 0.02): a Morton sort every 100
-        # steps keeps the tiles compact (every 500 lets halos outgrow the
-        # per-tile list before the next sort)
+        # DPD particles diffuse fast (dt = 0.02): a Morton sort every 10 steps
+        # keeps the tiles compact (measured: 1.77e9 particle-steps/s, against
+        # 1.73e9 every 25, 1.68e9 every 50, 1.16e9 every 100, where tiles
+        # outgrow the framed build and the force pass's LDS stage; every 5
+        # forces extra rebuilds between the ones due every second step)
         d = inputs.dpd_bulk()
         p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=33,
-                          sort_period=100)
+                          sort_period=10)
         return other_workload(B, torch, "dpd_1M", [p], [dict(pos=d.pos, vel=d.vel, L=d.L)], steps, warmup)
 
     def batch():
@@ -389,7 +391,7 @@ def pmc_pass(B, inputs, torch, s, fixed, steps, workload="lj"):
     if workload == "dpd":
         s = inputs.dpd_bulk()
         p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=33,
-                          sort_period=100, use_graph=0, **kw)
+                          sort_period=10, use_graph=0, **kw)
     else:
         p = B.ModelParams(precision=B.MIXED, pair=B.PAIR_LJ, r_cut=2.5, r_buff=0.4, dt=0.005,
                           sort_period=500, use_graph=0, **kw)
