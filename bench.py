@@ -347,8 +347,9 @@ def other_workloads(B, inputs, torch, steps, warmup, only=None):
                   for sy in ens]
         systems = [dict(pos=sy.pos, vel=sy.vel, L=sy.L, bonds=sy.bonds, tag=sy.tag) for sy in ens]
         r = other_workload(B, torch, "batch_256", params, systems, steps, warmup)
-        r["per_system_launches"] = batch_per_system(B, torch, params, systems, max(steps // 5, 20), warmup)
-        r["batched_over_per_system"] = r["value"] / r["per_system_launches"]["value"]
+        if only is None:  # (a profiling run of the batch alone leaves the comparison out)
+            r["per_system_launches"] = batch_per_system(B, torch, params, systems, max(steps // 5, 20), warmup)
+            r["batched_over_per_system"] = r["value"] / r["per_system_launches"]["value"]
         return r
 
     def nvt():
@@ -497,7 +498,8 @@ def main():
     ap.add_argument("--other-steps", type=int, default=1000)
     ap.add_argument("--others-only", default=None,
                     choices=["dpd_1M", "batch_256", "lj_nvt_32k", "subdomain_32k"],
-                    help="run one secondary workload, print its JSON line and exit (for profiling)")
+                    help="run one secondary workload (the batch without its per-system comparison), "
+                         "print its JSON line and exit (for profiling)")
     ap.add_argument("--tuning-out", default=None,
                     help="write the lanes/block sizes chosen per precision to this JSON file")
     ap.add_argument("--tuning-from", default=None,
