@@ -169,10 +169,13 @@ typedef struct {
     double L[3];
     int32_t periodic[3];
     int32_t pad_;
-    int64_t n_local;       /* particles integrated and given forces          */
+    int64_t n_local;       /* particles integrated and given forces (>= 0)   */
     int64_t n_cap;         /* rows available (locals + room for ghosts)      */
     int64_t n_bonds;       /* entries in the bond table                      */
 } hoomd_box;
+/* A system may be empty (n_local = 0, with or without rows): it takes no
+ * part in any launch and reports zero energies.  A context needs at least one
+ * row over all its systems (HOOMD_E_ARG otherwise). */
 
 /* Device arrays of one context (see the layout above).  bonds: int32[n_bonds]
  * [2] pairs of tags (unordered), or NULL.  When n_sys > 1 the arrays of all

@@ -62,6 +62,11 @@ int cell_bins(double L, double rl)
 bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
 {
     if (!p || !boxes || n_sys < 1) return false;
+    // systems may be empty (no rows, or rows that hold no particle yet), but
+    // a context has at least one row
+    int64_t rows = 0;
+    for (int s = 0; s < n_sys; ++s) rows += boxes[s].n_cap > 0 ? boxes[s].n_cap : 0;
+    if (rows == 0) return false;
     for (int s = 0; s < n_sys; ++s) {
         const hoomd_params &q = p[s];
         const hoomd_box &b = boxes[s];

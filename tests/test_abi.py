@@ -63,6 +63,25 @@ def test_strerror_and_workspace_sizing(hlib):
     assert hlib.hoomd_workspace_bytes(C.byref(p), 1, C.byref(box)) == 0
 
 
+def test_empty_systems_are_accepted_beside_others_but_not_alone(hlib):
+    """A system with no particles (with or without rows) may sit in a batch;
+    a context without a single row is rejected."""
+    from paper_1412_3387_amd import binding as B
+    ps = (B.Params * 3)(*[B.ModelParams(precision=B.MIXED).to_c(0.8442) for _ in range(3)])
+    boxes = (B.Box * 3)()
+    for b in boxes:
+        for a in range(3):
+            b.L[a] = 16.796
+            b.periodic[a] = 1
+    boxes[1].n_local = boxes[1].n_cap = 4000
+    boxes[2].n_cap = 100
+    assert hlib.hoomd_workspace_bytes(ps, 3, boxes) > 0
+    boxes[1].n_local = boxes[1].n_cap = 0
+    boxes[2].n_cap = 0
+    assert hlib.hoomd_workspace_bytes(ps, 3, boxes) == 0
+    assert hlib.hoomd_workspace_bytes(ps, 1, boxes) == 0
+
+
 def test_init_rejects_bad_arguments_without_device_work(hlib):
     from paper_1412_3387_amd import binding as B
     p = B.ModelParams(precision=B.MIXED).to_c(0.8442)

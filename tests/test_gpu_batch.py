@@ -90,3 +90,39 @@ def test_batch_short_run_fp64(orc, B):
         x, v = by_tag(tag, x, v)
         assert np.max(np.abs(min_image_diff(x, xo, sy.L))) <= 1e-10
         assert np.max(np.abs(v - vo)) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_with_empty_and_one_particle_systems(B, prec):
+    """Degenerate systems beside a 900-particle liquid: one without rows, one
+    with 100 rows and no particle, and a lone particle in a periodic box.  The
+    liquid evolves bit for bit as it does alone, the lone particle feels no
+    force and moves in a straight line across the periodic boundary, and the
+    empty systems report zero energies and temperature."""
+    lj = inputs.lj_fluid(900, 51, 52)
+    L = np.array([10.0, 10.0, 10.0])
+    x1 = np.array([[9.9, 0.05, 5.0]])
+    v1 = np.array([[0.7, -0.45, 0.3]])
+    empty = dict(pos=np.zeros((0, 3)), vel=np.zeros((0, 3)), L=L)
+    systems = [dict(pos=lj.pos, vel=lj.vel, L=lj.L), dict(empty), dict(empty, n_cap=100),
+               dict(pos=x1, vel=v1, L=L)]
+    p = B.ModelParams(precision=prec, sort_period=20)
+    batch = B.Context([p] * 4, systems)
+    print(f"[case] empty and one-particle systems, precision {prec}", flush=True)
+    batch.step(0, 60, log_every=10)
+    batch.check()
+    one = B.Context([p], systems[:1])
+    one.step(0, 60, log_every=10)
+    one.check()
+    for u, w in zip(batch.host_state(0), one.host_state(0)):
+        assert np.array_equal(u, w)
+    assert all(a.shape[0] == 0 for a in batch.host_state(1)) and all(a.shape[0] == 0 for a in batch.host_state(2))
+    x, v, f, tag = batch.host_state(3)
+    assert np.array_equal(v, v1) and np.all(f == 0) and tag[0] == 0
+    # 60 steps of 0.005 along v, folded into [0, L): x crosses the boundary at 0
+    assert np.max(np.abs(min_image_diff(x, x1 + 0.3 * v1, L))) <= 1e-12
+    assert np.all((x >= 0) & (x < L)) and x[0, 0] < 1.0
+    log = batch.thermo_log()
+    assert np.all(log[:, 1:3, 1:] == 0)
+    assert np.allclose(log[:, 3, 1], 0.5 * np.sum(v1 ** 2), rtol=1e-14) and np.all(log[:, 3, 2:] == 0)
+    assert np.array_equal(log[:, 0, :], one.thermo_log()[:, 0, :])
