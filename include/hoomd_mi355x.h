@@ -147,7 +147,20 @@ typedef struct {
                               nvt_tau required)                              */
     double nvt_T0;         /* NVT: set temperature (> 0)                     */
     double nvt_tau;        /* NVT: coupling time (> 0)                       */
+    int32_t force_launch;  /* force pass (equal in all systems):
+                              HOOMD_FORCE_AUTO, _SPLIT or _ONE               */
+    int32_t pad_;
 } hoomd_params;
+
+/* Launches of the force pass.  SPLIT: a launch over the tiles whose halo fits
+ * the LDS stage of a workgroup sized for full occupancy, then a small launch
+ * over the rest (tiles that need per-pair images, or larger halos).  ONE: a
+ * single launch of the second kind over every tile: no occupancy budget, but
+ * one launch latency per pass instead of two.  AUTO: ONE when every
+ * workgroup of that launch is resident at once (a context of few tiles: a
+ * small system, a subdomain), else SPLIT.  The results are the same bit for
+ * bit. */
+enum { HOOMD_FORCE_AUTO = 0, HOOMD_FORCE_SPLIT = 1, HOOMD_FORCE_ONE = 2 };
 
 /* Integrators (Sec. 3: NVE by velocity Verlet; Sec. 6.1: the weak-scaling LJ
  * runs use a Nose-Hoover thermostat that is not fully symplectic and takes

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libhoomd_mi355x.so")
 FP64, MIXED = 0, 1
 PAIR_LJ, PAIR_WCA, PAIR_DPD = 0, 1, 2
 NVE, NVT = 0, 1
+FORCE_AUTO, FORCE_SPLIT, FORCE_ONE = 0, 1, 2
 ENERGY, VIRIAL = 1, 2
 GHOST_SELECT, GHOST_UPDATE = 0, 1
 FIELD_POS, FIELD_VEL, FIELD_TAG = 1, 2, 4
@@ -48,7 +49,7 @@ class Params(C.Structure):
                 ("tpp_nlist", C.c_int32), ("tpp_force", C.c_int32), ("block_nlist", C.c_int32),
                 ("block_force", C.c_int32), ("use_graph", C.c_int32), ("tune_period", C.c_int32),
                 ("integrator", C.c_int32), ("nvt_group", C.c_int32), ("nvt_T0", C.c_double),
-                ("nvt_tau", C.c_double)]
+                ("nvt_tau", C.c_double), ("force_launch", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Box(C.Structure):
@@ -185,6 +186,8 @@ class ModelParams:
     nvt_group: int = 0
     nvt_T0: float = 1.0
     nvt_tau: float = 1.0
+    force_launch: int = 0
+    pad_: int = 0
 
     def list_radius(self) -> float:
         rc = 2.0 ** (1.0 / 6.0) * self.sigma if self.pair == PAIR_WCA else self.r_cut

@@ -502,14 +502,19 @@ __global__ __launch_bounds__(1024) void k_force(FORCE_ARGS)
 }
 
 // The tiles the last build listed as rare (per-pair images or a halo larger
-// than the staging area).
+// than the staging area), or, without a list, every local tile (the whole
+// pass in one launch).
 template <int W, bool MIXED, int POT, bool LOG>
 __global__ __launch_bounds__(1024) void k_force_rare(FORCE_ARGS)
 {
     extern __shared__ double lds[];
-    const int cnt = *rare_n;
+    if (!rare_list && a.flag_clear && blockIdx.x == 0) {
+        if (threadIdx.x == 0) *a.flag_clear = 0;
+        for (int q = threadIdx.x; q < n_sys; q += blockDim.x) a.sflag_clear[q] = 0;
+    }
+    const int cnt = rare_list ? *rare_n : tprefix[n_sys];
     for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
-        force_tile<W, MIXED, POT, LOG, true>(rare_list[k], lds, FORCE_PASS);
+        force_tile<W, MIXED, POT, LOG, true>(rare_list ? rare_list[k] : k, lds, FORCE_PASS);
         __syncthreads();
     }
 }
@@ -763,11 +768,6 @@ template <int W, bool MIXED, int POT, bool LOG>
 static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
 {
     if (L.tiles_local == 0) return;
-    const size_t lds = force_lds_bytes(POT, L.halo_lds, L.nlist_cap);
-    hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(L.tiles_local), dim3(W * kWave), lds, L.stream,
-                       L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
-                       L.halo_cap, L.halo_lds, L.prow, L.xbuild, L.partials, L.status,
-                       L.rare_list, L.rare_n, F);
     // the launch over rare tiles runs few workgroups: it stages up to the
     // whole halo list (at most kRareLds bytes), so that oversized halos are
     // read from LDS too
@@ -776,6 +776,29 @@ static void force_inst(const LaunchCtx &L, const ForceLaunch &F)
     rare_lds_entries = rare_lds_entries < L.halo_cap ? rare_lds_entries : L.halo_cap;
     rare_lds_entries = rare_lds_entries > L.halo_lds ? rare_lds_entries : L.halo_lds;
     const size_t rare_lds = force_lds_bytes(POT, rare_lds_entries, L.nlist_cap);
+    // One launch of the second kind over every tile when the workgroups of
+    // all tiles that hold local rows are resident at once: at most 16 waves
+    // per CU (it takes up to 128 VGPRs) and as many workgroups as the CU's
+    // 160 KB of LDS holds
+    bool one = L.force_launch == kForceOne;
+    if (L.force_launch == kForceAuto) {
+        const int by_waves = 16 / W > 0 ? 16 / W : 1;
+        const int by_lds = (int)((size_t)163840 / (rare_lds > 0 ? rare_lds : 1));
+        const int per_cu = by_waves < by_lds ? by_waves : by_lds;
+        one = L.busy_tiles <= 256 * per_cu;
+    }
+    if (one) {
+        hipLaunchKernelGGL((k_force_rare<W, MIXED, POT, LOG>), dim3(rb), dim3(W * kWave), rare_lds, L.stream,
+                           L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
+                           L.halo_cap, rare_lds_entries, L.prow, L.xbuild, L.partials, L.status,
+                           (const int32_t *)nullptr, (const int32_t *)nullptr, F);
+        return;
+    }
+    const size_t lds = force_lds_bytes(POT, L.halo_lds, L.nlist_cap);
+    hipLaunchKernelGGL((k_force<W, MIXED, POT, LOG>), dim3(L.tiles_local), dim3(W * kWave), lds, L.stream,
+                       L.sys, L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n,
+                       L.halo_cap, L.halo_lds, L.prow, L.xbuild, L.partials, L.status,
+                       L.rare_list, L.rare_n, F);
     hipLaunchKernelGGL((k_force_rare<W, MIXED, POT, LOG>), dim3(rb), dim3(W * kWave), rare_lds, L.stream, L.sys,
                        L.tprefix_local, L.n_sys, L.nlist, L.nn, L.nlist_cap, L.halo, L.halo_n, L.halo_cap,
                        rare_lds_entries, L.prow, L.xbuild, L.partials, L.status, L.rare_list,

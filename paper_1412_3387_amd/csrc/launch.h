@@ -16,6 +16,9 @@ enum StepMode : int32_t {
     MODE_LAST = 3    // F(t) from v(t-1/2); v(t); writes F
 };
 
+// Launches of the force pass (the values of the public HOOMD_FORCE_*).
+constexpr int kForceAuto = 0, kForceSplit = 1, kForceOne = 2;
+
 struct LaunchCtx {
     hipStream_t stream;
     int n_sys;
@@ -52,6 +55,8 @@ struct LaunchCtx {
     int32_t *slow_n;               // their number (cleared by the binning launch)
     int32_t *rare_list;            // tiles the force pass handles in its second launch
     int32_t *rare_n;               // their number (cleared by the binning launch)
+    int force_launch;              // kForceAuto / kForceSplit / kForceOne
+    int busy_tiles;                // tiles holding local rows (the others have nothing to do)
     int32_t *flag;                 // rebuild flag read by the rebuild kernels (some system needs one)
     int32_t *sflag;                // per-system rebuild flags of the same slot (n_sys entries)
     int32_t *build_count;

@@ -59,6 +59,9 @@ int cell_bins(double L, double rl)
     return (int)std::max<int64_t>(b, 1);
 }
 
+static_assert(kForceAuto == HOOMD_FORCE_AUTO && kForceSplit == HOOMD_FORCE_SPLIT && kForceOne == HOOMD_FORCE_ONE,
+              "force launch modes");
+
 bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
 {
     if (!p || !boxes || n_sys < 1) return false;
@@ -87,6 +90,9 @@ bool valid(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
         if (q.tune_period < 0 || q.tune_period != p[0].tune_period) return false;
         if (q.tpp_force != p[0].tpp_force || q.block_force != p[0].block_force) return false;
         if (q.integrator != HOOMD_NVE && q.integrator != HOOMD_NVT) return false;
+        if (q.force_launch < HOOMD_FORCE_AUTO || q.force_launch > HOOMD_FORCE_ONE ||
+            q.force_launch != p[0].force_launch)
+            return false;
         if (q.integrator == HOOMD_NVT) {
             if (!(q.nvt_T0 > 0) || !std::isfinite(q.nvt_T0) || !(q.nvt_tau > 0) || !std::isfinite(q.nvt_tau))
                 return false;
@@ -375,6 +381,15 @@ namespace {
 
 template <typename T> T *ws_ptr(hoomd_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
 
+// Tiles that hold local rows, over all systems (the force pass's choice of
+// one launch or two depends on it).
+void count_busy_tiles(hoomd_ctx *c)
+{
+    int64_t t = 0;
+    for (const SysDev &S : c->lay.sys) t += (S.n_local + kTile - 1) / kTile;
+    c->L.busy_tiles = (int)t;
+}
+
 void default_tuning(hoomd_ctx *c)
 {
     // neighbours per particle and particles per CU decide the lane count;
@@ -616,6 +631,8 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.thermostat = ws_ptr<double>(c, lay.thermostat);
     L.nvt = false;
     for (int s = 0; s < n_sys; ++s) L.nvt = L.nvt || params[s].integrator == HOOMD_NVT;
+    L.force_launch = params[0].force_launch;
+    count_busy_tiles(c);
     c->sortb = make_sort_buffers(c->ws + lay.sort_ws, lay.rows);
     c->ghostb = make_ghost_buffers(c->ws + lay.ghost_ws, lay.rows, n_sys);
     default_tuning(c);
@@ -1090,6 +1107,7 @@ int migrate_particles(hoomd_ctx *c, int32_t sys, const hoomd_subdomain *sd, void
     S.n_total = cnt[1];
     c->box[sys].n_local = cnt[1];
     launch_set_counts(c->L, sys, S.n_local, S.n_total);
+    count_busy_tiles(c);
     c->built = false;
     c->retune = c->tune_period > 0;
     *n_sent = cnt[0];
@@ -1130,6 +1148,7 @@ int receive_particles(hoomd_ctx *c, int32_t sys, const void *recv, int64_t n_rec
     S.n_total = S.n_local;
     c->box[sys].n_local = S.n_local;
     launch_set_counts(c->L, sys, S.n_local, S.n_total);
+    count_busy_tiles(c);
     c->built = false;
     c->retune = c->tune_period > 0;
     return hipGetLastError() == hipSuccess ? HOOMD_OK : HOOMD_E_DEVICE;

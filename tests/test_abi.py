@@ -168,6 +168,26 @@ def test_params_struct_matches_header():
     assert names == [f[0] for f in B.Params._fields_]
 
 
+def test_force_launch_field_is_validated(hlib):
+    """force_launch takes HOOMD_FORCE_AUTO, _SPLIT or _ONE, equal in all
+    systems."""
+    from paper_1412_3387_amd import binding as B
+    boxes = (B.Box * 2)()
+    for b in boxes:
+        for a in range(3):
+            b.L[a] = 16.796
+            b.periodic[a] = 1
+        b.n_local = b.n_cap = 4000
+
+    def ws(m0, m1):
+        ps = (B.Params * 2)(B.ModelParams(force_launch=m0).to_c(0.8442), B.ModelParams(force_launch=m1).to_c(0.8442))
+        return hlib.hoomd_workspace_bytes(ps, 2, boxes)
+
+    for m in (B.FORCE_AUTO, B.FORCE_SPLIT, B.FORCE_ONE):
+        assert ws(m, m) > 0
+    assert ws(-1, -1) == 0 and ws(3, 3) == 0 and ws(B.FORCE_SPLIT, B.FORCE_ONE) == 0
+
+
 def test_integrator_fields_are_validated(hlib):
     """NVT needs a positive finite set temperature and coupling time and a
     group id >= 0; systems of one thermostat group must share dt, T0 and

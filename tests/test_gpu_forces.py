@@ -171,3 +171,49 @@ def test_lj_forces_halo_beyond_rare_stage(orc, B, prec):
     fr = np.sqrt(np.mean(np.sum(F * F, axis=1)))
     err = np.max(np.sqrt(np.sum((f[which, :3] - F) ** 2, axis=1))) / fr
     assert err <= TOL[prec]
+
+
+def _launch_cases(B):
+    """Inputs that reach every branch of the force pass when it is split: a
+    sorted liquid (all tiles in the main launch), shuffled rows (halos beyond
+    the main launch's stage), the 4,000-particle box (per-pair images), an
+    unsorted DPD fluid, and a bonded melt."""
+    rng = np.random.default_rng(12)
+    big = inputs.lj_fluid(8000, 11, 12)
+    perm = rng.permutation(big.n)
+    shuffled = inputs.System(pos=big.pos[perm], vel=big.vel[perm], L=big.L, tag=perm.astype(np.int32))
+    melt = inputs.polymer_melt(20, seed_vel=71)
+    melt.pos = inputs.wrap(melt.pos + rng.uniform(-0.08, 0.08, melt.pos.shape), melt.L)
+    return [
+        ("sorted liquid", big, B.ModelParams(precision=B.MIXED, sort_period=100)),
+        ("shuffled rows", shuffled, B.ModelParams(precision=B.FP64, sort_period=0)),
+        ("4,000 box", inputs.lj_small(), B.ModelParams(precision=B.MIXED, sort_period=50)),
+        ("DPD", inputs.dpd_fluid(3000, 72, 73),
+         B.ModelParams(precision=B.MIXED, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=5)),
+        ("melt", melt, B.ModelParams(precision=B.FP64, pair=B.PAIR_WCA, bond_cap=2, sort_period=50)),
+    ]
+
+
+@pytest.mark.parametrize("w", [1, 2, 4, 8, 16])
+def test_one_launch_equals_split_launches(B, w):
+    """The force pass as one launch over every tile and as the split pair of
+    launches (a main launch sized for occupancy, then the tiles it leaves)
+    give the same trajectories, forces and logged energies bit for bit, and
+    the split pair does leave tiles to its second launch in the cases built
+    for that."""
+    import dataclasses
+    for name, s, p in _launch_cases(B):
+        out = []
+        for mode in (B.FORCE_SPLIT, B.FORCE_ONE):
+            q = dataclasses.replace(p, tpp_force=w, force_launch=mode)
+            ctx = B.Context([q], [dict(pos=s.pos, vel=s.vel, L=s.L, bonds=s.bonds, tag=s.tag)])
+            print(f"[case] {name}, {w} lanes, mode {mode}", flush=True)
+            ctx.step(0, 20, log_every=5)
+            ctx.check()
+            out.append((ctx.host_state(), ctx.thermo_log(), ctx.rare_tiles()))
+        (a, la, ra), (b, lb, rb) = out
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v), name
+        assert np.array_equal(la, lb), name
+        if name in ("shuffled rows", "4,000 box"):
+            assert ra > 0, name
