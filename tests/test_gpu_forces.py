@@ -177,7 +177,7 @@ def _launch_cases(B):
     """Inputs that reach every branch of the force pass when it is split: a
     sorted liquid (all tiles in the main launch), shuffled rows (halos beyond
     the main launch's stage), the 4,000-particle box (per-pair images), an
-    unsorted DPD fluid, and a bonded melt."""
+    unsorted DPD fluid, a bonded melt, and a Nose-Hoover liquid."""
     rng = np.random.default_rng(12)
     big = inputs.lj_fluid(8000, 11, 12)
     perm = rng.permutation(big.n)
@@ -191,6 +191,8 @@ def _launch_cases(B):
         ("DPD", inputs.dpd_fluid(3000, 72, 73),
          B.ModelParams(precision=B.MIXED, pair=B.PAIR_DPD, r_cut=1.0, r_buff=0.4, dt=0.02, dpd_seed=5)),
         ("melt", melt, B.ModelParams(precision=B.FP64, pair=B.PAIR_WCA, bond_cap=2, sort_period=50)),
+        ("NVT liquid", inputs.lj_fluid(6000, 74, 75),
+         B.ModelParams(precision=B.MIXED, sort_period=100, integrator=B.NVT, nvt_T0=1.5, nvt_tau=0.5)),
     ]
 
 
@@ -210,10 +212,12 @@ def test_one_launch_equals_split_launches(B, w):
             print(f"[case] {name}, {w} lanes, mode {mode}", flush=True)
             ctx.step(0, 20, log_every=5)
             ctx.check()
-            out.append((ctx.host_state(), ctx.thermo_log(), ctx.rare_tiles()))
-        (a, la, ra), (b, lb, rb) = out
+            out.append((ctx.host_state(), ctx.thermo_log(), ctx.rare_tiles(), ctx.thermostat()))
+        (a, la, ra, ta), (b, lb, rb, tb) = out
         for u, v in zip(a, b):
             assert np.array_equal(u, v), name
-        assert np.array_equal(la, lb), name
+        assert np.array_equal(la, lb) and np.array_equal(ta, tb), name
+        if name == "NVT liquid":
+            assert abs(ta[0, 0]) > 0.01  # the thermostat acted
         if name in ("shuffled rows", "4,000 box"):
             assert ra > 0, name
