@@ -533,7 +533,23 @@ __global__ __launch_bounds__(1024) void k_thermo_reduce(const SysDev *__restrict
     const int64_t w0 = (int64_t)tprefix[s] * W;
     const int64_t w1 = (int64_t)tprefix[s + 1] * W;
     double k = 0, e = 0, v = 0;
-    for (int64_t q = w0 + threadIdx.x; q < w1; q += blockDim.x) {
+    const int64_t st = blockDim.x;
+    int64_t q = w0 + threadIdx.x;
+    // four partials in flight, added in the same order as one at a time
+    for (; q + 3 * st < w1; q += 4 * st) {
+        double a[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[u][c] = partials[3 * (q + u * st) + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            k += a[u][0];
+            e += a[u][1];
+            v += a[u][2];
+        }
+    }
+    for (; q < w1; q += st) {
         k += partials[3 * q + 0];
         e += partials[3 * q + 1];
         v += partials[3 * q + 2];
@@ -734,7 +750,17 @@ __global__ __launch_bounds__(256) void k_nvt_update(const SysDev *__restrict__ s
         if (sys[q].nvt_slot != s) continue;
         n += sys[q].n_local;
         const int64_t w0 = (int64_t)tprefix[q] * w, w1 = (int64_t)tprefix[q + 1] * w;
-        for (int64_t p = w0 + threadIdx.x; p < w1; p += blockDim.x) k += khalf[p];
+        const int64_t st = blockDim.x;
+        int64_t p = w0 + threadIdx.x;
+        // eight loads in flight, added in the same order as one at a time
+        for (; p + 7 * st < w1; p += 8 * st) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = khalf[p + u * st];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) k += a[u];
+        }
+        for (; p < w1; p += st) k += khalf[p];
     }
     red[threadIdx.x] = k;
     __syncthreads();
