@@ -16,6 +16,10 @@ enum StepMode : int32_t {
     MODE_LAST = 3    // F(t) from v(t-1/2); v(t); writes F
 };
 
+// The framed build's per-die tile counters sit this many words apart: one
+// cache line each, so that the dies' atomics do not queue on one line.
+constexpr int kTileCtrStride = 64;
+
 // Launches of the force pass (the values of the public HOOMD_FORCE_*).
 constexpr int kForceAuto = 0, kForceSplit = 1, kForceOne = 2;
 
@@ -55,6 +59,8 @@ struct LaunchCtx {
     int32_t *slow_n;               // their number (cleared by the binning launch)
     int32_t *rare_list;            // tiles the force pass handles in its second launch
     int32_t *rare_n;               // their number (cleared by the binning launch)
+    int32_t *tile_ctr;             // kDies counters of tiles taken by the framed build's workgroups,
+                                   // kTileCtrStride words apart (cleared by the binning launch)
     int force_launch;              // kForceAuto / kForceSplit / kForceOne
     int busy_tiles;                // tiles holding local rows (the others have nothing to do)
     int32_t *flag;                 // rebuild flag read by the rebuild kernels (some system needs one)

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
                                              const int32_t *__restrict__ flag,
                                              const int32_t *__restrict__ sflag, Status *st,
                                              uint32_t *step_counter, int32_t *slow_n, int32_t *rare_n,
-                                             int32_t *since, int since_inc)
+                                             int32_t *tile_ctr, int32_t *since, int since_inc)
 {
     // the binning launch follows every fused step launch: it also advances
     // the device step counter read by graph-replayed steps, and each system's
@@ -73,6 +73,8 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
         *slow_n = 0;
         *rare_n = 0;
     }
+    // the framed build's per-die tile counters
+    if (blockIdx.x == 0 && threadIdx.x < kDies) tile_ctr[threadIdx.x * kTileCtrStride] = 0;
     const int lane = lane_id();
     const uint64_t lt = lanemask_lt();
     const int waves = (int)(gridDim.x * blockDim.x) >> 6;
@@ -763,6 +765,7 @@ struct FastShared {
     double xref[3];                      // first row's position: the frame reference
     int32_t info[5];                     // distinct cells, per-pair image flag, longest row, slots,
                                          // FP32 decision band (float bits)
+    int32_t grab[2];                     // tile indices taken from the die's counter
 };
 
 // Per-tile plan of the framed build, written by k_cells_and_plan and read by
@@ -1147,6 +1150,18 @@ __global__ void k_zero_counts(int32_t *__restrict__ cell_count, int64_t n_cells,
         cell_count[c] = 0;
 }
 
+// One tile index from a die's counter, by one lane.  The pointer gets a zero
+// from a vector register that the compiler cannot see through: taken as
+// divergent, the atomic is issued plainly and its result waited for where it
+// is used (the pass that merges the atomics of a wave into one would wait
+// for it at once).
+__device__ __forceinline__ int take_tile(int32_t *ctr)
+{
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    return atomicAdd(ctr + zero, 1);
+}
+
 // A plan header read through the vector memory path: the index gets a zero
 // from a vector register that the compiler cannot see through, so the read is
 // not made a scalar one (a pending scalar read would be waited for at the
@@ -1168,7 +1183,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const float4 *__restrict__ cell_xf, int cell_cap,
     uint16_t *__restrict__ nlist, int32_t *__restrict__ nn, int cap, int rstride,
     int32_t *__restrict__ halo, int32_t *__restrict__ halo_n, int halo_cap, PlanPtrs plan,
-    int halo_lds, int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n,
+    int halo_lds, int32_t *__restrict__ rare_list, int32_t *__restrict__ rare_n, int32_t *__restrict__ tile_ctr,
     int32_t *__restrict__ cell_count, int64_t n_cells,
     const int32_t *__restrict__ flag, const int32_t *__restrict__ sflag, int32_t *build_count, Status *st)
 {
@@ -1187,20 +1202,53 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     static_assert(LPR == 32 || LPR == 64, "a row per wave or per half wave");
     if (blockIdx.x == 0 && tid == 0) atomicAdd(build_count, 1);
 
+    // Each die's workgroups walk one contiguous run of tiles.  With one
+    // system every tile of the run is built, and the tiles are handed out one
+    // at a time from the die's counter (cleared by the binning launch), two
+    // ahead: the loader wave (which makes no global writes, so its wait for
+    // the count waits for no write) takes the one after next once it has
+    // read the tile's plan.  Workgroups that meet costly tiles take fewer, so
+    // the launch ends with its run.  A batch rebuilds only some systems, and
+    // a count for each tile it skips would cost more than it balances: there
+    // the workgroups of a die take every step-th tile of the run.
+    const bool dyn = n_sys == 1;
+    const int D = (int)gridDim.x < kDies ? (int)gridDim.x : kDies;
+    const int die = (int)blockIdx.x % D;
     int64_t tfirst, tend;
     int tstep;
     die_range(blockIdx.x, gridDim.x, tiles, tfirst, tend, tstep);
+    int32_t *ctr = tile_ctr + die * kTileCtrStride;
+    int grabbed = 0;
+    int64_t t_next = tfirst;
+    if (dyn) {
+        if (tid == kWave) {
+            sh.grab[0] = take_tile(ctr);
+            grabbed = take_tile(ctr);
+        }
+        lds_barrier();
+        t_next = (int64_t)tiles * die / D + sh.grab[0];
+    }
     // each tile's plan header is read one tile ahead, by every thread, with
     // no branch, so that the read stays in flight until its use
-    int4 hd_next = next_header(plan.hdr, tfirst < tend ? tfirst : 0);
-    for (int tile = (int)tfirst; tile < tend; tile += tstep) {
+    int4 hd_next = next_header(plan.hdr, t_next < tend ? (int)t_next : 0);
+    bool built = false;  // a tile was built since the last barrier (its LDS may still be read)
+    for (int it = 1;; ++it) {
+        if (dyn && tid == kWave) sh.grab[it & 1] = grabbed;
+        if (dyn || built) lds_barrier();  // LDS of the previous tile no longer read; the next index published
+        built = false;
+        const int64_t t_cur = t_next;
+        t_next = dyn ? (int64_t)tiles * die / D + sh.grab[it & 1] : t_cur + tstep;
+        if (t_cur >= tend) break;
+        const int tile = (int)t_cur;
+        const int4 hd_tile = hd_next;
+        hd_next = next_header(plan.hdr, t_next < tend ? (int)t_next : tile);
         const int s = find_sys(tprefix, n_sys, tile);
         if (!sflag[s]) {
-            // a system that keeps its list (the binning launch has put its
-            // tile back on the second force launch's list if needed)
-            hd_next = next_header(plan.hdr, tile + tstep < tend ? tile + tstep : tile);
+            // a system that keeps its list
+            if (dyn && tid == kWave) grabbed = take_tile(ctr);
             continue;
         }
+        built = true;
         const SysDev &S = sys[s];
         const double Ls[3] = {S.L[0], S.L[1], S.L[2]};
         const double iL[3] = {S.invL[0], S.invL[1], S.invL[2]};
@@ -1211,7 +1259,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const double rl2 = S.rl2;
         const int r0 = (tile - S.tile0) * kTile;
 
-        lds_barrier();  // LDS of the previous tile no longer read
         // ---- 1. the tile's plan ------------------------------------------------
         // Wave 1 does this tile's global reads and no global writes: a wave's
         // wait for a read also waits for all of its earlier writes, and the
@@ -1219,7 +1266,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const bool loader = wv == 1;
         const int tr = tid - kWave;  // lane of the loader wave
         if (loader) {
-            const int4 hd = hd_next;
+            const int4 hd = hd_tile;
             if (tr == 0) {
                 sh.info[0] = hd.x;
                 sh.info[1] = hd.z;
@@ -1275,7 +1322,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             sh.rown[tid] = r0 + tid < n_local ? 0 : -1;
         }
         lds_barrier();
-        hd_next = next_header(plan.hdr, tile + tstep < tend ? tile + tstep : tile);
+        if (dyn && tid == kWave) grabbed = take_tile(ctr);  // the tile after next
         const int nu = uni(sh.info[0]);
         const int nslot = uni(sh.info[3]);
         if (nu <= 0 || nu > kUMax || nslot > kFastSlotMax) continue;  // built by the general kernel
@@ -1748,7 +1795,7 @@ void launch_bin(const LaunchCtx &L, const double4 *pos)
     const int blocks = capped(((int64_t)L.tiles_all * kWave + 255) / 256);
     hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.tprefix_all, L.n_sys,
                        L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.sflag, L.status,
-                       L.step_counter, L.slow_n, L.rare_n, L.since, L.since_inc);
+                       L.step_counter, L.slow_n, L.rare_n, L.tile_ctr, L.since, L.since_inc);
 }
 
 void launch_cell_sort(const LaunchCtx &L, const double4 *pos)
@@ -1828,7 +1875,7 @@ static void fast_inst(const LaunchCtx &L, const double4 *pos, const int32_t *tag
     hipLaunchKernelGGL((k_build_fast<EXCL, NT, LPR>), dim3(blocks), dim3(NT), dyn, L.stream, L.sys, L.tprefix_local,
                        L.n_sys, L.tiles_local, pos, tag, L.ptag, L.cell_size, L.cell_idx, L.cell_xf, L.cell_cap,
                        L.nlist, L.nn, L.nlist_cap, rs, L.halo, L.halo_n, L.halo_cap, plan, L.halo_lds, L.rare_list,
-                       L.rare_n, L.cell_count, L.n_cells, L.flag, L.sflag, L.build_count, L.status);
+                       L.rare_n, L.tile_ctr, L.cell_count, L.n_cells, L.flag, L.sflag, L.build_count, L.status);
 }
 
 template <bool EXCL>

@@ -35,7 +35,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
     // byte offsets into the workspace
-    size_t sysdev, tpl, tpa, cpre, status, flags, sysflags, thermo, thermo_log, partials, khalf, thermostat;
+    size_t sysdev, tpl, tpa, cpre, status, flags, tile_ctr, sysflags, thermo, thermo_log, partials, khalf, thermostat;
     size_t pos_alt, vel_alt, xbuild, nlist, nn, cell_count, cell_size, cell_idx, cell_xf, halo, halo_n;
     size_t ptag, pdir, prow, btmp, hash, slow_list, rare_list, plan, sort_ws, ghost_ws, total;
     // sizes
@@ -294,6 +294,7 @@ Layout make_layout(const hoomd_params *p, int32_t n_sys, const hoomd_box *boxes)
     Lo.cpre = take(sizeof(int64_t) * (n_sys + 1));
     Lo.status = take(sizeof(Status));
     Lo.flags = take(sizeof(int32_t) * 8);
+    Lo.tile_ctr = take(sizeof(int32_t) * kTileCtrStride * kDies);
     Lo.sysflags = take(sizeof(int32_t) * 4 * (size_t)n_sys);
     Lo.thermo = take(sizeof(double) * 4 * n_sys);
     Lo.thermo_log = take(sizeof(double) * 5 * (size_t)n_sys * kLogRows);
@@ -623,6 +624,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     L.rare_list = ws_ptr<int32_t>(c, lay.rare_list);
     L.plan = ws_ptr<char>(c, lay.plan);
     L.rare_n = flag_ptr(c, 7);
+    L.tile_ctr = ws_ptr<int32_t>(c, lay.tile_ctr);
     L.status = ws_ptr<Status>(c, lay.status);
     L.partials = ws_ptr<double>(c, lay.partials);
     L.thermo = ws_ptr<double>(c, lay.thermo);
@@ -650,6 +652,7 @@ int hoomd_init(hoomd_ctx **out, const hoomd_params *params, int32_t n_sys, const
     if (e == hipSuccess) e = hipMemcpy(c->ws + lay.cpre, lay.cpre_host.data(), sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.status, 0, sizeof(Status));
     if (e == hipSuccess) e = hipMemset(c->ws + lay.flags, 0, sizeof(int32_t) * 8);
+    if (e == hipSuccess) e = hipMemset(c->ws + lay.tile_ctr, 0, sizeof(int32_t) * kTileCtrStride * kDies);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.sysflags, 0, sizeof(int32_t) * 4 * (size_t)n_sys);
     if (e == hipSuccess) e = hipMemset(c->ws + lay.cell_count, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(lay.n_cells, 1));
     if (e == hipSuccess) e = hipMemset(c->ws + lay.thermo, 0, sizeof(double) * 4 * n_sys);
@@ -1415,6 +1418,8 @@ int tune_now(hoomd_ctx *c, bool use_cache)
             const float t = median5(c,
                                     [&] {
                                         launch_set_flag(c->L, flag_ptr(c, 7), 0);
+                                        (void)hipMemsetAsync(c->L.tile_ctr, 0, sizeof(int32_t) * kTileCtrStride * kDies,
+                                                             c->stream);
                                         launch_set_flags(c->L, flag, sflag, 1);
                                         c->L.flag = flag;
                                         c->L.sflag = sflag;
