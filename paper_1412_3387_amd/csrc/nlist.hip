@@ -1204,19 +1204,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
     // Each die's workgroups walk one contiguous run of tiles.  With one
     // system every tile of the run is built, and the tiles are handed out one
-    // at a time from the die's counter (cleared by the binning launch), two
-    // ahead: the loader wave (which makes no global writes, so its wait for
-    // the count waits for no write) takes the one after next once it has
-    // read the tile's plan.  Workgroups that meet costly tiles take fewer, so
-    // the launch ends with its run.  A batch rebuilds only some systems, and
-    // a count for each tile it skips would cost more than it balances: there
-    // the workgroups of a die take every step-th tile of the run.
+    // at a time from the die's counter (cleared by the binning launch): a
+    // workgroup that meets costly tiles takes fewer, so the launch ends with
+    // its run.  The loader wave (which makes no global writes, so its wait
+    // for the count waits for no write) takes the tile after next as a tile
+    // starts.  A batch rebuilds only some systems, and a count for every tile
+    // it skips would cost more than it balances: there the workgroups of a
+    // die take every step-th tile of the run, and skip without a barrier.
     const bool dyn = n_sys == 1;
     const int D = (int)gridDim.x < kDies ? (int)gridDim.x : kDies;
     const int die = (int)blockIdx.x % D;
     int64_t tfirst, tend;
     int tstep;
     die_range(blockIdx.x, gridDim.x, tiles, tfirst, tend, tstep);
+    const int64_t dfirst = (int64_t)tiles * die / D;
     int32_t *ctr = tile_ctr + die * kTileCtrStride;
     int grabbed = 0;
     int64_t t_next = tfirst;
@@ -1226,28 +1227,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             grabbed = take_tile(ctr);
         }
         lds_barrier();
-        t_next = (int64_t)tiles * die / D + sh.grab[0];
+        t_next = dfirst + sh.grab[0];
     }
+    int par = 0;
     // each tile's plan header is read one tile ahead, by every thread, with
     // no branch, so that the read stays in flight until its use
     int4 hd_next = next_header(plan.hdr, t_next < tend ? (int)t_next : 0);
     bool built = false;  // a tile was built since the last barrier (its LDS may still be read)
-    for (int it = 1;; ++it) {
-        if (dyn && tid == kWave) sh.grab[it & 1] = grabbed;
-        if (dyn || built) lds_barrier();  // LDS of the previous tile no longer read; the next index published
+    for (;;) {
+        if (dyn) {
+            // the next tile's index, taken during the last tile
+            par ^= 1;
+            if (tid == kWave) sh.grab[par] = grabbed;
+        }
+        if (dyn || built) lds_barrier();  // LDS of the previous tile no longer read; the index published
         built = false;
         const int64_t t_cur = t_next;
-        t_next = dyn ? (int64_t)tiles * die / D + sh.grab[it & 1] : t_cur + tstep;
+        t_next = dyn ? dfirst + sh.grab[par] : t_cur + tstep;
         if (t_cur >= tend) break;
+        if (dyn && tid == kWave) grabbed = take_tile(ctr);  // the tile after next
         const int tile = (int)t_cur;
         const int4 hd_tile = hd_next;
         hd_next = next_header(plan.hdr, t_next < tend ? (int)t_next : tile);
         const int s = find_sys(tprefix, n_sys, tile);
-        if (!sflag[s]) {
-            // a system that keeps its list
-            if (dyn && tid == kWave) grabbed = take_tile(ctr);
-            continue;
-        }
+        if (!sflag[s]) continue;  // a system that keeps its list
         built = true;
         const SysDev &S = sys[s];
         const double Ls[3] = {S.L[0], S.L[1], S.L[2]};
@@ -1322,7 +1325,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             sh.rown[tid] = r0 + tid < n_local ? 0 : -1;
         }
         lds_barrier();
-        if (dyn && tid == kWave) grabbed = take_tile(ctr);  // the tile after next
         const int nu = uni(sh.info[0]);
         const int nslot = uni(sh.info[3]);
         if (nu <= 0 || nu > kUMax || nslot > kFastSlotMax) continue;  // built by the general kernel
