@@ -32,7 +32,7 @@ def _rec_bytes(fields):
     return 8 * (3 * bool(fields & 1) + 3 * bool(fields & 2) + bool(fields & 4))
 
 
-def _loopback(B, sd, precision=1, update_shift=None, fields=None, update_dv=None):
+def _loopback(B, sd, precision=1, update_shift=None, fields=None, update_dv=None, tpp_force=0):
     import torch
     full = sd.full
     L = full.L
@@ -46,7 +46,7 @@ def _loopback(B, sd, precision=1, update_shift=None, fields=None, update_dv=None
         systems.append(dict(pos=full.pos[loc], vel=full.vel[loc], tag=loc.astype(np.int32),
                             L=np.full(3, frame), lo=lo, periodic=(0, 0, 0),
                             n_cap=int(1.2 * rho * frame ** 3) + 64))
-        params.append(B.ModelParams(precision=precision, nlist_cap=160))
+        params.append(B.ModelParams(precision=precision, nlist_cap=160, tpp_force=tpp_force))
     ctx = B.Context(params, systems)
     dev = ctx.device
     if fields is None:
@@ -148,6 +148,54 @@ def test_ghost_receive_set_and_local_forces(orc, B, cells, prec):
     fr = np.sqrt(np.mean(np.sum(F * F, axis=1)))
     err = np.max(np.sqrt(np.sum((f[pick] - F) ** 2, axis=1))) / fr
     assert err <= (1e-12 if prec == 0 else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_subdomain_alone_as_benchmarked(orc, B, prec):
+    """Subdomain 0 of the 864,000-particle box in a context of its own, as
+    the benchmark runs it (one system: the framed build hands tiles out one
+    at a time, and its 500 tiles of local rows take the force pass in one
+    launch): the ghosts received from the 26 neighbours unpacked, local
+    forces against the full-box forces, and the same forces bit for bit as
+    subdomain 0 of the 27-subdomain context with the same lanes per
+    particle (a batch: fixed tile split, split force launch)."""
+    import torch
+    sd = inputs.lj_subdomain_box(grid=3, cells=60)
+    r = _loopback(B, sd, precision=prec, tpp_force=4)
+    big = r["ctx"]
+    full = sd.full
+    fields = B.FIELD_POS | B.FIELD_TAG
+    rec = _rec_bytes(fields)
+    pieces = []
+    for s in range(1, 27):
+        d = _dir_to(s, 0)
+        a, n = int(r["offsets"][s][d]), int(r["counts"][s][d])
+        pieces.append(r["sends"][s][a * rec:(a + n) * rec])
+    recv = torch.cat(pieces).contiguous()
+    frame = sd.side + 2 * (W + MARGIN)
+    rho = full.n / float(np.prod(full.L))
+    loc = sd.local(0)
+    p = B.ModelParams(precision=prec, nlist_cap=160, tpp_force=4)
+    one = B.Context([p], [dict(pos=full.pos[loc], vel=full.vel[loc], tag=loc.astype(np.int32),
+                               L=np.full(3, frame), lo=sd.lo(0) - W - MARGIN, periodic=(0, 0, 0),
+                               n_cap=int(1.2 * rho * frame ** 3) + 64)])
+    print(f"[case] subdomain 0 alone, precision {prec}, {r['n_recv']} ghosts", flush=True)
+    one.unpack_ghosts(0, recv, r["n_recv"], fields, B.GHOST_SELECT, full.L)
+    one.compute_forces(0, 1)
+    one.check()
+    n0 = one.n_local[0]
+    f = one.force[:n0, :3].cpu().numpy()
+    rng = np.random.default_rng(14)
+    pick = np.sort(rng.choice(n0, 256, replace=False))
+    F, u, w, nc = orc.pair_forces("lj", full.pos, full.L, LJ, which=loc[pick])
+    fr = np.sqrt(np.mean(np.sum(F * F, axis=1)))
+    err = np.max(np.sqrt(np.sum((f[pick] - F) ** 2, axis=1))) / fr
+    assert err <= (1e-12 if prec == 0 else 1e-5), err
+    # the 27-subdomain context with the same lanes per particle
+    big.compute_forces(0, 1)
+    big.check()
+    o = big.offsets[0]
+    assert np.array_equal(big.force[o:o + n0].cpu().numpy(), one.force[:n0].cpu().numpy())
 
 
 @pytest.mark.parametrize("cells", [12, 60])
