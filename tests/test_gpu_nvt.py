@@ -188,3 +188,39 @@ def test_nvt_extended_energy_and_temperature_mixed(B):
     assert np.max(np.abs(H - H[0])) <= 3e-4 * abs(H[0])
     assert np.max(np.abs(E - E[0])) > 50 * np.max(np.abs(H - H[0]))
     assert len(T) == 200 and abs(np.mean(T[100:]) - T0) <= 0.03 * T0
+
+
+
+@pytest.fixture(scope="module")
+def weak_ref(orc):
+    w = inputs.lj_weak_share()
+    xo, vo, Fo, th, ext, st = orc.run_nvt("lj", w.pos, w.vel, w.L, [1.0, 1.0, 3.0], 0.002, 6, T0=1.2, tau=0.5,
+                                         xi=0.3, eta=0.0)
+    assert st == 0
+    return w, xo, vo, ext
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nvt_weak_share_as_benchmarked(B, weak_ref, prec):
+    """The 32,000-particle share of the weak-scaling fluid (packing fraction
+    0.2, r_cut 3.0, r_buff 0.4, dt 0.002, Morton-sorted, T0 = 1.2, tau =
+    0.5) in the configuration the benchmark steps (one system: the framed
+    build hands tiles out one at a time, the force pass runs as one
+    launch), from xi = 0.3, 6 steps against the oracle's full NVT run: FP64
+    within 1e-10, mixed within 1e-5 of the velocity scale."""
+    w, xo, vo, ext = weak_ref
+    p = B.ModelParams(precision=prec, r_cut=3.0, r_buff=0.4, dt=0.002, sort_period=500, integrator=B.NVT,
+                      nvt_T0=1.2, nvt_tau=0.5)
+    ctx = B.Context([p], [dict(pos=w.pos, vel=w.vel, L=w.L)])
+    ctx.set_thermostat([[0.3, 0.0]])
+    print(f"[case] weak share NVT, precision {prec}", flush=True)
+    ctx.step(0, 6)
+    ctx.check()
+    x, v, f, tag = ctx.host_state()
+    x, v = by_tag(tag, x, v)
+    vs = np.sqrt(np.mean(vo ** 2))
+    assert np.max(np.abs(min_image_diff(x, xo, w.L))) <= (1e-10 if prec == 0 else 1e-6)
+    assert np.max(np.abs(v - vo)) <= (1e-10 if prec == 0 else 1e-5 * vs)
+    xe = ctx.thermostat()[0]
+    assert np.max(np.abs(xe - ext[-1])) <= (1e-10 if prec == 0 else 1e-7)
+    assert abs(ext[-1, 0] - 0.3) > 5e-5 and ext[-1, 1] > 1e-3  # the thermostat acted
