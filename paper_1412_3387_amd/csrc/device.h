@@ -235,4 +235,55 @@ __device__ __forceinline__ uint32_t dpd_bits(uint32_t ta, uint32_t tb, uint32_t 
     return philox_first_word(a, b, 0u, 0u, seed, step) >> 8;
 }
 
+// Nose-Hoover update of the thermostat group whose first system is s, by a
+// workgroup of nt threads (this one tid; every thread calls it): the group's
+// half-step kinetic-energy partials (w per tile, tiles in order) summed as
+// kNvtSums strided partial sums and a tree over them, the same order for
+// any workgroup size, then
+//   xi' = xi + dt/tau^2 (T/T0 - 1),  eta' = eta + dt/2 (xi + xi'),
+// with T = 2 KE / (3 N - 3) over the group's N local particles.  red holds
+// kNvtSums doubles in LDS.
+constexpr int kNvtSums = 256;
+__device__ inline void nvt_group_update(const SysDev *__restrict__ sys, const int32_t *__restrict__ tprefix,
+                                        int n_sys, int w, const double *__restrict__ khalf,
+                                        double *__restrict__ thermostat, int s, double *red, int nt, int tid)
+{
+    for (int v = tid; v < kNvtSums; v += nt) {
+        double k = 0.0;
+        for (int q = s; q < n_sys; ++q) {
+            if (sys[q].nvt_slot != s) continue;
+            const int64_t w0 = (int64_t)tprefix[q] * w, w1 = (int64_t)tprefix[q + 1] * w;
+            int64_t p = w0 + v;
+            // eight loads in flight, added in the same order as one at a time
+            for (; p + 7 * kNvtSums < w1; p += 8 * kNvtSums) {
+                double a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = khalf[p + u * kNvtSums];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) k += a[u];
+            }
+            for (; p < w1; p += kNvtSums) k += khalf[p];
+        }
+        red[v] = k;
+    }
+    __syncthreads();
+    for (int m = kNvtSums / 2; m > 0; m >>= 1) {
+        for (int v = tid; v < m; v += nt) red[v] += red[v + m];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int64_t n = 0;
+        for (int q = s; q < n_sys; ++q)
+            if (sys[q].nvt_slot == s) n += sys[q].n_local;
+        const SysDev &S = sys[s];
+        const double g = 3.0 * (double)n - 3.0;
+        const double T = g > 0 ? 2.0 * red[0] / g : S.nvt_T0;
+        const double xi = thermostat[2 * s];
+        const double xn = xi + S.nvt_c * (T / S.nvt_T0 - 1.0);
+        thermostat[2 * s + 1] = thermostat[2 * s + 1] + S.hdt * (xi + xn);
+        thermostat[2 * s] = xn;
+    }
+    __syncthreads();  // red free again
+}
+
 }  // namespace md

@@ -730,52 +730,17 @@ __global__ void k_half_step(const SysDev *__restrict__ sys, const int32_t *__res
     drift_and_check(S, s, i, v, pos, xbuild, flag, sflag);
 }
 
-// Nose-Hoover update, one workgroup per system; the first system of each
-// group sums the half-step kinetic-energy partials of the group's systems
-// (w per tile, tiles in order, a fixed order), then
-//   xi' = xi + dt/tau^2 (T/T0 - 1),  eta' = eta + dt/2 (xi + xi'),
-// with T = 2 KE / (3 N - 3) over the group's N local particles.
-__global__ __launch_bounds__(256) void k_nvt_update(const SysDev *__restrict__ sys,
-                                                    const int32_t *__restrict__ tprefix, int n_sys, int w,
-                                                    const double *__restrict__ khalf,
-                                                    double *__restrict__ thermostat)
+// Nose-Hoover update, one workgroup per system (the first system of each
+// group does its group).
+__global__ __launch_bounds__(kNvtSums) void k_nvt_update(const SysDev *__restrict__ sys,
+                                                         const int32_t *__restrict__ tprefix, int n_sys, int w,
+                                                         const double *__restrict__ khalf,
+                                                         double *__restrict__ thermostat)
 {
-    __shared__ double red[256];
+    __shared__ double red[kNvtSums];
     const int s = blockIdx.x;
-    const SysDev &S = sys[s];
-    if (S.nvt_slot != s) return;
-    double k = 0.0;
-    int64_t n = 0;
-    for (int q = s; q < n_sys; ++q) {
-        if (sys[q].nvt_slot != s) continue;
-        n += sys[q].n_local;
-        const int64_t w0 = (int64_t)tprefix[q] * w, w1 = (int64_t)tprefix[q + 1] * w;
-        const int64_t st = blockDim.x;
-        int64_t p = w0 + threadIdx.x;
-        // eight loads in flight, added in the same order as one at a time
-        for (; p + 7 * st < w1; p += 8 * st) {
-            double a[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] = khalf[p + u * st];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) k += a[u];
-        }
-        for (; p < w1; p += st) k += khalf[p];
-    }
-    red[threadIdx.x] = k;
-    __syncthreads();
-    for (int m = blockDim.x / 2; m > 0; m >>= 1) {
-        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double g = 3.0 * (double)n - 3.0;
-        const double T = g > 0 ? 2.0 * red[0] / g : S.nvt_T0;
-        const double xi = thermostat[2 * s];
-        const double xn = xi + S.nvt_c * (T / S.nvt_T0 - 1.0);
-        thermostat[2 * s + 1] = thermostat[2 * s + 1] + S.hdt * (xi + xn);
-        thermostat[2 * s] = xn;
-    }
+    if (sys[s].nvt_slot != s) return;
+    nvt_group_update(sys, tprefix, n_sys, w, khalf, thermostat, s, red, blockDim.x, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -945,8 +910,8 @@ void launch_half_step(const LaunchCtx &L, double4 *pos, double4 *vel, const void
 void launch_nvt_update(const LaunchCtx &L, int w)
 {
     if (!L.nvt) return;
-    hipLaunchKernelGGL(k_nvt_update, dim3(L.n_sys), dim3(256), 0, L.stream, L.sys, L.tprefix_local, L.n_sys, w,
-                       L.khalf, L.thermostat);
+    hipLaunchKernelGGL(k_nvt_update, dim3(L.n_sys), dim3(kNvtSums), 0, L.stream, L.sys, L.tprefix_local, L.n_sys,
+                       w, L.khalf, L.thermostat);
 }
 
 

@@ -103,7 +103,9 @@ struct ForceLaunch {
     double *khalf;             // where the launch writes the half-step kinetic-energy partials
 };
 
-void launch_bin(const LaunchCtx &L, const double4 *pos);
+// nvt_w > 0: the launch also does the Nose-Hoover update of the force launch
+// just before it (launch_nvt_update(L, nvt_w) folded in).
+void launch_bin(const LaunchCtx &L, const double4 *pos, int nvt_w = 0);
 void launch_cell_sort(const LaunchCtx &L, const double4 *pos);
 void launch_nlist(const LaunchCtx &L, const double4 *pos, const int32_t *tag, int w, int block);
 void launch_force(const LaunchCtx &L, const ForceLaunch &F, int w, int block);

@@ -58,8 +58,20 @@ __global__ __launch_bounds__(256) void k_bin(const SysDev *__restrict__ sys,
                                              const int32_t *__restrict__ flag,
                                              const int32_t *__restrict__ sflag, Status *st,
                                              uint32_t *step_counter, int32_t *slow_n, int32_t *rare_n,
-                                             int32_t *tile_ctr, int32_t *since, int since_inc)
+                                             int32_t *tile_ctr, int32_t *since, int since_inc,
+                                             const int32_t *__restrict__ tprefix_local, int nvt_w,
+                                             const double *__restrict__ khalf, double *__restrict__ thermostat)
 {
+    // The Nose-Hoover update of the force launch just before (its half-step
+    // partials are complete at that launch's end), folded into this launch,
+    // which follows every step's force launch: a workgroup per thermostat
+    // group.  The next force launch reads the new state.
+    if (khalf) {
+        __shared__ double red[kNvtSums];
+        for (int q = blockIdx.x; q < n_sys; q += gridDim.x)
+            if (sys[q].nvt_slot == q)
+                nvt_group_update(sys, tprefix_local, n_sys, nvt_w, khalf, thermostat, q, red, blockDim.x, threadIdx.x);
+    }
     // the binning launch follows every fused step launch: it also advances
     // the device step counter read by graph-replayed steps, and each system's
     // count of steps since its last build read by the displacement check
@@ -1791,13 +1803,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 static int capped(int64_t blocks) { return (int)(blocks < kRebuildGrid ? (blocks > 0 ? blocks : 1) : kRebuildGrid); }
 
-void launch_bin(const LaunchCtx &L, const double4 *pos)
+void launch_bin(const LaunchCtx &L, const double4 *pos, int nvt_w)
 {
     if (L.tiles_all == 0) return;
     const int blocks = capped(((int64_t)L.tiles_all * kWave + 255) / 256);
     hipLaunchKernelGGL(k_bin, dim3(blocks), dim3(256), 0, L.stream, L.sys, L.tprefix_all, L.n_sys,
                        L.tiles_all, pos, L.cell_count, L.cell_idx, L.cell_cap, L.flag, L.sflag, L.status,
-                       L.step_counter, L.slow_n, L.rare_n, L.tile_ctr, L.since, L.since_inc);
+                       L.step_counter, L.slow_n, L.rare_n, L.tile_ctr, L.since, L.since_inc, L.tprefix_local, nvt_w,
+                       nvt_w > 0 && L.nvt ? L.khalf : nullptr, L.thermostat);
 }
 
 void launch_cell_sort(const LaunchCtx &L, const double4 *pos)

@@ -445,12 +445,14 @@ int32_t *sflag_ptr(hoomd_ctx *c, int k) { return ws_ptr<int32_t>(c, c->lay.sysfl
 // kernel returns at once when *flag is clear.  The binning launch also keeps
 // the count of steps since the last build: reset by a build, else advanced by
 // since_inc (1 after a step, 0 after an explicit build request).
-void queue_rebuild(hoomd_ctx *c, const double4 *pos, const int32_t *tag, int slot, int since_inc)
+// nvt_w > 0: the binning launch also does the Nose-Hoover update of the
+// force launch before it (w lanes per particle).
+void queue_rebuild(hoomd_ctx *c, const double4 *pos, const int32_t *tag, int slot, int since_inc, int nvt_w = 0)
 {
     c->L.flag = flag_ptr(c, slot);
     c->L.sflag = sflag_ptr(c, slot);
     c->L.since_inc = since_inc;
-    launch_bin(c->L, pos);
+    launch_bin(c->L, pos, nvt_w);
     launch_cell_sort(c->L, pos);
     launch_nlist(c->L, pos, tag, c->tpp_nlist, c->block_nlist);
 }
@@ -489,8 +491,7 @@ void queue_mid_step(hoomd_ctx *c, int p, double4 *const *P, double4 *const *V, b
     F.sflag_clear = sflag_ptr(c, p ^ 1);
     if (c->L.nvt) F.khalf = c->L.khalf;
     launch_force(c->L, F, c->tpp_force, c->block_force);
-    launch_nvt_update(c->L, c->tpp_force);
-    queue_rebuild(c, P[p ^ 1], c->arr.tag, p, 1);
+    queue_rebuild(c, P[p ^ 1], c->arr.tag, p, 1, c->L.nvt ? c->tpp_force : 0);
 }
 
 // Pairs of middle steps in the long captured run: one graph launch per 16
@@ -850,7 +851,8 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
         const size_t e0 = mark(c);
         launch_force(c->L, F, c->tpp_force, c->block_force);
         if (c->profiling) c->ev_force.emplace_back(e0, mark(c));
-        if (F.khalf) launch_nvt_update(c->L, c->tpp_force);
+        // (a force launch with half-step partials is followed by a rebuild
+        // queue, whose binning launch does the thermostat update)
         if (F.log) {
             launch_thermo_reduce(c->L, c->tpp_force, log_row < kLogRows ? log_row : -1, (double)t);
             ++log_row;
@@ -867,7 +869,7 @@ int step(hoomd_ctx *c, uint64_t t0, int32_t n_steps, int32_t log_every)
             launch_set_flags(c->L, flag_ptr(c, p), sflag_ptr(c, p), 1);  // a sort moves every system's rows
         }
         const size_t r0 = mark(c);
-        queue_rebuild(c, P[p ^ 1], tag, p, 1);
+        queue_rebuild(c, P[p ^ 1], tag, p, 1, F.khalf ? c->tpp_force : 0);
         if (c->profiling) c->ev_rebuild.emplace_back(r0, mark(c));
         ++s;
     }
